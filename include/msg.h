@@ -1,0 +1,194 @@
+/*
+ * msg.h -- C-ABI of the MI355X batched Multiple Semi-Coarsened Multigrid
+ * (MSG) library: lognormal coefficient fields, batched full-MSG solves that
+ * return the solution on every semi-coarsened grid, and the multi-index
+ * differences of the per-grid quantities of interest.
+ *
+ * Paper: Robbe, Nuyens, Vandewalle, "Enhanced Multi-Index Monte Carlo by
+ * means of Multiple Semi-Coarsened Multigrid for Anisotropic Diffusion
+ * Problems" (arXiv 1907.12334).
+ *
+ * Problem (Section 1, eq. PDE): -div(k grad u) = h on the unit square,
+ * u = 0 on its boundary, k = exp(Z) with Z a Gaussian random field.
+ *
+ * Grids (Section 2, eq. hierarchy): a sample with finest index (P,Q) owns the
+ * rectangle of grids (p,q), 0 <= p <= P, 0 <= q <= Q; grid (p,q) has
+ * nx = c*2^p by ny = c*2^q cells (cell-centred finite volumes, mesh widths
+ * 1/nx and 1/ny), c being the coarsest number of cells per direction.
+ *
+ * Layout (the single convention shared by every array of this header):
+ *   - samples are packed one after another in batch order;
+ *   - inside a sample, grids are packed p-major then q-minor;
+ *   - inside a grid, values are row-major with x fastest:
+ *       cells   nx*ny        index j*nx + i,      cell centre ((i+1/2)/nx, (j+1/2)/ny)
+ *       x-faces (nx+1)*ny    index j*(nx+1) + i,  face at (i/nx, (j+1/2)/ny)
+ *       y-faces nx*(ny+1)    index j*nx + i,      face at ((i+1/2)/nx, j/ny)
+ *   - per-grid scalars (Q, Delta Q, cycle counts) are packed the same way,
+ *     (P+1)*(Q+1) per sample.
+ * msg_layout() returns every offset; it is the source of truth.
+ *
+ * Conventions: "d_" pointers are device pointers (HIP global memory on the
+ * handle's device), owned by the caller; the library never frees them and
+ * keeps no reference after a call returns.  Host arrays are read during the
+ * call only.  Every call reports argument and layout errors through its
+ * return value before touching the device; msg_last_error() then holds a
+ * message (thread-local, valid until the next call on that thread).  Calls
+ * are not re-entrant on one handle.
+ */
+#ifndef MSG_H
+#define MSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct msg_handle_s *msg_handle;
+typedef void *msg_stream;   /* a hipStream_t; NULL is the null stream */
+
+typedef enum {
+    MSG_OK = 0,
+    MSG_ERR_ARG = -1,          /* bad argument (NULL, size, option out of range) */
+    MSG_ERR_LAYOUT = -2,       /* batch shape outside the supported range */
+    MSG_ERR_WORKSPACE = -3,    /* workspace smaller than msg_workspace_size() */
+    MSG_ERR_HIP = -4,          /* a HIP runtime call failed */
+    MSG_ERR_UNSUPPORTED = -5   /* combination of options not implemented */
+} msg_status;
+
+/* per-sample outcome written to d_status */
+enum { MSG_SAMPLE_CONVERGED = 0, MSG_SAMPLE_MAXITER = 1, MSG_SAMPLE_NONFINITE = 2 };
+
+/* field kinds (Section 1: k = exp(Z), Z Gaussian) */
+enum {
+    /* Z(x,y) = sum_t amp_t xi_t cos(pi a_t x) cos(pi b_t y), t < n_terms */
+    MSG_FIELD_COS_TABLE = 0,
+    /* separable squared-exponential Karhunen-Loeve expansion: per direction
+     * phi_0 = 1, phi_k = sqrt(2) cos(pi k x), eigenvalues proportional to
+     * exp(-pi^2 l^2 k^2 / 2) normalised to sum one, and
+     * Z = sqrt(sigma2) sum_{m<mx, n<my} sqrt(lam_m lam_n) xi_{m*my+n} phi_m(x) phi_n(y) */
+    MSG_FIELD_SEPARABLE_SE = 1
+};
+
+enum { MSG_FP64 = 0, MSG_MIXED = 1 };
+
+typedef struct {
+    int32_t kind;               /* MSG_FIELD_* */
+    int32_t n_terms;            /* COS_TABLE: number of terms; SEPARABLE_SE: mx*my */
+    const int32_t *a;           /* COS_TABLE: host [n_terms] x-frequencies (>= 0) */
+    const int32_t *b;           /* COS_TABLE: host [n_terms] y-frequencies (>= 0) */
+    const double *amp;          /* COS_TABLE: host [n_terms] amplitudes */
+    int32_t mx, my;             /* SEPARABLE_SE: modes per direction */
+    double lx, ly, sigma2;      /* SEPARABLE_SE: correlation lengths and variance */
+} msg_field_spec;
+
+typedef struct {
+    int32_t n_samples;          /* S >= 1 */
+    int32_t c;                  /* coarsest cells per direction, 1..8 */
+    const int32_t *P;           /* host [S] finest x index, 0..14 */
+    const int32_t *Q;           /* host [S] finest y index, 0..14 */
+} msg_batch_desc;
+
+typedef struct {
+    int32_t mu;                 /* 1 = V-cycle, 2 = W-cycle (Section 2) */
+    int32_t nu1, nu2;           /* red-black Gauss-Seidel sweeps before / after */
+    int32_t max_cycles;         /* cap on cycles per grid of the F-cycle */
+    double tol;                 /* stop when ||b - A v||_2 <= tol ||b||_2 per grid */
+    double omega;               /* damping of the coarse-grid correction (1 = none) */
+    int32_t precision;          /* MSG_FP64, or MSG_MIXED: FP32 inner cycles refined in FP64 */
+    int32_t tail_levels;        /* -1 = automatic; else levels 0..tail_levels run in one
+                                   workgroup per grid from on-chip memory */
+} msg_solve_opts;
+
+/* Fill opts with the defaults: W(2,2), 50 cycles, tol 1e-10, omega 1, FP64. */
+void msg_default_opts(msg_solve_opts *opts);
+
+/* Create a handle bound to HIP device `device`.  Returns MSG_OK or MSG_ERR_HIP. */
+msg_status msg_create(msg_handle *h, int device);
+void msg_destroy(msg_handle h);
+const char *msg_last_error(void);
+
+/* Offsets of the packed layout.  All outputs are host arrays the caller
+ * sizes: cell_off, xface_off, yface_off have n_samples+1 entries (sample
+ * starts, last = totals); grid_off has n_samples+1 entries indexing the
+ * per-grid scalar arrays.  Any output pointer may be NULL. */
+msg_status msg_layout(const msg_batch_desc *batch, int64_t *cell_off, int64_t *xface_off,
+                      int64_t *yface_off, int64_t *grid_off);
+
+/* Bytes of device workspace msg_solve_batch needs for this batch and options. */
+msg_status msg_workspace_size(msg_handle h, const msg_batch_desc *batch,
+                              const msg_solve_opts *opts, size_t *bytes);
+
+/* Coefficient field k = exp(Z) at every face midpoint of every grid of every
+ * sample (direct discretisation on each grid, Section 2; the paper samples
+ * Z exactly, Section 5 -- here Z is the KL sum of msg_field_spec).
+ * d_xi: device [S][n_terms] standard normal coefficients, row per sample.
+ * d_kx, d_ky: device FP64 outputs in the face layout.  d_kx32, d_ky32: NULL,
+ * or FP32 copies (needed by MSG_MIXED solves).  Enqueued on `stream`. */
+msg_status msg_sample_field(msg_handle h, const msg_field_spec *spec, const msg_batch_desc *batch,
+                            const double *d_xi, double *d_kx, double *d_ky,
+                            float *d_kx32, float *d_ky32, msg_stream stream);
+
+/* Full MSG solve of every sample (Section 2, Algorithm MSG F-cycle with the
+ * MSG mu-cycle, eq. restriction, eq. interpolation, eq. weight_factors),
+ * returning the solution of every grid (p,q) of every sample -- the "free
+ * solutions on all coarser grids" of Section 3 -- and Q = mean of u per grid.
+ *   d_kx, d_ky      device FP64 face coefficients (msg_sample_field layout)
+ *   d_kx32, d_ky32  device FP32 copies, required for MSG_MIXED, else ignored
+ *   d_rhs           NULL for h = 1, else device FP64 right-hand side at the
+ *                   cell centres of each sample's finest grid, packed per
+ *                   sample (finest-grid cells only)
+ *   d_u_out         device FP64 [cells] every grid's solution
+ *   d_q_out         device FP64 [grids] mean of u over each grid
+ *   d_status        device int32 [S] MSG_SAMPLE_*
+ *   d_cycles        device int32 [grids] cycles run per grid (NULL allowed)
+ *   d_ws, ws_bytes  device workspace of at least msg_workspace_size() bytes
+ * Each grid (p,q), level by level from (0,0) up, starts from the weighted
+ * cubic interpolation of the level below and runs mu-cycles over its own
+ * rectangle [0..p]x[0..q] until ||r||_2 <= tol ||b||_2 or max_cycles.  A
+ * sample whose norms turn non-finite gets status NONFINITE and NaN on the
+ * grids of that level and above; other samples are unaffected.  The call
+ * returns after the solve has completed on `stream` (it reads convergence
+ * flags back between cycles). */
+msg_status msg_solve_batch(msg_handle h, const msg_batch_desc *batch, const msg_solve_opts *opts,
+                           const double *d_kx, const double *d_ky,
+                           const float *d_kx32, const float *d_ky32,
+                           const double *d_rhs, double *d_u_out, double *d_q_out,
+                           int32_t *d_status, int32_t *d_cycles,
+                           void *d_ws, size_t ws_bytes, msg_stream stream);
+
+/* Multi-index differences (Section 3): for every sample and grid l = (p,q),
+ * Delta Q_l = (Delta_1 x Delta_2) Q_l with Delta_i Q_l = Q_l - Q_{l - e_i}
+ * when l_i > 0, else Q_l.  d_q, d_dq: device FP64 [grids] in the per-grid
+ * layout.  Enqueued on `stream`. */
+msg_status mimc_delta_q(const msg_batch_desc *batch, const double *d_q, double *d_dq,
+                        msg_stream stream);
+
+/* Per-kernel timing (measurement support).  While enabled, msg_solve_batch
+ * records a pair of HIP events around every launch of each kernel kind on
+ * the caller's stream and accumulates, per kind, the launches, the summed
+ * event time and the algorithmic bytes of those launches (the data the
+ * kernel must touch at least once for the problems still cycling: see the
+ * design notes).  Enabling or disabling clears the totals. */
+enum {
+    MSG_KERNEL_SMOOTH = 0,        /* red-black Gauss-Seidel passes */
+    MSG_KERNEL_RESTRICT = 1,      /* residual + restriction (eq. restriction) */
+    MSG_KERNEL_PROLONG = 2,       /* weighted correction (eq. interpolation) */
+    MSG_KERNEL_TAIL = 3,          /* on-chip cycles of the lowest levels */
+    MSG_KERNEL_RESIDUAL_NORM = 4, /* finest-grid residual norms */
+    MSG_KERNEL_KINDS = 5
+};
+typedef struct {
+    int64_t launches;
+    double milliseconds;          /* sum of per-launch event times */
+    double bytes;                 /* algorithmic bytes of those launches */
+} msg_kernel_stats;
+
+msg_status msg_set_profiling(msg_handle h, int enable);
+msg_status msg_get_profile(msg_handle h, int kind, msg_kernel_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,102 @@
+// msg_device.hpp -- structures passed from the host scheduler to the HIP
+// kernels of the batched MSG solver, and the closed-form offsets of the packed
+// grid layout (grids of a sample packed p-major then q-minor, each grid
+// row-major with x fastest; see include/msg.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msg {
+
+constexpr int kMaxIndex = 14;          // largest p or q of a grid
+constexpr int kMaxLevelGrids = kMaxIndex + 1;
+constexpr int kMaxTailGrids = 45;      // grids with p + q <= 8
+constexpr int kMaxCosTerms = 64;
+constexpr int kMaxModes = 64;
+constexpr int kBlock = 256;            // threads per block of the level kernels
+constexpr int kRbgsLds = 2048;         // elements of the smoother's LDS tile (with halo)
+
+// ---- offsets of grid (p,q) inside a sample with finest index (P,Qs) ------
+// cells of the grids before (p,q): sum over a < p, b <= Qs of c2^a c2^b,
+// plus sum over b < q of c2^p c2^b.
+__host__ __device__ inline int64_t cell_off(int c, int Qs, int p, int q)
+{
+    const int64_t c2 = (int64_t)c * c;
+    return c2 * (((int64_t)1 << p) - 1) * (((int64_t)2 << Qs) - 1) + c2 * ((int64_t)1 << p) * (((int64_t)1 << q) - 1);
+}
+// x-faces: grid (a,b) holds (c2^a + 1) c2^b of them
+__host__ __device__ inline int64_t xface_off(int c, int Qs, int p, int q)
+{
+    const int64_t rows = (int64_t)c * (((int64_t)2 << Qs) - 1);
+    return rows * ((int64_t)c * (((int64_t)1 << p) - 1) + p) + ((int64_t)c * ((int64_t)1 << p) + 1) * (int64_t)c * (((int64_t)1 << q) - 1);
+}
+// y-faces: grid (a,b) holds c2^a (c2^b + 1) of them
+__host__ __device__ inline int64_t yface_off(int c, int Qs, int p, int q)
+{
+    const int64_t cols = (int64_t)c * (((int64_t)2 << Qs) - 1) + (Qs + 1);
+    return (int64_t)c * (((int64_t)1 << p) - 1) * cols + (int64_t)c * ((int64_t)1 << p) * ((int64_t)c * (((int64_t)1 << q) - 1) + q);
+}
+__host__ __device__ inline int64_t sample_cells(int c, int P, int Q) { return cell_off(c, Q, P + 1, 0); }
+__host__ __device__ inline int64_t sample_xfaces(int c, int P, int Q) { return xface_off(c, Q, P + 1, 0); }
+__host__ __device__ inline int64_t sample_yfaces(int c, int P, int Q) { return yface_off(c, Q, P + 1, 0); }
+
+// One problem of an F-cycle level: grid (p,q) of one sample, iterated over
+// its own rectangle [0..p] x [0..q].  Its iterates and right-hand sides live
+// in the stage arena; its coefficients are the sample's.
+struct KProb {
+    int32_t sample;
+    int32_t Qs;            // sample's finest y index (layout of its arrays)
+    int64_t cell_base;     // sample's first cell in u_out / b_pyr
+    int64_t fx_base;       // sample's first x-face
+    int64_t fy_base;       // sample's first y-face
+    int64_t arena_base;    // problem's first cell in the arena
+    int64_t part_base;     // problem's first partial-sum slot
+    int32_t grid_index;    // (p,q) as p*(Qs+1)+q inside the sample's per-grid arrays
+    int32_t pad;
+};
+
+// One grid of a problem class at the level a kernel works on.
+struct KGrid {
+    int32_t nx, ny;        // cells
+    int32_t p, q;          // grid index
+    int32_t tw, th;        // tile of the smoother (cells)
+    int32_t tiles_x;       // tiles per row of tiles
+    int32_t tile0;         // first block of this grid inside the launch
+    int64_t aoff;          // arena offset of the grid inside a problem
+    int64_t aoff_x;        // arena offset of the x-related grid ((p+1,q) or (p-1,q)), -1 if none
+    int64_t aoff_y;        // arena offset of the y-related grid ((p,q+1) or (p,q-1)), -1 if none
+};
+
+struct KLevel {
+    int32_t ngrids;
+    int32_t ntiles;        // blocks per problem
+    KGrid g[kMaxLevelGrids];
+};
+
+// The grids of levels 0..top of a problem class held in LDS by the tail
+// kernel; grids are ordered by level, then p.
+struct KTailGrid {
+    int32_t nx, ny, p, q;
+    int32_t lv, lb, lkx, lky;  // LDS element offsets of v, b, x-faces, y-faces
+    int64_t aoff;              // arena offset (used for the top level)
+    int16_t cx, cy;            // tail index of child (p-1,q) / (p,q-1), -1 if none
+    int16_t px, py;            // tail index of parent (p+1,q) / (p,q+1), -1 if none
+};
+
+struct KTail {
+    int32_t ngrids;
+    int32_t top;               // level the cycles start on
+    int32_t lds_elems;         // LDS elements of type T (chol factor in doubles after them)
+    int32_t chol_off;          // byte offset of the coarsest factor in LDS
+    int32_t level_begin[32];
+    KTailGrid g[kMaxTailGrids];
+};
+
+struct KCosTable {
+    int32_t n;
+    int32_t a[kMaxCosTerms];
+    int32_t b[kMaxCosTerms];
+    double amp[kMaxCosTerms];
+};
+
+}  // namespace msg

@@ -1,0 +1,1015 @@
+// msg_host.cpp -- C-ABI (include/msg.h) and host scheduler of the batched
+// MSG solver: layout, workspace plan, the F-cycle level loop and the
+// recursive mu-cycle, issuing the kernels of msg_kernels.hip.
+//
+// Paper: Robbe, Nuyens, Vandewalle, arXiv 1907.12334, Section 2 (Algorithm
+// MSG mu-cycle, Algorithm MSG F-cycle).  Each grid (p,q) of F-cycle level L
+// is one "problem": it is iterated with mu-cycles over its own rectangle
+// [0..p] x [0..q]; problems with the same (p,q) form a "class" and share one
+// launch per kernel, whatever samples they come from.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/msg.h"
+#include "msg_device.hpp"
+#include "msg_kernels.hpp"
+
+using namespace msg;
+
+namespace {
+
+thread_local std::string g_err;
+
+msg_status fail(msg_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(MSG_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- validation
+msg_status check_batch(const msg_batch_desc* b)
+{
+    if (!b) return fail(MSG_ERR_ARG, "batch descriptor is NULL");
+    if (b->n_samples < 1) return fail(MSG_ERR_ARG, "n_samples must be >= 1 (got %d)", b->n_samples);
+    if (b->c < 1 || b->c > 8) return fail(MSG_ERR_LAYOUT, "c must be in 1..8 (got %d)", b->c);
+    if (!b->P || !b->Q) return fail(MSG_ERR_ARG, "P and Q arrays are required");
+    for (int s = 0; s < b->n_samples; ++s) {
+        const int P = b->P[s], Q = b->Q[s];
+        if (P < 0 || Q < 0 || P > kMaxIndex || Q > kMaxIndex)
+            return fail(MSG_ERR_LAYOUT, "sample %d: (P,Q) = (%d,%d) outside 0..%d", s, P, Q, kMaxIndex);
+        if (((int64_t)b->c << P) > 32768 || ((int64_t)b->c << Q) > 32768)
+            return fail(MSG_ERR_LAYOUT, "sample %d: finest grid side above 32768 cells", s);
+    }
+    return MSG_OK;
+}
+
+msg_status check_opts(const msg_solve_opts* o)
+{
+    if (!o) return fail(MSG_ERR_ARG, "options are NULL");
+    if (o->mu < 1 || o->mu > 3) return fail(MSG_ERR_ARG, "mu must be 1..3");
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 16 || o->nu2 > 16) return fail(MSG_ERR_ARG, "nu1, nu2 must be 0..16");
+    if (o->max_cycles < 0 || o->max_cycles > 100000) return fail(MSG_ERR_ARG, "max_cycles out of range");
+    if (!(o->tol >= 0.0)) return fail(MSG_ERR_ARG, "tol must be >= 0");
+    if (!std::isfinite(o->omega)) return fail(MSG_ERR_ARG, "omega must be finite");
+    if (o->precision != MSG_FP64 && o->precision != MSG_MIXED) return fail(MSG_ERR_ARG, "unknown precision");
+    if (o->tail_levels < -1 || o->tail_levels > 8) return fail(MSG_ERR_ARG, "tail_levels must be -1..8");
+    return MSG_OK;
+}
+
+// ---------------------------------------------------------------- layout
+struct BatchLayout {
+    int S, c;
+    std::vector<int> P, Q;
+    std::vector<int64_t> cell, xf, yf, grid, top;   // S+1 prefix arrays (top: finest-grid cells)
+    int maxL;
+};
+
+BatchLayout make_layout(const msg_batch_desc* b)
+{
+    BatchLayout L;
+    L.S = b->n_samples;
+    L.c = b->c;
+    L.P.assign(b->P, b->P + L.S);
+    L.Q.assign(b->Q, b->Q + L.S);
+    L.cell.assign(L.S + 1, 0);
+    L.xf.assign(L.S + 1, 0);
+    L.yf.assign(L.S + 1, 0);
+    L.grid.assign(L.S + 1, 0);
+    L.top.assign(L.S + 1, 0);
+    L.maxL = 0;
+    for (int s = 0; s < L.S; ++s) {
+        const int P = L.P[s], Q = L.Q[s];
+        L.cell[s + 1] = L.cell[s] + sample_cells(L.c, P, Q);
+        L.xf[s + 1] = L.xf[s] + sample_xfaces(L.c, P, Q);
+        L.yf[s + 1] = L.yf[s] + sample_yfaces(L.c, P, Q);
+        L.grid[s + 1] = L.grid[s] + (int64_t)(P + 1) * (Q + 1);
+        L.top[s + 1] = L.top[s] + ((int64_t)L.c << P) * ((int64_t)L.c << Q);
+        L.maxL = std::max(L.maxL, P + Q);
+    }
+    return L;
+}
+
+// ---------------------------------------------------------------- plans
+int g_fuse = 2;              // smoother sweeps fused per pass (1 or 2)
+int g_tail_lds = 65536;      // LDS budget of the automatic tail choice
+
+void rbgs_tile(int nx, int ny, int H, int& tw, int& th)
+{
+    tw = std::min(nx, 64);
+    th = 1;
+    while (th * 2 <= ny && tw * th * 2 <= 1024 && (tw + 2 * H) * (th * 2 + 2 * H) <= kRbgsLds) th *= 2;
+    if (th < ny && th * 2 > ny) {
+        // non-power-of-two heights: take the largest fitting height
+        int t = ny;
+        while (t > th && (tw * t > 1024 || (tw + 2 * H) * (t + 2 * H) > kRbgsLds)) --t;
+        th = std::max(th, t);
+    }
+}
+
+struct ClassPlan {
+    int pc, qc, L;
+    int K = 0;
+    int first = 0;                 // first problem of the class in the stage table
+    int64_t arena = 0;             // arena offset of the class
+    int64_t stride = 0;            // arena cells per problem
+    std::vector<int64_t> goff;     // arena offset per grid a*(qc+1)+b
+    int tail_top = 0;
+    KTail tail;
+    size_t tail_lds = 0;
+    KLevel top1d;                  // the finest grid, 1-D tiles
+    std::vector<KLevel> rb, pro, res;   // per level: smoother tiles, prolongation, restriction into level-1
+    int64_t part0 = 0;             // first partial-sum slot
+    std::vector<int> samples;
+};
+
+struct StagePlan {
+    int L;
+    std::vector<ClassPlan> classes;
+    int K = 0;
+    int64_t arena_cells = 0;
+    int64_t part_slots = 0;
+};
+
+int64_t grid_cells(int c, int a, int b) { return ((int64_t)c << a) * ((int64_t)c << b); }
+
+KLevel level_1d(int c, int pc, int qc, int lev, const std::vector<int64_t>& goff, int rel /*0 none, 1 children, 2 parents*/,
+                int maxq)
+{
+    KLevel K;
+    std::memset(&K, 0, sizeof K);
+    int tiles = 0;
+    for (int a = 0; a <= pc; ++a) {
+        const int b = lev - a;
+        if (b < 0 || b > qc) continue;
+        KGrid& G = K.g[K.ngrids++];
+        G.nx = c << a;
+        G.ny = c << b;
+        G.p = a;
+        G.q = b;
+        G.tw = G.nx;
+        G.th = 1;
+        G.tiles_x = 1;
+        G.tile0 = tiles;
+        G.aoff = goff[a * (maxq + 1) + b];
+        G.aoff_x = G.aoff_y = -1;
+        if (rel == 1) {
+            if (a > 0) G.aoff_x = goff[(a - 1) * (maxq + 1) + b];
+            if (b > 0) G.aoff_y = goff[a * (maxq + 1) + b - 1];
+        } else if (rel == 2) {
+            if (a + 1 <= pc) G.aoff_x = goff[(a + 1) * (maxq + 1) + b];
+            if (b + 1 <= qc) G.aoff_y = goff[a * (maxq + 1) + b + 1];
+        }
+        tiles += (int)ceil_div(grid_cells(c, a, b), kBlock);
+    }
+    K.ntiles = tiles;
+    return K;
+}
+
+KLevel level_rbgs(int c, int pc, int qc, int lev, const std::vector<int64_t>& goff, int H)
+{
+    KLevel K;
+    std::memset(&K, 0, sizeof K);
+    int tiles = 0;
+    for (int a = 0; a <= pc; ++a) {
+        const int b = lev - a;
+        if (b < 0 || b > qc) continue;
+        KGrid& G = K.g[K.ngrids++];
+        G.nx = c << a;
+        G.ny = c << b;
+        G.p = a;
+        G.q = b;
+        rbgs_tile(G.nx, G.ny, H, G.tw, G.th);
+        G.tiles_x = (int)ceil_div(G.nx, G.tw);
+        G.tile0 = tiles;
+        G.aoff = goff[a * (qc + 1) + b];
+        G.aoff_x = G.aoff_y = -1;
+        tiles += G.tiles_x * (int)ceil_div(G.ny, G.th);
+    }
+    K.ntiles = tiles;
+    return K;
+}
+
+// LDS layout of the tail of class (pc,qc) with top level m; returns bytes
+template <typename T>
+size_t tail_layout(int c, int pc, int qc, int m, const std::vector<int64_t>& goff, KTail& TL)
+{
+    std::memset(&TL, 0, sizeof TL);
+    TL.top = m;
+    int64_t off = 0;
+    std::map<std::pair<int, int>, int> idx;
+    for (int lev = 0; lev <= m; ++lev) {
+        TL.level_begin[lev] = TL.ngrids;
+        for (int a = 0; a <= pc; ++a) {
+            const int b = lev - a;
+            if (b < 0 || b > qc) continue;
+            if (TL.ngrids >= kMaxTailGrids) return 0;
+            KTailGrid& G = TL.g[TL.ngrids];
+            idx[{a, b}] = TL.ngrids++;
+            G.nx = c << a;
+            G.ny = c << b;
+            G.p = a;
+            G.q = b;
+            const int64_t n = (int64_t)G.nx * G.ny;
+            G.lv = (int)off; off += n;
+            G.lb = (int)off; off += n;
+            G.lkx = (int)off; off += (int64_t)(G.nx + 1) * G.ny;
+            G.lky = (int)off; off += (int64_t)G.nx * (G.ny + 1);
+            G.aoff = goff[a * (qc + 1) + b];
+        }
+    }
+    TL.level_begin[m + 1] = TL.ngrids;
+    for (int g = 0; g < TL.ngrids; ++g) {
+        KTailGrid& G = TL.g[g];
+        auto find = [&](int a, int b) -> int16_t {
+            auto it = idx.find({a, b});
+            return it == idx.end() ? (int16_t)-1 : (int16_t)it->second;
+        };
+        G.cx = G.p > 0 ? find(G.p - 1, G.q) : (int16_t)-1;
+        G.cy = G.q > 0 ? find(G.p, G.q - 1) : (int16_t)-1;
+        G.px = G.p + 1 <= pc ? find(G.p + 1, G.q) : (int16_t)-1;
+        G.py = G.q + 1 <= qc ? find(G.p, G.q + 1) : (int16_t)-1;
+    }
+    TL.lds_elems = (int)off;
+    TL.chol_off = (int)(((size_t)off * sizeof(T) + 15) / 16 * 16);
+    return (size_t)TL.chol_off + sizeof(double) * (size_t)c * c * c * c;
+}
+
+template <typename T>
+int choose_tail(int c, int pc, int qc, int L, int req, const std::vector<int64_t>& goff)
+{
+    KTail TL;
+    if (req >= 0) return std::min(req, L);
+    int best = 0;
+    for (int m = 0; m <= std::min(L, 8); ++m) {
+        const size_t bytes = tail_layout<T>(c, pc, qc, m, goff, TL);
+        if (bytes == 0 || bytes > (size_t)g_tail_lds) break;
+        best = m;
+    }
+    return best;
+}
+
+std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o)
+{
+    std::vector<StagePlan> plans(BL.maxL + 1);
+    const int c = BL.c;
+    const int H = 2 * g_fuse;
+    for (int L = 0; L <= BL.maxL; ++L) {
+        StagePlan& SP = plans[L];
+        SP.L = L;
+        for (int pc = 0; pc <= L; ++pc) {
+            const int qc = L - pc;
+            if (pc > kMaxIndex || qc > kMaxIndex) continue;
+            ClassPlan C;
+            C.pc = pc;
+            C.qc = qc;
+            C.L = L;
+            for (int s = 0; s < BL.S; ++s)
+                if (BL.P[s] >= pc && BL.Q[s] >= qc) C.samples.push_back(s);
+            if (C.samples.empty()) continue;
+            C.K = (int)C.samples.size();
+            C.goff.assign((size_t)(pc + 1) * (qc + 1), 0);
+            int64_t off = 0;
+            for (int a = 0; a <= pc; ++a)
+                for (int b = 0; b <= qc; ++b) {
+                    C.goff[a * (qc + 1) + b] = off;
+                    off += grid_cells(c, a, b);
+                }
+            C.stride = off;
+            C.first = SP.K;
+            C.arena = SP.arena_cells;
+            SP.K += C.K;
+            SP.arena_cells += C.stride * C.K;
+            C.tail_top = o.precision == MSG_MIXED ? choose_tail<float>(c, pc, qc, L, o.tail_levels, C.goff)
+                                                   : choose_tail<double>(c, pc, qc, L, o.tail_levels, C.goff);
+            C.tail_lds = o.precision == MSG_MIXED ? tail_layout<float>(c, pc, qc, C.tail_top, C.goff, C.tail)
+                                                   : tail_layout<double>(c, pc, qc, C.tail_top, C.goff, C.tail);
+            C.top1d = level_1d(c, pc, qc, L, C.goff, 1, qc);
+            C.rb.resize(L + 1);
+            C.pro.resize(L + 1);
+            C.res.resize(L + 1);
+            for (int lev = 1; lev <= L; ++lev) {
+                C.rb[lev] = level_rbgs(c, pc, qc, lev, C.goff, H);
+                C.pro[lev] = level_1d(c, pc, qc, lev, C.goff, 1, qc);
+                C.res[lev] = level_1d(c, pc, qc, lev - 1, C.goff, 2, qc);
+            }
+            C.part0 = SP.part_slots;
+            SP.part_slots += (int64_t)C.top1d.ntiles * C.K;
+            SP.classes.push_back(std::move(C));
+        }
+    }
+    return plans;
+}
+
+// ---------------------------------------------------------------- workspace
+struct Ws {
+    size_t bpyr, chol, a64v, a64v2, a64b, a32v, a32v2, a32b, part, active, pcycles, dead, nactive, sbase, gbase, rbase, probs,
+        pyrprobs, total;
+};
+
+Ws ws_layout(const BatchLayout& BL, const std::vector<StagePlan>& plans, bool mixed)
+{
+    int64_t arena = 0, parts = 0, probs = 0;
+    for (const StagePlan& SP : plans) {
+        arena = std::max(arena, SP.arena_cells);
+        parts = std::max(parts, SP.part_slots);
+        probs = std::max<int64_t>(probs, SP.K);
+    }
+    const int n0 = BL.c * BL.c;
+    Ws w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
+    w.bpyr = take(sizeof(double) * BL.cell[BL.S]);
+    w.chol = take(sizeof(double) * (size_t)BL.S * n0 * n0);
+    w.a64v = take(sizeof(double) * arena);
+    w.a64v2 = take(sizeof(double) * arena);
+    w.a64b = take(sizeof(double) * arena);
+    w.a32v = take(mixed ? sizeof(float) * arena : 0);
+    w.a32v2 = take(mixed ? sizeof(float) * arena : 0);
+    w.a32b = take(mixed ? sizeof(float) * arena : 0);
+    w.part = take(sizeof(double) * 2 * std::max<int64_t>(parts, 1));
+    w.active = take(sizeof(int32_t) * std::max<int64_t>(probs, 1));
+    w.pcycles = take(sizeof(int32_t) * std::max<int64_t>(probs, 1));
+    w.dead = take(sizeof(int32_t) * BL.S);
+    w.nactive = take(sizeof(int32_t) * (kMaxIndex + 1));
+    w.sbase = take(sizeof(SampleBase) * BL.S);
+    w.gbase = take(sizeof(int64_t) * BL.S);
+    w.rbase = take(sizeof(int64_t) * BL.S);
+    w.probs = take(sizeof(KProb) * std::max<int64_t>(probs, 1));
+    w.pyrprobs = take(sizeof(KProb) * BL.S);
+    w.total = off;
+    return w;
+}
+
+std::vector<SampleBase> sample_bases(const BatchLayout& BL)
+{
+    std::vector<SampleBase> v(BL.S);
+    for (int s = 0; s < BL.S; ++s) {
+        v[s].fx = BL.xf[s];
+        v[s].fy = BL.yf[s];
+        v[s].P = BL.P[s];
+        v[s].Q = BL.Q[s];
+    }
+    return v;
+}
+
+// launch a per-problem kernel over problems [0, K) in chunks that keep the
+// block count below 2^31
+template <typename F>
+msg_status chunked(const KLevel& L, int K, F&& f)
+{
+    const int64_t per = std::max<int64_t>(1, ((int64_t)1 << 30) / std::max(1, L.ntiles));
+    for (int64_t k0 = 0; k0 < K; k0 += per) {
+        const int kn = (int)std::min<int64_t>(per, K - k0);
+        hipError_t e = f((int)k0, kn);
+        if (e != hipSuccess) return fail(MSG_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    }
+    return MSG_OK;
+}
+
+}  // namespace
+
+// Per-kernel-kind event timing while profiling is on: a pair of events
+// around each launch, resolved at the next synchronisation point.
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int kind;
+        double bytes;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> pending;
+    msg_kernel_stats tot[MSG_KERNEL_KINDS] = {};
+
+    hipEvent_t get()
+    {
+        if (pool.empty()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            return e;
+        }
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    // resolve every pending pair (the stream has been synchronised)
+    void resolve()
+    {
+        for (Rec& r : pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                tot[r.kind].launches += 1;
+                tot[r.kind].milliseconds += ms;
+                tot[r.kind].bytes += r.bytes;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+    void reset()
+    {
+        pending.clear();
+        for (auto& t : tot) t = msg_kernel_stats{0, 0.0, 0.0};
+    }
+    ~Profiler()
+    {
+        for (hipEvent_t e : pool) hipEventDestroy(e);
+        for (Rec& r : pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+    }
+};
+
+struct msg_handle_s {
+    int device;
+    Profiler prof;
+};
+
+// ======================================================================
+// C-ABI
+// ======================================================================
+extern "C" {
+
+void msg_default_opts(msg_solve_opts* o)
+{
+    if (!o) return;
+    o->mu = 2;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->max_cycles = 50;
+    o->tol = 1e-10;
+    o->omega = 1.0;
+    o->precision = MSG_FP64;
+    o->tail_levels = -1;
+}
+
+const char* msg_last_error(void) { return g_err.c_str(); }
+
+msg_status msg_create(msg_handle* h, int device)
+{
+    if (!h) return fail(MSG_ERR_ARG, "handle pointer is NULL");
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(MSG_ERR_ARG, "device %d not present (%d devices)", device, n);
+    HIPCHK(hipSetDevice(device));
+    if (const char* f = std::getenv("MSG_RBGS_FUSE")) g_fuse = std::atoi(f) == 1 ? 1 : 2;
+    if (const char* t = std::getenv("MSG_TAIL_LDS")) g_tail_lds = std::max(1024, std::atoi(t));
+    *h = new msg_handle_s{device};
+    return MSG_OK;
+}
+
+void msg_destroy(msg_handle h) { delete h; }
+
+msg_status msg_layout(const msg_batch_desc* batch, int64_t* cell_off_out, int64_t* xface_off_out,
+                      int64_t* yface_off_out, int64_t* grid_off_out)
+{
+    msg_status st = check_batch(batch);
+    if (st != MSG_OK) return st;
+    const BatchLayout BL = make_layout(batch);
+    for (int s = 0; s <= BL.S; ++s) {
+        if (cell_off_out) cell_off_out[s] = BL.cell[s];
+        if (xface_off_out) xface_off_out[s] = BL.xf[s];
+        if (yface_off_out) yface_off_out[s] = BL.yf[s];
+        if (grid_off_out) grid_off_out[s] = BL.grid[s];
+    }
+    return MSG_OK;
+}
+
+msg_status msg_workspace_size(msg_handle, const msg_batch_desc* batch, const msg_solve_opts* opts, size_t* bytes)
+{
+    msg_status st = check_batch(batch);
+    if (st != MSG_OK) return st;
+    if ((st = check_opts(opts)) != MSG_OK) return st;
+    if (!bytes) return fail(MSG_ERR_ARG, "bytes is NULL");
+    const BatchLayout BL = make_layout(batch);
+    const std::vector<StagePlan> plans = make_plans(BL, *opts);
+    *bytes = ws_layout(BL, plans, opts->precision == MSG_MIXED).total;
+    return MSG_OK;
+}
+
+msg_status msg_sample_field(msg_handle h, const msg_field_spec* spec, const msg_batch_desc* batch,
+                            const double* d_xi, double* d_kx, double* d_ky, float* d_kx32, float* d_ky32,
+                            msg_stream stream)
+{
+    if (!h) return fail(MSG_ERR_ARG, "handle is NULL");
+    msg_status st = check_batch(batch);
+    if (st != MSG_OK) return st;
+    if (!spec || !d_xi || !d_kx || !d_ky) return fail(MSG_ERR_ARG, "spec, xi, kx and ky are required");
+    if ((d_kx32 == nullptr) != (d_ky32 == nullptr)) return fail(MSG_ERR_ARG, "give both FP32 copies or neither");
+    hipStream_t s = (hipStream_t)stream;
+    FieldArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.c = batch->c;
+    if (spec->kind == MSG_FIELD_COS_TABLE) {
+        if (spec->n_terms < 1 || spec->n_terms > kMaxCosTerms || !spec->a || !spec->b || !spec->amp)
+            return fail(MSG_ERR_ARG, "cosine table needs 1..%d terms with a, b, amp", kMaxCosTerms);
+        A.kind = 0;
+        A.n_terms = spec->n_terms;
+        A.cos.n = spec->n_terms;
+        int mx = 0, my = 0;
+        for (int t = 0; t < spec->n_terms; ++t) {
+            if (spec->a[t] < 0 || spec->b[t] < 0 || spec->a[t] >= kMaxModes || spec->b[t] >= kMaxModes)
+                return fail(MSG_ERR_ARG, "term %d: frequencies must be in 0..%d", t, kMaxModes - 1);
+            if (!std::isfinite(spec->amp[t])) return fail(MSG_ERR_ARG, "term %d: amplitude not finite", t);
+            A.cos.a[t] = spec->a[t];
+            A.cos.b[t] = spec->b[t];
+            A.cos.amp[t] = spec->amp[t];
+            mx = std::max(mx, spec->a[t] + 1);
+            my = std::max(my, spec->b[t] + 1);
+        }
+        A.Mx = mx;
+        A.My = my;
+    } else if (spec->kind == MSG_FIELD_SEPARABLE_SE) {
+        if (spec->mx < 1 || spec->my < 1 || spec->mx > kMaxModes || spec->my > kMaxModes)
+            return fail(MSG_ERR_ARG, "separable field needs 1..%d modes per direction", kMaxModes);
+        if (spec->n_terms != spec->mx * spec->my) return fail(MSG_ERR_ARG, "n_terms must equal mx*my");
+        if (!(spec->sigma2 >= 0.0) || !(spec->lx > 0.0) || !(spec->ly > 0.0))
+            return fail(MSG_ERR_ARG, "need sigma2 >= 0 and positive correlation lengths");
+        A.kind = 1;
+        A.n_terms = spec->n_terms;
+        A.Mx = spec->mx;
+        A.My = spec->my;
+        A.sigma = std::sqrt(spec->sigma2);
+        // per-direction eigenvalues exp(-pi^2 l^2 k^2 / 2), normalised to sum one
+        auto eig = [](int m, double l, double* lam) {
+            double sum = 0.0;
+            for (int k = 0; k < m; ++k) sum += (lam[k] = std::exp(-M_PI * M_PI * l * l * k * k / 2.0));
+            for (int k = 0; k < m; ++k) lam[k] /= sum;
+        };
+        eig(spec->mx, spec->lx, A.lamx);
+        eig(spec->my, spec->ly, A.lamy);
+    } else {
+        return fail(MSG_ERR_ARG, "unknown field kind %d", spec->kind);
+    }
+    const BatchLayout BL = make_layout(batch);
+    const std::vector<SampleBase> bases = sample_bases(BL);
+    // samples grouped by grid index: one launch per (grid, face kind)
+    std::map<std::pair<int, int>, std::vector<int32_t>> bygrid;
+    for (int s = 0; s < BL.S; ++s)
+        for (int p = 0; p <= BL.P[s]; ++p)
+            for (int q = 0; q <= BL.Q[s]; ++q) bygrid[{p, q}].push_back(s);
+    size_t nlist = 0;
+    for (auto& kv : bygrid) nlist += kv.second.size();
+    HIPCHK(hipSetDevice(h->device));
+    void* dmem = nullptr;
+    const size_t bytes = align_up(sizeof(SampleBase) * BL.S) + sizeof(int32_t) * nlist;
+    HIPCHK(hipMallocAsync(&dmem, bytes, s));
+    SampleBase* d_bases = (SampleBase*)dmem;
+    int32_t* d_lists = (int32_t*)((char*)dmem + align_up(sizeof(SampleBase) * BL.S));
+    std::vector<int32_t> lists;
+    lists.reserve(nlist);
+    for (auto& kv : bygrid) lists.insert(lists.end(), kv.second.begin(), kv.second.end());
+    HIPCHK(hipMemcpyAsync(d_bases, bases.data(), sizeof(SampleBase) * BL.S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_lists, lists.data(), sizeof(int32_t) * nlist, hipMemcpyHostToDevice, s));
+    size_t at = 0;
+    for (auto& kv : bygrid) {
+        A.p = kv.first.first;
+        A.q = kv.first.second;
+        A.nx = batch->c << A.p;
+        A.ny = batch->c << A.q;
+        const int n = (int)kv.second.size();
+        for (int kind = 0; kind < 2; ++kind) {
+            A.kind_faces = kind;
+            for (int s0 = 0; s0 < n; s0 += 65535) {
+                hipError_t e = launch_field(A, std::min(65535, n - s0), d_lists + at + s0, d_bases, d_xi, d_kx, d_ky,
+                                            d_kx32, d_ky32, s);
+                if (e != hipSuccess) return fail(MSG_ERR_HIP, "field launch: %s", hipGetErrorString(e));
+            }
+        }
+        at += n;
+    }
+    HIPCHK(hipFreeAsync(dmem, s));
+    HIPCHK(hipStreamSynchronize(s));   // the host staging vectors die with this call
+    return MSG_OK;
+}
+
+msg_status mimc_delta_q(const msg_batch_desc* batch, const double* d_q, double* d_dq, msg_stream stream)
+{
+    msg_status st = check_batch(batch);
+    if (st != MSG_OK) return st;
+    if (!d_q || !d_dq) return fail(MSG_ERR_ARG, "q and dq are required");
+    hipStream_t s = (hipStream_t)stream;
+    const BatchLayout BL = make_layout(batch);
+    std::vector<int32_t> pq(2 * BL.S);
+    int maxg = 1;
+    for (int k = 0; k < BL.S; ++k) {
+        pq[2 * k] = BL.P[k];
+        pq[2 * k + 1] = BL.Q[k];
+        maxg = std::max(maxg, (BL.P[k] + 1) * (BL.Q[k] + 1));
+    }
+    void* dmem = nullptr;
+    const size_t a = align_up(sizeof(int32_t) * 2 * BL.S);
+    HIPCHK(hipMallocAsync(&dmem, a + sizeof(int64_t) * BL.S, s));
+    HIPCHK(hipMemcpyAsync(dmem, pq.data(), sizeof(int32_t) * 2 * BL.S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync((char*)dmem + a, BL.grid.data(), sizeof(int64_t) * BL.S, hipMemcpyHostToDevice, s));
+    for (int s0 = 0; s0 < BL.S; s0 += 65535) {
+        const int n = std::min(65535, BL.S - s0);
+        hipError_t e = launch_delta_q(n, maxg, (int32_t*)dmem + 2 * s0, (int64_t*)((char*)dmem + a) + s0, d_q, d_dq, s);
+        if (e != hipSuccess) return fail(MSG_ERR_HIP, "delta_q launch: %s", hipGetErrorString(e));
+    }
+    HIPCHK(hipFreeAsync(dmem, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MSG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- the solve
+namespace {
+
+struct Ctx {
+    const BatchLayout* BL;
+    const msg_solve_opts* o;
+    hipStream_t s;
+    int c;
+    const double* chol;
+    KProb* probs;       // device, current stage
+    int32_t* active;
+    Profiler* prof;
+    int64_t kact;       // problems of the current class still cycling
+};
+
+// algorithmic bytes: data a kernel must touch at least once per active problem
+template <typename T>
+double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolong*/, int64_t K)
+{
+    double per = 0.0;
+    for (int g = 0; g < L.ngrids; ++g) {
+        const KGrid& G = L.g[g];
+        const double cells = (double)G.nx * G.ny;
+        const double faces = (double)(G.nx + 1) * G.ny + (double)G.nx * (G.ny + 1);
+        if (kind_rel == 0) {
+            per += 3 * cells + faces;                         // v, b, kx, ky read; v written
+        } else if (kind_rel == 1) {
+            per += 2 * cells;                                 // coarse b and v written
+            if (G.aoff_x >= 0) per += 2 * (2 * cells) + ((2 * G.nx + 1.0) * G.ny + 2.0 * G.nx * (G.ny + 1));
+            if (G.aoff_y >= 0) per += 2 * (2 * cells) + ((G.nx + 1.0) * 2 * G.ny + G.nx * (2.0 * G.ny + 1));
+        } else {
+            per += 2 * cells + faces;                         // fine v read and written, faces read
+            if (G.aoff_x >= 0) per += cells / 2;
+            if (G.aoff_y >= 0) per += cells / 2;
+        }
+    }
+    return per * sizeof(T) * (double)K;
+}
+
+template <typename F>
+msg_status timed(const Ctx& X, int kind, double bytes, F&& f)
+{
+    Profiler* P = X.prof;
+    if (!P || !P->on) return f();
+    Profiler::Rec r{P->get(), P->get(), kind, bytes};
+    if (!r.a || !r.b) return fail(MSG_ERR_HIP, "event creation failed");
+    HIPCHK(hipEventRecord(r.a, X.s));
+    msg_status st = f();
+    HIPCHK(hipEventRecord(r.b, X.s));
+    P->pending.push_back(r);
+    return st;
+}
+
+// The iterates of a class live in two buffers: the smoother reads one and
+// writes the other.  cur[l] says which buffer holds the current iterate of
+// the grids on level l (all grids of a level of a class move together).
+template <typename T>
+struct Iter {
+    T* v[2];
+    int cur[2 * kMaxIndex + 2];
+    T* now(int l) const { return v[cur[l]]; }
+};
+
+// Algorithm MSG mu-cycle on level lev of class C, recursion on the host down
+// to the tail level, whose cycles run inside one workgroup per problem.
+template <typename T>
+msg_status mu_cycle(const Ctx& X, const ClassPlan& C, int lev, Iter<T>& it, T* B, const T* KX, const T* KY)
+{
+    const KProb* pr = X.probs + C.first;
+    const int32_t* act = X.active + C.first;
+    msg_status st;
+    auto tail = [&](int count) {
+        T* V = it.now(C.tail_top);
+        double bytes = 0.0;
+        for (int g = 0; g < C.tail.ngrids; ++g) {
+            const KTailGrid& G = C.tail.g[g];
+            bytes += (double)(G.nx + 1) * G.ny + (double)G.nx * (G.ny + 1);
+            if (G.p + G.q == C.tail.top) bytes += 3.0 * G.nx * G.ny;
+        }
+        bytes = bytes * sizeof(T) * (double)X.kact;
+        return timed(X, MSG_KERNEL_TAIL, bytes, [&] {
+            return chunked(C.top1d, C.K, [&](int k0, int kn) {
+                return launch_tail<T>(C.tail, C.tail_lds, kn, pr + k0, act + k0, X.c, X.o->mu, X.o->nu1, X.o->nu2,
+                                      (T)X.o->omega, count, V, B, KX, KY, X.chol, X.s);
+            });
+        });
+    };
+    if (lev <= C.tail_top) return tail(1);
+    auto smooth = [&](int sweeps) -> msg_status {
+        while (sweeps > 0) {
+            // tiles are planned for the configured fusion; one sweep fits the same tile
+            const int ns = (sweeps >= 2 && g_fuse == 2) ? 2 : 1;
+            const KLevel& L = C.rb[lev];
+            const T* vin = it.now(lev);
+            T* vout = it.v[1 - it.cur[lev]];
+            msg_status r = timed(X, MSG_KERNEL_SMOOTH, level_bytes<T>(L, 0, X.kact), [&] {
+                return chunked(L, C.K, [&](int k0, int kn) {
+                    return launch_rbgs<T>(ns, L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, X.s);
+                });
+            });
+            if (r != MSG_OK) return r;
+            it.cur[lev] ^= 1;
+            sweeps -= ns;
+        }
+        return MSG_OK;
+    };
+    if ((st = smooth(X.o->nu1)) != MSG_OK) return st;
+    {
+        const KLevel& L = C.res[lev];
+        const T* vf = it.now(lev);
+        T* vc = it.v[0];
+        st = timed(X, MSG_KERNEL_RESTRICT, level_bytes<T>(L, 1, X.kact), [&] {
+            return chunked(L, C.K, [&](int k0, int kn) {
+                return launch_restrict<T>(false, L, kn, pr + k0, act + k0, X.c, vf, vc, B, KX, KY, X.s);
+            });
+        });
+        if (st != MSG_OK) return st;
+        it.cur[lev - 1] = 0;
+    }
+    if (lev - 1 <= C.tail_top) {
+        if ((st = tail(X.o->mu)) != MSG_OK) return st;
+    } else {
+        for (int m = 0; m < X.o->mu; ++m)
+            if ((st = mu_cycle<T>(X, C, lev - 1, it, B, KX, KY)) != MSG_OK) return st;
+    }
+    {
+        const KLevel& L = C.pro[lev];
+        const T* vc = it.now(lev - 1);
+        T* vf = it.now(lev);
+        st = timed(X, MSG_KERNEL_PROLONG, level_bytes<T>(L, 2, X.kact), [&] {
+            return chunked(L, C.K, [&](int k0, int kn) {
+                return launch_prolong<T>(L, kn, pr + k0, act + k0, X.c, (T)X.o->omega, vc, vf, KX, KY, X.s);
+            });
+        });
+        if (st != MSG_OK) return st;
+    }
+    return smooth(X.o->nu2);
+}
+
+}  // namespace
+
+extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch, const msg_solve_opts* opts,
+                                      const double* d_kx, const double* d_ky, const float* d_kx32,
+                                      const float* d_ky32, const double* d_rhs, double* d_u_out, double* d_q_out,
+                                      int32_t* d_status, int32_t* d_cycles, void* d_ws, size_t ws_bytes,
+                                      msg_stream stream)
+{
+    if (!h) return fail(MSG_ERR_ARG, "handle is NULL");
+    msg_status st = check_batch(batch);
+    if (st != MSG_OK) return st;
+    if ((st = check_opts(opts)) != MSG_OK) return st;
+    if (!d_kx || !d_ky || !d_u_out || !d_q_out || !d_status || !d_ws)
+        return fail(MSG_ERR_ARG, "kx, ky, u_out, q_out, status and workspace are required");
+    const bool mixed = opts->precision == MSG_MIXED;
+    if (mixed && (!d_kx32 || !d_ky32)) return fail(MSG_ERR_ARG, "mixed precision needs the FP32 coefficient copies");
+    const BatchLayout BL = make_layout(batch);
+    const std::vector<StagePlan> plans = make_plans(BL, *opts);
+    const Ws W = ws_layout(BL, plans, mixed);
+    if (ws_bytes < W.total) return fail(MSG_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, W.total);
+    if ((uintptr_t)d_ws % kAlign) return fail(MSG_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+    for (const StagePlan& SP : plans)
+        for (const ClassPlan& C : SP.classes)
+            if (C.tail_lds == 0 || C.tail_lds > 160 * 1024)
+                return fail(MSG_ERR_UNSUPPORTED, "tail of class (%d,%d) does not fit LDS; lower tail_levels", C.pc, C.qc);
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    const int c = BL.c, S = BL.S;
+
+    // host tables, alive until the final synchronisation
+    const std::vector<SampleBase> bases = sample_bases(BL);
+    std::vector<int64_t> gbase(BL.grid.begin(), BL.grid.begin() + S), rbase(BL.top.begin(), BL.top.begin() + S);
+    HIPCHK(hipMemcpyAsync(ws + W.sbase, bases.data(), sizeof(SampleBase) * S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws + W.gbase, gbase.data(), sizeof(int64_t) * S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws + W.rbase, rbase.data(), sizeof(int64_t) * S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(d_status, 0, sizeof(int32_t) * S, s));
+    HIPCHK(hipMemsetAsync(ws + W.dead, 0x7f, sizeof(int32_t) * S, s));
+
+    double* bpyr = (double*)(ws + W.bpyr);
+    double* chol = (double*)(ws + W.chol);
+    SampleBase* d_bases = (SampleBase*)(ws + W.sbase);
+    int32_t* dead = (int32_t*)(ws + W.dead);
+    int32_t* nact = (int32_t*)(ws + W.nactive);
+    double* part = (double*)(ws + W.part);
+
+    // coarsest factors, one per sample
+    {
+        hipError_t e = launch_chol(S, c, d_bases, d_kx, d_ky, chol, s);
+        if (e != hipSuccess) return fail(MSG_ERR_HIP, "cholesky launch: %s", hipGetErrorString(e));
+    }
+
+    // right-hand side pyramid (Algorithm MSG F-cycle, restriction of b by
+    // eq. restriction), per class of samples sharing a rectangle
+    std::map<std::pair<int, int>, std::vector<int>> rects;
+    for (int k = 0; k < S; ++k) rects[{BL.P[k], BL.Q[k]}].push_back(k);
+    std::vector<KProb> pyr;
+    pyr.reserve(S);
+    for (auto& kv : rects)
+        for (int k : kv.second) {
+            KProb p;
+            std::memset(&p, 0, sizeof p);
+            p.sample = k;
+            p.Qs = BL.Q[k];
+            p.cell_base = BL.cell[k];
+            p.fx_base = BL.xf[k];
+            p.fy_base = BL.yf[k];
+            p.arena_base = BL.cell[k];
+            pyr.push_back(p);
+        }
+    HIPCHK(hipMemcpyAsync(ws + W.pyrprobs, pyr.data(), sizeof(KProb) * S, hipMemcpyHostToDevice, s));
+    {
+        const KProb* dp = (const KProb*)(ws + W.pyrprobs);
+        int first = 0;
+        for (auto& kv : rects) {
+            const int P = kv.first.first, Q = kv.first.second, K = (int)kv.second.size();
+            std::vector<int64_t> goff((size_t)(P + 1) * (Q + 1));
+            for (int a = 0; a <= P; ++a)
+                for (int b = 0; b <= Q; ++b) goff[a * (Q + 1) + b] = cell_off(c, Q, a, b);
+            const KLevel top = level_1d(c, P, Q, P + Q, goff, 0, Q);
+            st = chunked(top, K, [&](int k0, int kn) {
+                return launch_rhs_top(top, kn, dp + first + k0, bpyr, d_rhs, (const int64_t*)(ws + W.rbase), s);
+            });
+            if (st != MSG_OK) return st;
+            for (int lev = P + Q - 1; lev >= 0; --lev) {
+                const KLevel L = level_1d(c, P, Q, lev, goff, 2, Q);
+                st = chunked(L, K, [&](int k0, int kn) {
+                    return launch_restrict<double>(true, L, kn, dp + first + k0, nullptr, c, nullptr, nullptr, bpyr,
+                                                   d_kx, d_ky, s);
+                });
+                if (st != MSG_OK) return st;
+            }
+            first += K;
+        }
+    }
+
+    Ctx X;
+    X.BL = &BL;
+    X.o = opts;
+    X.s = s;
+    X.c = c;
+    X.chol = chol;
+    X.prof = &h->prof;
+    X.kact = 0;
+    double* a64b = (double*)(ws + W.a64b);
+    float* a32b = mixed ? (float*)(ws + W.a32b) : nullptr;
+    Iter<double> it64;
+    Iter<float> it32;
+    it64.v[0] = (double*)(ws + W.a64v);
+    it64.v[1] = (double*)(ws + W.a64v2);
+    it32.v[0] = mixed ? (float*)(ws + W.a32v) : nullptr;
+    it32.v[1] = mixed ? (float*)(ws + W.a32v2) : nullptr;
+    X.probs = (KProb*)(ws + W.probs);
+    X.active = (int32_t*)(ws + W.active);
+    int32_t* pcycles = (int32_t*)(ws + W.pcycles);
+
+    std::vector<KProb> probs;
+    for (const StagePlan& SP : plans) {
+        // problems of this F-cycle level (the previous level's table copy has
+        // completed: the stream was synchronised at its last convergence check)
+        HIPCHK(hipStreamSynchronize(s));
+        probs.assign(SP.K, KProb{});
+        for (const ClassPlan& C : SP.classes)
+            for (int k = 0; k < C.K; ++k) {
+                const int smp = C.samples[k];
+                KProb& p = probs[C.first + k];
+                p.sample = smp;
+                p.Qs = BL.Q[smp];
+                p.cell_base = BL.cell[smp];
+                p.fx_base = BL.xf[smp];
+                p.fy_base = BL.yf[smp];
+                p.arena_base = C.arena + (int64_t)k * C.stride;
+                p.part_base = C.part0 + (int64_t)k * C.top1d.ntiles;
+                p.grid_index = C.pc * (BL.Q[smp] + 1) + C.qc;
+            }
+        HIPCHK(hipMemcpyAsync(X.probs, probs.data(), sizeof(KProb) * SP.K, hipMemcpyHostToDevice, s));
+        {
+            hipError_t e = launch_activate(SP.K, X.probs, dead, SP.L, X.active, pcycles, s);
+            if (e != hipSuccess) return fail(MSG_ERR_HIP, "activate: %s", hipGetErrorString(e));
+        }
+        // which buffer holds each level's current iterate, per class
+        const int ncls = (int)SP.classes.size();
+        std::vector<Iter<double>> i64(ncls, it64);
+        std::vector<Iter<float>> i32(ncls, it32);
+        for (int ci = 0; ci < ncls; ++ci) {
+            std::fill(std::begin(i64[ci].cur), std::end(i64[ci].cur), 0);
+            std::fill(std::begin(i32[ci].cur), std::end(i32[ci].cur), 0);
+            const ClassPlan& C = SP.classes[ci];
+            st = chunked(C.top1d, C.K, [&](int k0, int kn) {
+                return launch_fmg(C.top1d, kn, X.probs + C.first + k0, X.active + C.first + k0, c, it64.v[0], a64b,
+                                  d_u_out, bpyr, d_kx, d_ky, s);
+            });
+            if (st != MSG_OK) return st;
+        }
+        // adaptive number of cycles per problem (Section 2): check, then cycle
+        std::vector<int32_t> host_active(ncls, 0);
+        for (int it = 0; it <= opts->max_cycles + 1; ++it) {
+            HIPCHK(hipMemsetAsync(nact, 0, sizeof(int32_t) * ncls, s));
+            for (int ci = 0; ci < ncls; ++ci) {
+                const ClassPlan& C = SP.classes[ci];
+                if (it > 0 && host_active[ci] == 0) continue;   // this class has stopped
+                if (mixed) i32[ci].cur[SP.L] = 0;          // the check writes the FP32 top iterate (zero)
+                const double nb = (3.0 * grid_cells(c, C.pc, C.qc) + (double)((c << C.pc) + 1) * (c << C.qc) +
+                                   (double)(c << C.pc) * ((c << C.qc) + 1)) * sizeof(double) *
+                                  (it == 0 ? C.K : host_active[ci]);
+                const double* vtop = i64[ci].now(SP.L);
+                st = timed(X, MSG_KERNEL_RESIDUAL_NORM, nb, [&] {
+                    return chunked(C.top1d, C.K, [&](int k0, int kn) {
+                        return launch_resnorm(C.top1d, kn, X.probs + C.first + k0, X.active + C.first + k0, c,
+                                              vtop, a64b, d_kx, d_ky, part, it32.v[0], a32b, s);
+                    });
+                });
+                if (st != MSG_OK) return st;
+                hipError_t e = launch_converge(C.K, C.top1d.ntiles, X.probs + C.first, X.active + C.first,
+                                               pcycles + C.first, dead, d_status, part, opts->tol, opts->max_cycles,
+                                               SP.L, nact + ci, s);
+                if (e != hipSuccess) return fail(MSG_ERR_HIP, "converge: %s", hipGetErrorString(e));
+            }
+            HIPCHK(hipMemcpyAsync(host_active.data(), nact, sizeof(int32_t) * ncls, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (h->prof.on) h->prof.resolve();
+            int64_t any = 0;
+            for (int32_t a : host_active) any += a;
+            if (any == 0) break;
+            for (int ci = 0; ci < ncls; ++ci) {
+                const ClassPlan& C = SP.classes[ci];
+                X.kact = host_active[ci];
+                if (X.kact == 0) continue;                 // every problem of this class has stopped
+                if (mixed) {
+                    st = mu_cycle<float>(X, C, SP.L, i32[ci], a32b, d_kx32, d_ky32);
+                    if (st != MSG_OK) return st;
+                    const float* e32 = i32[ci].now(SP.L);
+                    st = chunked(C.top1d, C.K, [&](int k0, int kn) {
+                        return launch_ir_update(C.top1d, kn, X.probs + C.first + k0, X.active + C.first + k0,
+                                                it64.v[0], e32, s);
+                    });
+                } else {
+                    st = mu_cycle<double>(X, C, SP.L, i64[ci], a64b, d_kx, d_ky);
+                }
+                if (st != MSG_OK) return st;
+            }
+        }
+        // returned solutions of this level and their means
+        for (int ci = 0; ci < ncls; ++ci) {
+            const ClassPlan& C = SP.classes[ci];
+            const double* vtop = i64[ci].now(SP.L);
+            st = chunked(C.top1d, C.K, [&](int k0, int kn) {
+                return launch_snapshot(C.top1d, kn, X.probs + C.first + k0, dead, SP.L, c, vtop, d_u_out, part, s);
+            });
+            if (st != MSG_OK) return st;
+            const int64_t cells = grid_cells(c, C.pc, C.qc);
+            hipError_t e = launch_qreduce(C.K, C.top1d.ntiles, cells, X.probs + C.first, pcycles + C.first,
+                                          (const int64_t*)(ws + W.gbase), part, d_q_out, d_cycles, s);
+            if (e != hipSuccess) return fail(MSG_ERR_HIP, "qreduce: %s", hipGetErrorString(e));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (h->prof.on) h->prof.resolve();
+    return MSG_OK;
+}
+
+extern "C" msg_status msg_set_profiling(msg_handle h, int enable)
+{
+    if (!h) return fail(MSG_ERR_ARG, "handle is NULL");
+    h->prof.on = enable != 0;
+    h->prof.reset();
+    return MSG_OK;
+}
+
+extern "C" msg_status msg_get_profile(msg_handle h, int kind, msg_kernel_stats* out)
+{
+    if (!h || !out) return fail(MSG_ERR_ARG, "handle and output are required");
+    if (kind < 0 || kind >= MSG_KERNEL_KINDS) return fail(MSG_ERR_ARG, "unknown kernel kind %d", kind);
+    *out = h->prof.tot[kind];
+    return MSG_OK;
+}

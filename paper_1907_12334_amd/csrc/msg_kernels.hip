@@ -1,0 +1,1001 @@
+// msg_kernels.hip -- CDNA4 (gfx950) kernels of the batched MSG solver.
+//
+// Paper: Robbe, Nuyens, Vandewalle, arXiv 1907.12334, Section 2 (MSG), with
+// the cell-centred finite-volume discretisation described in include/msg.h.
+//
+// Every stencil kernel here is memory-bound (a handful of flops per 8-byte
+// value), so the design goals are coalesced row-major access, LDS tiles with
+// recomputed halos for the smoother, and one block per tile of one grid of
+// one problem so that a launch covers the whole batch.  No MFMA: there is no
+// dense contraction on the path.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "msg_device.hpp"
+#include "msg_kernels.hpp"
+
+namespace msg {
+
+// ------------------------------------------------------------------------
+// 5-point cell-centred finite-volume operator (Section 1, eq. PDE): the flux
+// through a face is its conductance k/h^2 times the jump; a wall face is half
+// a cell from the Dirichlet wall (u = 0), so its conductance doubles.
+// ------------------------------------------------------------------------
+template <typename T>
+struct Stencil {
+    T wW, wE, wS, wN;
+};
+
+template <typename T>
+__device__ __forceinline__ Stencil<T> stencil_at(const T* __restrict__ kx, const T* __restrict__ ky, int nx, int ny,
+                                                 int i, int j, T ihx2, T ihy2)
+{
+    Stencil<T> s;
+    s.wW = kx[(int64_t)j * (nx + 1) + i] * ihx2;
+    s.wE = kx[(int64_t)j * (nx + 1) + i + 1] * ihx2;
+    s.wS = ky[(int64_t)j * nx + i] * ihy2;
+    s.wN = ky[(int64_t)(j + 1) * nx + i] * ihy2;
+    if (i == 0) s.wW *= T(2);
+    if (i == nx - 1) s.wE *= T(2);
+    if (j == 0) s.wS *= T(2);
+    if (j == ny - 1) s.wN *= T(2);
+    return s;
+}
+
+// r = b - A v at cell (i,j) of a grid stored row-major in global memory
+template <typename T>
+__device__ __forceinline__ T residual_at(const T* __restrict__ v, const T* __restrict__ b, const T* __restrict__ kx,
+                                         const T* __restrict__ ky, int nx, int ny, int i, int j, T ihx2, T ihy2)
+{
+    const Stencil<T> s = stencil_at(kx, ky, nx, ny, i, j, ihx2, ihy2);
+    const int64_t c = (int64_t)j * nx + i;
+    const T u = v[c];
+    const T uW = i > 0 ? v[c - 1] : T(0);
+    const T uE = i < nx - 1 ? v[c + 1] : T(0);
+    const T uS = j > 0 ? v[c - nx] : T(0);
+    const T uN = j < ny - 1 ? v[c + nx] : T(0);
+    return b[c] - (s.wW * (u - uW) + s.wE * (u - uE) + s.wS * (u - uS) + s.wN * (u - uN));
+}
+
+// Weight factors (eq. weight_factors) in closed form: with f = (-1)^i,
+// (A f)_ij = (-1)^i [2 (kW + kE)/hx^2 + 2 k_wall/hy^2 on cells touching a
+// y-wall]; symmetrically for g = (-1)^j.  kappa_x = lx^2 / (lx^2 + ly^2).
+template <typename T>
+__device__ __forceinline__ T kappa_x_at(const T* __restrict__ kx, const T* __restrict__ ky, int nx, int ny, int i,
+                                        int j, T ihx2, T ihy2)
+{
+    const T kW = kx[(int64_t)j * (nx + 1) + i], kE = kx[(int64_t)j * (nx + 1) + i + 1];
+    const T kS = ky[(int64_t)j * nx + i], kN = ky[(int64_t)(j + 1) * nx + i];
+    T lx = T(2) * (kW + kE) * ihx2;
+    T ly = T(2) * (kS + kN) * ihy2;
+    if (j == 0) lx += T(2) * kS * ihy2;
+    if (j == ny - 1) lx += T(2) * kN * ihy2;
+    if (i == 0) ly += T(2) * kW * ihx2;
+    if (i == nx - 1) ly += T(2) * kE * ihx2;
+    const T a = lx * lx, c = ly * ly;
+    return a / (a + c);
+}
+
+// value of a coarse line at index I with odd reflection at both walls
+template <typename T>
+__device__ __forceinline__ T odd_at(const T* __restrict__ line, int64_t stride, int n, int I)
+{
+    T sign = T(1);
+    while (I < 0 || I >= n) {
+        I = I < 0 ? -1 - I : 2 * n - 1 - I;
+        sign = -sign;
+    }
+    return sign * line[(int64_t)I * stride];
+}
+
+// cell-centred linear interpolation (3/4, 1/4) of fine index i from a coarse line
+template <typename T>
+__device__ __forceinline__ T linear_at(const T* __restrict__ line, int64_t stride, int n, int i)
+{
+    const int I = i >> 1;
+    const T e0 = odd_at(line, stride, n, I);
+    const T e1 = odd_at(line, stride, n, (i & 1) ? I + 1 : I - 1);
+    return T(0.75) * e0 + T(0.25) * e1;
+}
+
+// cell-centred cubic Lagrange interpolation: (-5, 35, 105, -7)/128 on I-2..I+1
+// for the fine cell at I - H/4, mirrored for I + H/4
+template <typename T>
+__device__ __forceinline__ T cubic_at(const T* __restrict__ line, int64_t stride, int n, int i)
+{
+    const int I = i >> 1;
+    if ((i & 1) == 0)
+        return (T(-5) * odd_at(line, stride, n, I - 2) + T(35) * odd_at(line, stride, n, I - 1) +
+                T(105) * odd_at(line, stride, n, I) - T(7) * odd_at(line, stride, n, I + 1)) /
+               T(128);
+    return (T(-7) * odd_at(line, stride, n, I - 1) + T(105) * odd_at(line, stride, n, I) +
+            T(35) * odd_at(line, stride, n, I + 1) - T(5) * odd_at(line, stride, n, I + 2)) /
+           T(128);
+}
+
+// block-wide sum of two values; result valid in thread 0
+__device__ __forceinline__ void block_sum2(double& a, double& b)
+{
+    __shared__ double sa[kBlock / 64], sb[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { sa[w] = a; sb[w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = sa[0]; b = sb[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) { a += sa[k]; b += sb[k]; }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Coefficient field k = exp(Z) at the faces of one grid for a list of samples.
+// Z = sum_{m<Mx, n<My} C_mn cos(pi m x) cos(pi n y); C is built per block from
+// xi and the field spec; the double sum is evaluated as a product of the
+// per-column cosine table and the per-row partial sums D_m(y) = sum_n C_mn cos(pi n y).
+// ------------------------------------------------------------------------
+constexpr int kFieldTI = 64, kFieldTJ = 16;
+
+__device__ __forceinline__ double cospi_ratio(int64_t num, int64_t den)
+{
+    // cos(pi num/den) with the argument reduced exactly modulo 2
+    int64_t r = num % (2 * den);
+    if (r < 0) r += 2 * den;
+    return cospi((double)r / (double)den);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_field(FieldArgs A, const int32_t* __restrict__ samples, const SampleBase* __restrict__ bases,
+        const double* __restrict__ xi, double* __restrict__ KX, double* __restrict__ KY,
+        float* __restrict__ KX32, float* __restrict__ KY32)
+{
+    extern __shared__ double sm[];
+    const int Mx = A.Mx, My = A.My;
+    double* C = sm;                              // Mx*My
+    double* cx = C + Mx * My;                    // Mx*(kFieldTI)
+    double* D = cx + Mx * kFieldTI;              // Mx*kFieldTJ
+    const int s = samples[blockIdx.y];
+    const SampleBase sb = bases[s];
+    const double* xs = xi + (int64_t)s * A.n_terms;
+
+    // coefficient matrix of this sample
+    for (int idx = threadIdx.x; idx < Mx * My; idx += blockDim.x) C[idx] = 0.0;
+    __syncthreads();
+    if (A.kind == 0) {
+        if (threadIdx.x == 0)
+            for (int t = 0; t < A.cos.n; ++t) C[A.cos.a[t] * My + A.cos.b[t]] += A.cos.amp[t] * xs[t];
+    } else {
+        for (int idx = threadIdx.x; idx < Mx * My; idx += blockDim.x) {
+            const int m = idx / My, n = idx % My;
+            const double nm = m == 0 ? 1.0 : sqrt(2.0), nn = n == 0 ? 1.0 : sqrt(2.0);
+            C[idx] = A.sigma * sqrt(A.lamx[m] * A.lamy[n]) * nm * nn * xs[m * My + n];
+        }
+    }
+    __syncthreads();
+
+    // this block's tile of faces
+    const int kind = A.kind_faces;                 // 0: x-faces, 1: y-faces
+    const int nx = A.nx, ny = A.ny;
+    const int fw = kind == 0 ? nx + 1 : nx;        // faces per row
+    const int fh = kind == 0 ? ny : ny + 1;        // rows of faces
+    const int tiles_x = (fw + kFieldTI - 1) / kFieldTI;
+    const int i0 = (blockIdx.x % tiles_x) * kFieldTI, j0 = (blockIdx.x / tiles_x) * kFieldTJ;
+    // x position of face column i: i/nx (x-faces) or (2i+1)/(2nx) (y-faces)
+    for (int idx = threadIdx.x; idx < Mx * kFieldTI; idx += blockDim.x) {
+        const int m = idx / kFieldTI, li = idx % kFieldTI, i = i0 + li;
+        cx[idx] = kind == 0 ? cospi_ratio((int64_t)m * i, nx) : cospi_ratio((int64_t)m * (2 * i + 1), 2 * nx);
+    }
+    // D_m(y_j) for the tile's rows; y position (2j+1)/(2ny) (x-faces) or j/ny (y-faces)
+    for (int idx = threadIdx.x; idx < Mx * kFieldTJ; idx += blockDim.x) {
+        const int m = idx / kFieldTJ, lj = idx % kFieldTJ, j = j0 + lj;
+        double d = 0.0;
+        for (int n = 0; n < My; ++n) {
+            const double cy = kind == 0 ? cospi_ratio((int64_t)n * (2 * j + 1), 2 * ny) : cospi_ratio((int64_t)n * j, ny);
+            d += C[m * My + n] * cy;
+        }
+        D[idx] = d;
+    }
+    __syncthreads();
+    const int64_t base = kind == 0 ? sb.fx + xface_off(A.c, sb.Q, A.p, A.q) : sb.fy + yface_off(A.c, sb.Q, A.p, A.q);
+    double* out = kind == 0 ? KX : KY;
+    float* out32 = kind == 0 ? KX32 : KY32;
+    for (int idx = threadIdx.x; idx < kFieldTI * kFieldTJ; idx += blockDim.x) {
+        const int li = idx % kFieldTI, lj = idx / kFieldTI;
+        const int i = i0 + li, j = j0 + lj;
+        if (i >= fw || j >= fh) continue;
+        double z = 0.0;
+        for (int m = 0; m < Mx; ++m) z += cx[m * kFieldTI + li] * D[m * kFieldTJ + lj];
+        const double k = exp(z);
+        const int64_t o = base + (int64_t)j * fw + i;
+        out[o] = k;
+        if (out32) out32[o] = (float)k;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Coarsest grid: dense Cholesky of A^(0,0) (c^2 unknowns) once per sample,
+// assembled column by column from the stencil; one wavefront per sample.
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(64)
+k_chol(int S, int c, const SampleBase* __restrict__ bases, const double* __restrict__ KX,
+       const double* __restrict__ KY, double* __restrict__ chol)
+{
+    extern __shared__ double A[];                 // n*n
+    const int s = blockIdx.x;
+    if (s >= S) return;
+    const int n = c * c;
+    const SampleBase sb = bases[s];
+    const double* kx = KX + sb.fx;                 // grid (0,0) is first in the sample
+    const double* ky = KY + sb.fy;
+    const double ih2 = (double)c * c;
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) A[idx] = 0.0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const int i = k % c, j = k / c;
+        const Stencil<double> w = stencil_at(kx, ky, c, c, i, j, ih2, ih2);
+        A[k * n + k] = w.wW + w.wE + w.wS + w.wN;
+        if (i > 0) A[(k - 1) * n + k] = -w.wW;
+        if (i < c - 1) A[(k + 1) * n + k] = -w.wE;
+        if (j > 0) A[(k - c) * n + k] = -w.wS;
+        if (j < c - 1) A[(k + c) * n + k] = -w.wN;
+    }
+    __syncthreads();
+    double* L = chol + (int64_t)s * n * n;
+    // lower factor overwrites A column by column
+    for (int j = 0; j < n; ++j) {
+        if (threadIdx.x == 0) {
+            double d = A[j * n + j];
+            for (int k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+            A[j * n + j] = sqrt(d);
+        }
+        __syncthreads();
+        for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
+            double t = A[i * n + j];
+            for (int k = 0; k < j; ++k) t -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = t / A[j * n + j];
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+        const int i = idx / n, j = idx % n;
+        L[idx] = j <= i ? A[idx] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Helpers shared by the level kernels: block -> (problem, grid, tile)
+// ------------------------------------------------------------------------
+struct Where {
+    int k;       // problem
+    int gi;      // grid inside the launch
+    int t;       // tile inside the grid
+};
+
+__device__ __forceinline__ Where locate(const KLevel& L)
+{
+    Where w;
+    const int b = blockIdx.x;
+    w.k = b / L.ntiles;
+    int t = b - w.k * L.ntiles;
+    int gi = 0;
+    while (gi + 1 < L.ngrids && t >= L.g[gi + 1].tile0) ++gi;
+    w.gi = gi;
+    w.t = t - L.g[gi].tile0;
+    return w;
+}
+
+// ------------------------------------------------------------------------
+// Red-black Gauss-Seidel (Section 2: nu1 = nu2 = 2 sweeps), NS sweeps fused
+// per pass: the tile's iterate plus a halo of 2*NS cells sits in LDS; each
+// half-sweep updates one colour on a region that shrinks by one cell, so the
+// tile interior ends exactly as NS global red-then-black sweeps would leave it.
+// The pass reads Vin and writes Vout (a different buffer): neighbouring tiles
+// read their halos from Vin while this tile writes, so an in-place update
+// would race.
+// ------------------------------------------------------------------------
+template <typename T, int NS>
+__global__ void __launch_bounds__(kBlock)
+k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c,
+       const T* __restrict__ Vin, T* __restrict__ Vout, const T* __restrict__ B, const T* __restrict__ KX,
+       const T* __restrict__ KY)
+{
+    constexpr int H = 2 * NS;
+    __shared__ T sv[kRbgsLds];
+    const Where w = locate(L);
+    if (!active[w.k]) return;
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int nx = G.nx, ny = G.ny, tw = G.tw, th = G.th;
+    const int i0 = (w.t % G.tiles_x) * tw, j0 = (w.t / G.tiles_x) * th;
+    const T* v = Vin + pr.arena_base + G.aoff;
+    T* vout = Vout + pr.arena_base + G.aoff;
+    const T* b = B + pr.arena_base + G.aoff;
+    const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
+    const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
+    const T ihx2 = T(nx) * T(nx), ihy2 = T(ny) * T(ny);
+    const int RW = tw + 2 * H, RH = th + 2 * H;
+
+    for (int idx = threadIdx.x; idx < RW * RH; idx += blockDim.x) {
+        const int i = i0 - H + idx % RW, j = j0 - H + idx / RW;
+        sv[idx] = (i >= 0 && i < nx && j >= 0 && j < ny) ? v[(int64_t)j * nx + i] : T(0);
+    }
+    __syncthreads();
+    for (int s = 0; s < NS; ++s) {
+        for (int colour = 0; colour < 2; ++colour) {
+            const int e = H - 1 - 2 * s - colour;            // extent of this half-sweep beyond the tile
+            const int EW = tw + 2 * e, EH = th + 2 * e, slots = (EW + 1) >> 1;
+            const int ib = i0 - e;
+            for (int idx = threadIdx.x; idx < slots * EH; idx += blockDim.x) {
+                const int lj = idx / slots, j = j0 - e + lj;
+                const int li = 2 * (idx - lj * slots) + ((colour - ib - j) & 1);
+                const int i = ib + li;
+                if (li >= EW || i < 0 || i >= nx || j < 0 || j >= ny) continue;
+                const Stencil<T> st = stencil_at(kx, ky, nx, ny, i, j, ihx2, ihy2);
+                const int r = (j - j0 + H) * RW + (i - i0 + H);
+                const T num = b[(int64_t)j * nx + i] + st.wW * sv[r - 1] + st.wE * sv[r + 1] + st.wS * sv[r - RW] +
+                              st.wN * sv[r + RW];
+                sv[r] = num / (st.wW + st.wE + st.wS + st.wN);
+            }
+            __syncthreads();
+        }
+    }
+    for (int idx = threadIdx.x; idx < tw * th; idx += blockDim.x) {
+        const int li = idx % tw, lj = idx / tw, i = i0 + li, j = j0 + lj;
+        if (i < nx && j < ny) vout[(int64_t)j * nx + i] = sv[(lj + H) * RW + li + H];
+    }
+}
+
+// ------------------------------------------------------------------------
+// Residual and restriction (eq. restriction): coarse b = average of the
+// x-restricted residual of (p+1,q) and the y-restricted residual of (p,q+1),
+// one-sided where only one exists; the coarse iterate is zeroed.  With
+// RHS = true the fine quantity is the right-hand side itself (F-cycle).
+// One thread per coarse cell; 256 consecutive cells of one grid per block.
+// ------------------------------------------------------------------------
+template <typename T, bool RHS>
+__global__ void __launch_bounds__(kBlock)
+k_restrict(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c,
+           const T* __restrict__ Vf, T* __restrict__ Vc, T* __restrict__ B, const T* __restrict__ KX,
+           const T* __restrict__ KY)
+{
+    const Where w = locate(L);
+    if (active && !active[w.k]) return;
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const int nx = G.nx, ny = G.ny;
+    if (cell >= (int64_t)nx * ny) return;
+    const int I = (int)(cell % nx), J = (int)(cell / nx);
+    T rx = T(0), ry = T(0);
+    const bool hx = G.aoff_x >= 0, hy = G.aoff_y >= 0;
+    if (hx) {                                   // fine grid (p+1,q): 2nx x ny
+        const int fnx = 2 * nx;
+        const T* vf = Vf + pr.arena_base + G.aoff_x;
+        const T* bf = B + pr.arena_base + G.aoff_x;
+        if (RHS) {
+            rx = T(0.5) * (bf[(int64_t)J * fnx + 2 * I] + bf[(int64_t)J * fnx + 2 * I + 1]);
+        } else {
+            const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p + 1, G.q);
+            const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p + 1, G.q);
+            const T ihx2 = T(fnx) * T(fnx), ihy2 = T(ny) * T(ny);
+            rx = T(0.5) * (residual_at(vf, bf, kx, ky, fnx, ny, 2 * I, J, ihx2, ihy2) +
+                           residual_at(vf, bf, kx, ky, fnx, ny, 2 * I + 1, J, ihx2, ihy2));
+        }
+    }
+    if (hy) {                                   // fine grid (p,q+1): nx x 2ny
+        const int fny = 2 * ny;
+        const T* vf = Vf + pr.arena_base + G.aoff_y;
+        const T* bf = B + pr.arena_base + G.aoff_y;
+        if (RHS) {
+            ry = T(0.5) * (bf[(int64_t)(2 * J) * nx + I] + bf[(int64_t)(2 * J + 1) * nx + I]);
+        } else {
+            const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q + 1);
+            const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q + 1);
+            const T ihx2 = T(nx) * T(nx), ihy2 = T(fny) * T(fny);
+            ry = T(0.5) * (residual_at(vf, bf, kx, ky, nx, fny, I, 2 * J, ihx2, ihy2) +
+                           residual_at(vf, bf, kx, ky, nx, fny, I, 2 * J + 1, ihx2, ihy2));
+        }
+    }
+    const T bc = (hx && hy) ? T(0.5) * rx + T(0.5) * ry : (hx ? rx : ry);
+    B[pr.arena_base + G.aoff + cell] = bc;
+    if (!RHS) Vc[pr.arena_base + G.aoff + cell] = T(0);
+}
+
+// ------------------------------------------------------------------------
+// Coarse-grid correction (eq. interpolation): v += omega (kappa_x P_x e^(p-1,q)
+// + kappa_y P_y e^(p,q-1)), one-sided on q = 0 (P_x only) and p = 0 (P_y only).
+// ------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_prolong(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c, T omega,
+          const T* __restrict__ Vc, T* __restrict__ Vf, const T* __restrict__ KX, const T* __restrict__ KY)
+{
+    const Where w = locate(L);
+    if (!active[w.k]) return;
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const int nx = G.nx, ny = G.ny;
+    if (cell >= (int64_t)nx * ny) return;
+    const int i = (int)(cell % nx), j = (int)(cell / nx);
+    const bool hx = G.aoff_x >= 0, hy = G.aoff_y >= 0;
+    T ex = T(0), ey = T(0);
+    if (hx) ex = linear_at(Vc + pr.arena_base + G.aoff_x + (int64_t)j * (nx / 2), (int64_t)1, nx / 2, i);
+    if (hy) ey = linear_at(Vc + pr.arena_base + G.aoff_y + i, (int64_t)nx, ny / 2, j);
+    T corr;
+    if (hx && hy) {
+        const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
+        const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
+        const T ka = kappa_x_at(kx, ky, nx, ny, i, j, T(nx) * T(nx), T(ny) * T(ny));
+        corr = ka * ex + (T(1) - ka) * ey;
+    } else {
+        corr = hx ? ex : ey;
+    }
+    Vf[pr.arena_base + G.aoff + cell] += omega * corr;
+}
+
+// ------------------------------------------------------------------------
+// Nested iteration (Algorithm MSG F-cycle): the initial iterate of each
+// problem's finest grid is the weighted cubic interpolation of the solutions
+// of (p-1,q) and (p,q-1) returned by the previous level; its right-hand side
+// is copied from the restricted right-hand side pyramid.
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_fmg(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c,
+      double* __restrict__ V, double* __restrict__ B, const double* __restrict__ U,
+      const double* __restrict__ BP, const double* __restrict__ KX, const double* __restrict__ KY)
+{
+    const Where w = locate(L);
+    if (!active[w.k]) return;
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const int nx = G.nx, ny = G.ny;
+    if (cell >= (int64_t)nx * ny) return;
+    const int i = (int)(cell % nx), j = (int)(cell / nx);
+    const bool hx = G.p > 0, hy = G.q > 0;
+    double ex = 0.0, ey = 0.0;
+    if (hx) ex = cubic_at(U + pr.cell_base + cell_off(c, pr.Qs, G.p - 1, G.q) + (int64_t)j * (nx / 2), (int64_t)1, nx / 2, i);
+    if (hy) ey = cubic_at(U + pr.cell_base + cell_off(c, pr.Qs, G.p, G.q - 1) + i, (int64_t)nx, ny / 2, j);
+    double v0;
+    if (hx && hy) {
+        const double* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
+        const double* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
+        const double ka = kappa_x_at(kx, ky, nx, ny, i, j, (double)nx * nx, (double)ny * ny);
+        v0 = ka * ex + (1.0 - ka) * ey;
+    } else if (hx || hy) {
+        v0 = hx ? ex : ey;
+    } else {
+        v0 = 0.0;                                  // the coarsest grid starts from zero
+    }
+    V[pr.arena_base + G.aoff + cell] = v0;
+    B[pr.arena_base + G.aoff + cell] = BP[pr.cell_base + cell_off(c, pr.Qs, G.p, G.q) + cell];
+}
+
+// ------------------------------------------------------------------------
+// Residual norm of each problem's finest grid in FP64: per block partial sums
+// of r^2 and b^2 (fixed order, so a problem's result does not depend on the
+// rest of the batch).  In mixed precision the FP64 residual is also handed to
+// the FP32 inner cycle as its right-hand side, with a zero FP32 iterate.
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_resnorm(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c,
+          const double* __restrict__ V, const double* __restrict__ B, const double* __restrict__ KX,
+          const double* __restrict__ KY, double* __restrict__ part, float* __restrict__ V32,
+          float* __restrict__ B32)
+{
+    const Where w = locate(L);
+    if (!active[w.k]) return;
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const int nx = G.nx, ny = G.ny;
+    double rr = 0.0, bb = 0.0;
+    if (cell < (int64_t)nx * ny) {
+        const int i = (int)(cell % nx), j = (int)(cell / nx);
+        const double* v = V + pr.arena_base + G.aoff;
+        const double* b = B + pr.arena_base + G.aoff;
+        const double* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
+        const double* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
+        const double r = residual_at(v, b, kx, ky, nx, ny, i, j, (double)nx * nx, (double)ny * ny);
+        rr = r * r;
+        bb = b[cell] * b[cell];
+        if (B32) {
+            B32[pr.arena_base + G.aoff + cell] = (float)r;
+            V32[pr.arena_base + G.aoff + cell] = 0.0f;
+        }
+    }
+    block_sum2(rr, bb);
+    if (threadIdx.x == 0) {
+        part[2 * (pr.part_base + w.t)] = rr;
+        part[2 * (pr.part_base + w.t) + 1] = bb;
+    }
+}
+
+// Convergence decision per problem (adaptive nu0 of Section 2): one wavefront
+// sums the partials; converged problems and non-finite ones stop cycling.
+__global__ void __launch_bounds__(64)
+k_converge(int K, int ntiles, const KProb* __restrict__ probs, int32_t* __restrict__ active,
+           int32_t* __restrict__ pcycles, int32_t* __restrict__ dead_level, int32_t* __restrict__ status,
+           const double* __restrict__ part, double tol, int max_cycles, int level, int32_t* __restrict__ n_active)
+{
+    const int k = blockIdx.x;
+    if (k >= K || !active[k]) return;
+    const KProb pr = probs[k];
+    double rr = 0.0, bb = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += 64) {
+        rr += part[2 * (pr.part_base + t)];
+        bb += part[2 * (pr.part_base + t) + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        rr += __shfl_down(rr, off, 64);
+        bb += __shfl_down(bb, off, 64);
+    }
+    if (threadIdx.x != 0) return;
+    const double rn = sqrt(rr), bn = sqrt(bb);
+    if (!isfinite(rn) || !isfinite(bn)) {
+        active[k] = 0;
+        atomicMax(&status[pr.sample], (int)MSG_ST_NONFINITE);
+        atomicMin(&dead_level[pr.sample], level);
+        return;
+    }
+    if (rn <= tol * bn) { active[k] = 0; return; }
+    if (pcycles[k] >= max_cycles) {
+        active[k] = 0;
+        atomicMax(&status[pr.sample], (int)MSG_ST_MAXITER);
+        return;
+    }
+    pcycles[k] += 1;                 // one more cycle is about to run
+    atomicAdd(n_active, 1);
+}
+
+// start of an F-cycle level: every problem cycles unless its sample already
+// went non-finite on a lower level
+__global__ void __launch_bounds__(kBlock)
+k_activate(int K, const KProb* __restrict__ probs, const int32_t* __restrict__ dead_level, int level,
+           int32_t* __restrict__ active, int32_t* __restrict__ pcycles)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    active[k] = dead_level[probs[k].sample] > level ? 1 : 0;
+    pcycles[k] = 0;
+}
+
+// mixed precision: the FP64 iterate takes the FP32 correction
+__global__ void __launch_bounds__(kBlock)
+k_ir_update(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active,
+            double* __restrict__ V, const float* __restrict__ V32)
+{
+    const Where w = locate(L);
+    if (!active[w.k]) return;
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    if (cell >= (int64_t)G.nx * G.ny) return;
+    V[pr.arena_base + G.aoff + cell] += (double)V32[pr.arena_base + G.aoff + cell];
+}
+
+// ------------------------------------------------------------------------
+// Snapshot at the end of an F-cycle level: the problem's finest-grid iterate
+// becomes the returned solution of grid (p,q) (NaN when its sample went
+// non-finite on this level or below), with partial sums for Q = mean of u.
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_snapshot(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ dead_level, int level, int c,
+           const double* __restrict__ V, double* __restrict__ U, double* __restrict__ part)
+{
+    const Where w = locate(L);
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const bool dead = dead_level[pr.sample] <= level;
+    double u = 0.0, zero = 0.0;
+    if (cell < (int64_t)G.nx * G.ny) {
+        u = dead ? __longlong_as_double(0x7ff8000000000000LL) : V[pr.arena_base + G.aoff + cell];
+        U[pr.cell_base + cell_off(c, pr.Qs, G.p, G.q) + cell] = u;
+    }
+    block_sum2(u, zero);
+    if (threadIdx.x == 0) part[2 * (pr.part_base + w.t)] = u;
+}
+
+__global__ void __launch_bounds__(64)
+k_qreduce(int K, int ntiles, int64_t cells, const KProb* __restrict__ probs, const int32_t* __restrict__ pcycles,
+          const int64_t* __restrict__ grid_base, const double* __restrict__ part, double* __restrict__ q_out,
+          int32_t* __restrict__ cycles_out)
+{
+    const int k = blockIdx.x;
+    if (k >= K) return;
+    const KProb pr = probs[k];
+    double s = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += 64) s += part[2 * (pr.part_base + t)];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (threadIdx.x == 0) {
+        q_out[grid_base[pr.sample] + pr.grid_index] = s / (double)cells;
+        if (cycles_out) cycles_out[grid_base[pr.sample] + pr.grid_index] = pcycles[k];
+    }
+}
+
+// right-hand side on each sample's finest grid: h = 1, or the caller's values
+__global__ void __launch_bounds__(kBlock)
+k_rhs_top(KLevel L, const KProb* __restrict__ probs, double* __restrict__ BP, const double* __restrict__ rhs,
+          const int64_t* __restrict__ rhs_base)
+{
+    const Where w = locate(L);
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    if (cell >= (int64_t)G.nx * G.ny) return;
+    BP[pr.arena_base + G.aoff + cell] = rhs ? rhs[rhs_base[pr.sample] + cell] : 1.0;
+}
+
+// ------------------------------------------------------------------------
+// Tail: the mu-cycles of levels 0..top of one problem run inside one
+// workgroup, with every grid of those levels (iterate, right-hand side and
+// face coefficients) held in LDS; the coarsest grid is solved with the
+// sample's FP64 Cholesky factor.  The top level's iterate and right-hand
+// side come from the arena and the iterate goes back there.
+// ------------------------------------------------------------------------
+template <typename T>
+__device__ void tail_smooth(const KTail& TL, T* sm, int lev, int sweeps)
+{
+    const int g0 = TL.level_begin[lev], g1 = TL.level_begin[lev + 1];
+    int total = 0;
+    for (int g = g0; g < g1; ++g) total += TL.g[g].nx * TL.g[g].ny;
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+                int g = g0, off = idx;
+                while (off >= TL.g[g].nx * TL.g[g].ny) { off -= TL.g[g].nx * TL.g[g].ny; ++g; }
+                const KTailGrid& G = TL.g[g];
+                const int i = off % G.nx, j = off / G.nx;
+                if (((i + j) & 1) != colour) continue;
+                T* v = sm + G.lv;
+                const T ihx2 = T(G.nx) * T(G.nx), ihy2 = T(G.ny) * T(G.ny);
+                const Stencil<T> st = stencil_at(sm + G.lkx, sm + G.lky, G.nx, G.ny, i, j, ihx2, ihy2);
+                const T uW = i > 0 ? v[off - 1] : T(0);
+                const T uE = i < G.nx - 1 ? v[off + 1] : T(0);
+                const T uS = j > 0 ? v[off - G.nx] : T(0);
+                const T uN = j < G.ny - 1 ? v[off + G.nx] : T(0);
+                const T num = sm[G.lb + off] + st.wW * uW + st.wE * uE + st.wS * uS + st.wN * uN;
+                v[off] = num / (st.wW + st.wE + st.wS + st.wN);
+            }
+            __syncthreads();
+        }
+}
+
+template <typename T>
+__device__ void tail_restrict(const KTail& TL, T* sm, int lev)   // level lev -> lev-1
+{
+    const int g0 = TL.level_begin[lev - 1], g1 = TL.level_begin[lev];
+    int total = 0;
+    for (int g = g0; g < g1; ++g) total += TL.g[g].nx * TL.g[g].ny;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int g = g0, off = idx;
+        while (off >= TL.g[g].nx * TL.g[g].ny) { off -= TL.g[g].nx * TL.g[g].ny; ++g; }
+        const KTailGrid& G = TL.g[g];
+        const int I = off % G.nx, J = off / G.nx;
+        T rx = T(0), ry = T(0);
+        if (G.px >= 0) {
+            const KTailGrid& F = TL.g[G.px];
+            const T ihx2 = T(F.nx) * T(F.nx), ihy2 = T(F.ny) * T(F.ny);
+            rx = T(0.5) * (residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, 2 * I, J, ihx2, ihy2) +
+                           residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, 2 * I + 1, J, ihx2, ihy2));
+        }
+        if (G.py >= 0) {
+            const KTailGrid& F = TL.g[G.py];
+            const T ihx2 = T(F.nx) * T(F.nx), ihy2 = T(F.ny) * T(F.ny);
+            ry = T(0.5) * (residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, I, 2 * J, ihx2, ihy2) +
+                           residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, I, 2 * J + 1, ihx2, ihy2));
+        }
+        const bool hx = G.px >= 0, hy = G.py >= 0;
+        sm[G.lb + off] = (hx && hy) ? T(0.5) * rx + T(0.5) * ry : (hx ? rx : ry);
+        sm[G.lv + off] = T(0);
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void tail_prolong(const KTail& TL, T* sm, int lev, T omega)
+{
+    const int g0 = TL.level_begin[lev], g1 = TL.level_begin[lev + 1];
+    int total = 0;
+    for (int g = g0; g < g1; ++g) total += TL.g[g].nx * TL.g[g].ny;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int g = g0, off = idx;
+        while (off >= TL.g[g].nx * TL.g[g].ny) { off -= TL.g[g].nx * TL.g[g].ny; ++g; }
+        const KTailGrid& G = TL.g[g];
+        const int i = off % G.nx, j = off / G.nx;
+        const bool hx = G.cx >= 0, hy = G.cy >= 0;
+        T ex = T(0), ey = T(0);
+        if (hx) ex = linear_at(sm + TL.g[G.cx].lv + j * (G.nx / 2), (int64_t)1, G.nx / 2, i);
+        if (hy) ey = linear_at(sm + TL.g[G.cy].lv + i, (int64_t)G.nx, G.ny / 2, j);
+        T corr;
+        if (hx && hy) {
+            const T ka = kappa_x_at(sm + G.lkx, sm + G.lky, G.nx, G.ny, i, j, T(G.nx) * T(G.nx), T(G.ny) * T(G.ny));
+            corr = ka * ex + (T(1) - ka) * ey;
+        } else {
+            corr = hx ? ex : ey;
+        }
+        sm[G.lv + off] += omega * corr;
+    }
+    __syncthreads();
+}
+
+// v^(0,0) = L^-T L^-1 b^(0,0), computed in FP64 by the first wavefront
+template <typename T>
+__device__ void tail_coarse(const KTail& TL, T* sm, const double* Lc, int n)
+{
+    const KTailGrid& G = TL.g[0];
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        double r = lane < n ? (double)sm[G.lb + lane] : 0.0;
+        double y = 0.0;
+        for (int k = 0; k < n; ++k) {                  // forward: L y = b
+            const double yk = __shfl(r, k, 64) / Lc[k * n + k];
+            if (lane == k) y = yk;
+            if (lane > k && lane < n) r -= Lc[lane * n + k] * yk;
+        }
+        double s = y, x = 0.0;
+        for (int k = n - 1; k >= 0; --k) {             // backward: L^T x = y
+            const double xk = __shfl(s, k, 64) / Lc[k * n + k];
+            if (lane == k) x = xk;
+            if (lane < k) s -= Lc[k * n + lane] * xk;
+        }
+        if (lane < n) sm[G.lv + lane] = (T)x;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_tail(KTail TL, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c, int mu, int nu1,
+       int nu2, T omega, int count, T* __restrict__ V, T* __restrict__ B, const T* __restrict__ KX,
+       const T* __restrict__ KY, const double* __restrict__ chol)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    double* Lc = reinterpret_cast<double*>(smem + TL.chol_off);
+    const int k = blockIdx.x;
+    if (!active[k]) return;
+    const KProb pr = probs[k];
+    const int n0 = c * c;
+    // stage in: coefficients of every tail grid, top-level iterate and rhs, factor
+    for (int g = 0; g < TL.ngrids; ++g) {
+        const KTailGrid& G = TL.g[g];
+        const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
+        const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
+        const int nfx = (G.nx + 1) * G.ny, nfy = G.nx * (G.ny + 1);
+        for (int idx = threadIdx.x; idx < nfx; idx += blockDim.x) sm[G.lkx + idx] = kx[idx];
+        for (int idx = threadIdx.x; idx < nfy; idx += blockDim.x) sm[G.lky + idx] = ky[idx];
+        if (G.p + G.q == TL.top) {
+            const int n = G.nx * G.ny;
+            for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+                sm[G.lv + idx] = V[pr.arena_base + G.aoff + idx];
+                sm[G.lb + idx] = B[pr.arena_base + G.aoff + idx];
+            }
+        }
+    }
+    for (int idx = threadIdx.x; idx < n0 * n0; idx += blockDim.x) Lc[idx] = chol[(int64_t)pr.sample * n0 * n0 + idx];
+    __syncthreads();
+
+    // iterative form of the recursive mu-cycle: left[l] counts the cycles
+    // still to run on level l before returning to level l+1
+    int left[kMaxIndex * 2 + 2];
+    int lev = TL.top;
+    left[lev] = count;
+    bool down = true;
+    for (;;) {
+        if (down) {
+            if (lev == 0) {
+                tail_coarse(TL, sm, Lc, n0);
+                down = false;
+                continue;
+            }
+            tail_smooth(TL, sm, lev, nu1);
+            tail_restrict(TL, sm, lev);
+            --lev;
+            left[lev] = mu;
+        } else {
+            // one cycle on level lev just finished
+            if (--left[lev] > 0) { down = true; continue; }
+            if (lev == TL.top) break;
+            ++lev;
+            tail_prolong(TL, sm, lev, omega);
+            tail_smooth(TL, sm, lev, nu2);
+        }
+    }
+    // stage out the top level's iterates
+    for (int g = TL.level_begin[TL.top]; g < TL.level_begin[TL.top + 1]; ++g) {
+        const KTailGrid& G = TL.g[g];
+        const int n = G.nx * G.ny;
+        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) V[pr.arena_base + G.aoff + idx] = sm[G.lv + idx];
+    }
+}
+
+// ------------------------------------------------------------------------
+// Multi-index differences (Section 3), one thread per (sample, grid)
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_delta_q(int S, const int32_t* __restrict__ PQ, const int64_t* __restrict__ gbase, const double* __restrict__ q,
+          double* __restrict__ dq)
+{
+    const int s = blockIdx.y;
+    if (s >= S) return;
+    const int P = PQ[2 * s], Q = PQ[2 * s + 1];
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (P + 1) * (Q + 1)) return;
+    const int p = g / (Q + 1), r = g % (Q + 1);
+    const double* qs = q + gbase[s];
+    double d = qs[g];
+    if (p > 0) d -= qs[g - (Q + 1)];
+    if (r > 0) d -= qs[g - 1];
+    if (p > 0 && r > 0) d += qs[g - (Q + 1) - 1];
+    dq[gbase[s] + g] = d;
+}
+
+// ------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------
+#define LAUNCH_CHECK() (hipGetLastError())
+
+hipError_t launch_field(const FieldArgs& A, int nsamples, const int32_t* samples, const SampleBase* bases,
+                        const double* xi, double* kx, double* ky, float* kx32, float* ky32, hipStream_t st)
+{
+    const int fw = A.kind_faces == 0 ? A.nx + 1 : A.nx, fh = A.kind_faces == 0 ? A.ny : A.ny + 1;
+    const int tiles = ((fw + kFieldTI - 1) / kFieldTI) * ((fh + kFieldTJ - 1) / kFieldTJ);
+    const size_t lds = sizeof(double) * ((size_t)A.Mx * A.My + (size_t)A.Mx * kFieldTI + (size_t)A.Mx * kFieldTJ);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_field, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_field, dim3(tiles, nsamples), dim3(kBlock), lds, st, A, samples, bases, xi, kx, ky, kx32, ky32);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_chol(int S, int c, const SampleBase* bases, const double* kx, const double* ky, double* chol,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_chol, dim3(S), dim3(64), sizeof(double) * c * c * c * c, st, S, c, bases, kx, ky, chol);
+    return LAUNCH_CHECK();
+}
+
+static dim3 level_grid(const KLevel& L, int K) { return dim3((unsigned)((int64_t)L.ntiles * K)); }
+
+template <typename T>
+hipError_t launch_rbgs(int ns, const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
+                       const T* Vin, T* Vout, const T* B, const T* KX, const T* KY, hipStream_t st)
+{
+    if (ns == 1)
+        hipLaunchKernelGGL((k_rbgs<T, 1>), level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, Vin, Vout, B, KX, KY);
+    else
+        hipLaunchKernelGGL((k_rbgs<T, 2>), level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, Vin, Vout, B, KX, KY);
+    return LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t launch_restrict(bool rhs, const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
+                           const T* Vf, T* Vc, T* B, const T* KX, const T* KY, hipStream_t st)
+{
+    if (rhs)
+        hipLaunchKernelGGL((k_restrict<T, true>), level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, Vf, Vc, B, KX, KY);
+    else
+        hipLaunchKernelGGL((k_restrict<T, false>), level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, Vf, Vc, B, KX, KY);
+    return LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, T omega,
+                          const T* Vc, T* Vf, const T* KX, const T* KY, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_prolong<T>), level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, omega, Vc, Vf, KX, KY);
+    return LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t launch_tail(const KTail& TL, size_t lds_bytes, int K, const KProb* probs, const int32_t* active, int c,
+                       int mu, int nu1, int nu2, T omega, int count, T* V, T* B, const T* KX, const T* KY,
+                       const double* chol, hipStream_t st)
+{
+    if (lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_tail<T>), dim3(K), dim3(kBlock), lds_bytes, st, TL, probs, active, c, mu, nu1, nu2, omega,
+                       count, V, B, KX, KY, chol);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_fmg(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, double* V, double* B,
+                      const double* U, const double* BP, const double* KX, const double* KY, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fmg, level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, V, B, U, BP, KX, KY);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_resnorm(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, const double* V,
+                          const double* B, const double* KX, const double* KY, double* part, float* V32, float* B32,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_resnorm, level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, V, B, KX, KY, part, V32, B32);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_converge(int K, int ntiles, const KProb* probs, int32_t* active, int32_t* pcycles,
+                           int32_t* dead_level, int32_t* status, const double* part, double tol, int max_cycles,
+                           int level, int32_t* n_active, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_converge, dim3(K), dim3(64), 0, st, K, ntiles, probs, active, pcycles, dead_level, status, part,
+                       tol, max_cycles, level, n_active);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_ir_update(const KLevel& L, int K, const KProb* probs, const int32_t* active, double* V,
+                            const float* V32, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ir_update, level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, V, V32);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_snapshot(const KLevel& L, int K, const KProb* probs, const int32_t* dead_level, int level, int c,
+                           const double* V, double* U, double* part, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_snapshot, level_grid(L, K), dim3(kBlock), 0, st, L, probs, dead_level, level, c, V, U, part);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_qreduce(int K, int ntiles, int64_t cells, const KProb* probs, const int32_t* pcycles,
+                          const int64_t* grid_base, const double* part, double* q_out, int32_t* cycles_out,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_qreduce, dim3(K), dim3(64), 0, st, K, ntiles, cells, probs, pcycles, grid_base, part, q_out,
+                       cycles_out);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_rhs_top(const KLevel& L, int K, const KProb* probs, double* BP, const double* rhs,
+                          const int64_t* rhs_base, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rhs_top, level_grid(L, K), dim3(kBlock), 0, st, L, probs, BP, rhs, rhs_base);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_activate(int K, const KProb* probs, const int32_t* dead_level, int level, int32_t* active,
+                           int32_t* pcycles, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_activate, dim3((K + kBlock - 1) / kBlock), dim3(kBlock), 0, st, K, probs, dead_level, level,
+                       active, pcycles);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_delta_q(int S, int max_grids, const int32_t* PQ, const int64_t* gbase, const double* q, double* dq,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_delta_q, dim3((max_grids + kBlock - 1) / kBlock, S), dim3(kBlock), 0, st, S, PQ, gbase, q, dq);
+    return LAUNCH_CHECK();
+}
+
+template hipError_t launch_rbgs<double>(int, const KLevel&, int, const KProb*, const int32_t*, int, const double*,
+                                        double*, const double*, const double*, const double*, hipStream_t);
+template hipError_t launch_rbgs<float>(int, const KLevel&, int, const KProb*, const int32_t*, int, const float*,
+                                       float*, const float*, const float*, const float*, hipStream_t);
+template hipError_t launch_restrict<double>(bool, const KLevel&, int, const KProb*, const int32_t*, int,
+                                            const double*, double*, double*, const double*, const double*,
+                                            hipStream_t);
+template hipError_t launch_restrict<float>(bool, const KLevel&, int, const KProb*, const int32_t*, int, const float*,
+                                           float*, float*, const float*, const float*, hipStream_t);
+template hipError_t launch_prolong<double>(const KLevel&, int, const KProb*, const int32_t*, int, double,
+                                           const double*, double*, const double*, const double*, hipStream_t);
+template hipError_t launch_prolong<float>(const KLevel&, int, const KProb*, const int32_t*, int, float, const float*,
+                                          float*, const float*, const float*, hipStream_t);
+template hipError_t launch_tail<double>(const KTail&, size_t, int, const KProb*, const int32_t*, int, int, int, int,
+                                        double, int, double*, double*, const double*, const double*, const double*,
+                                        hipStream_t);
+template hipError_t launch_tail<float>(const KTail&, size_t, int, const KProb*, const int32_t*, int, int, int, int,
+                                       float, int, float*, float*, const float*, const float*, const double*,
+                                       hipStream_t);
+
+}  // namespace msg

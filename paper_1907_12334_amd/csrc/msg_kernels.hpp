@@ -1,0 +1,71 @@
+// msg_kernels.hpp -- launch wrappers of the HIP kernels (msg_kernels.hip),
+// called by the host scheduler (msg_host.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "msg_device.hpp"
+
+namespace msg {
+
+enum { MSG_ST_CONVERGED = 0, MSG_ST_MAXITER = 1, MSG_ST_NONFINITE = 2 };
+
+// where a sample's arrays start, and its rectangle
+struct SampleBase {
+    int64_t fx, fy;        // first x-face / y-face
+    int32_t P, Q;
+};
+
+// one launch of the field synthesis: one face kind of one grid (p,q) for a
+// list of samples sharing that grid
+struct FieldArgs {
+    int32_t kind;          // 0: cosine table, 1: separable squared-exponential
+    int32_t n_terms;       // xi values per sample
+    int32_t Mx, My;        // coefficient matrix C[Mx][My] of cos(pi m x) cos(pi n y)
+    int32_t c, p, q, nx, ny;
+    int32_t kind_faces;    // 0: x-faces, 1: y-faces
+    double sigma;
+    double lamx[kMaxModes], lamy[kMaxModes];
+    KCosTable cos;
+};
+
+hipError_t launch_field(const FieldArgs& A, int nsamples, const int32_t* samples, const SampleBase* bases,
+                        const double* xi, double* kx, double* ky, float* kx32, float* ky32, hipStream_t st);
+hipError_t launch_chol(int S, int c, const SampleBase* bases, const double* kx, const double* ky, double* chol,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_rbgs(int ns, const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
+                       const T* Vin, T* Vout, const T* B, const T* KX, const T* KY, hipStream_t st);
+template <typename T>
+hipError_t launch_restrict(bool rhs, const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
+                           const T* Vf, T* Vc, T* B, const T* KX, const T* KY, hipStream_t st);
+template <typename T>
+hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, T omega,
+                          const T* Vc, T* Vf, const T* KX, const T* KY, hipStream_t st);
+template <typename T>
+hipError_t launch_tail(const KTail& TL, size_t lds_bytes, int K, const KProb* probs, const int32_t* active, int c,
+                       int mu, int nu1, int nu2, T omega, int count, T* V, T* B, const T* KX, const T* KY,
+                       const double* chol, hipStream_t st);
+hipError_t launch_fmg(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, double* V, double* B,
+                      const double* U, const double* BP, const double* KX, const double* KY, hipStream_t st);
+hipError_t launch_resnorm(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, const double* V,
+                          const double* B, const double* KX, const double* KY, double* part, float* V32, float* B32,
+                          hipStream_t st);
+hipError_t launch_converge(int K, int ntiles, const KProb* probs, int32_t* active, int32_t* pcycles,
+                           int32_t* dead_level, int32_t* status, const double* part, double tol, int max_cycles,
+                           int level, int32_t* n_active, hipStream_t st);
+hipError_t launch_ir_update(const KLevel& L, int K, const KProb* probs, const int32_t* active, double* V,
+                            const float* V32, hipStream_t st);
+hipError_t launch_snapshot(const KLevel& L, int K, const KProb* probs, const int32_t* dead_level, int level, int c,
+                           const double* V, double* U, double* part, hipStream_t st);
+hipError_t launch_qreduce(int K, int ntiles, int64_t cells, const KProb* probs, const int32_t* pcycles,
+                          const int64_t* grid_base, const double* part, double* q_out, int32_t* cycles_out,
+                          hipStream_t st);
+hipError_t launch_rhs_top(const KLevel& L, int K, const KProb* probs, double* BP, const double* rhs,
+                          const int64_t* rhs_base, hipStream_t st);
+hipError_t launch_delta_q(int S, int max_grids, const int32_t* PQ, const int64_t* gbase, const double* q, double* dq,
+                          hipStream_t st);
+hipError_t launch_activate(int K, const KProb* probs, const int32_t* dead_level, int level, int32_t* active,
+                           int32_t* pcycles, hipStream_t st);
+
+}  // namespace msg

@@ -80,6 +80,7 @@ class Workload:
     precision: str = "fp64"     # "fp64" or "mixed"
     ir_tol: float = 1e-8
     seed: int = BASE_SEED
+    max_cycles: int = 50        # cap per grid; strongly anisotropic fields need more on tiny coarse grids
 
     @property
     def n_samples(self) -> int:
@@ -102,7 +103,8 @@ def config(k: int) -> Workload:
     if k == 1:   # 16 samples, finest 32x32 with 4x4 coarsest, KL-10, FP64, W(2,2) to 1e-10
         return uniform("kl10-32x32-s16", 4, 3, 3, 16, KL10, seed=BASE_SEED + 1)
     if k == 2:   # 4096 samples, finest 256x256, 2x2 coarsest (64 grids), separable SE 50x50
-        return uniform("se-256x256-s4096", 2, 7, 7, 4096, separable(0.3, 0.03, 1.0), seed=BASE_SEED + 2)
+        return uniform("se-256x256-s4096", 2, 7, 7, 4096, separable(0.3, 0.03, 1.0), seed=BASE_SEED + 2,
+                       max_cycles=1000)
     if k == 3:   # ragged MIMC index set l1+l2 <= 8, N_l = 8192 * 2^-(l1+l2), at least 16
         P, Q = [], []
         for l1 in range(9):
@@ -113,7 +115,7 @@ def config(k: int) -> Workload:
         return Workload("kl10-ragged-l1+l2<=8", 4, P, Q, KL10, seed=BASE_SEED + 3)
     if k == 4:   # 1024 samples, finest 1024x64, strong anisotropy, mixed precision
         return uniform("se-1024x64-s1024-mixed", 4, 8, 4, 1024, separable(1.0, 0.01, 2.0),
-                       precision="mixed", ir_tol=1e-8, seed=BASE_SEED + 4)
+                       precision="mixed", ir_tol=1e-8, seed=BASE_SEED + 4, max_cycles=1000)
     raise ValueError(f"no workload preset {k}")
 
 

@@ -1,0 +1,268 @@
+"""ctypes binding of ``libmsg.so`` (C-ABI of include/msg.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+PyTorch supplies device memory and the stream.  A missing library is an
+error; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmsg.so")
+
+MSG_OK, MSG_ERR_ARG, MSG_ERR_LAYOUT, MSG_ERR_WORKSPACE, MSG_ERR_HIP, MSG_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+SAMPLE_CONVERGED, SAMPLE_MAXITER, SAMPLE_NONFINITE = 0, 1, 2
+FIELD_COS_TABLE, FIELD_SEPARABLE_SE = 0, 1
+FP64, MIXED = 0, 1
+
+EXPORTS = ("msg_default_opts", "msg_create", "msg_destroy", "msg_last_error", "msg_layout",
+           "msg_workspace_size", "msg_sample_field", "msg_solve_batch", "mimc_delta_q",
+           "msg_set_profiling", "msg_get_profile")
+KERNEL_SMOOTH, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_TAIL, KERNEL_RESIDUAL_NORM = range(5)
+KERNEL_NAMES = ("smooth", "restrict", "prolong", "tail", "residual_norm")
+
+
+class MsgError(RuntimeError):
+    def __init__(self, code, where, detail):
+        super().__init__(f"{where} failed ({code}): {detail}")
+        self.code = code
+
+
+class FieldSpecC(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_terms", ctypes.c_int32),
+                ("a", ctypes.POINTER(ctypes.c_int32)), ("b", ctypes.POINTER(ctypes.c_int32)),
+                ("amp", ctypes.POINTER(ctypes.c_double)),
+                ("mx", ctypes.c_int32), ("my", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("sigma2", ctypes.c_double)]
+
+
+class BatchDescC(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int32), ("c", ctypes.c_int32),
+                ("P", ctypes.POINTER(ctypes.c_int32)), ("Q", ctypes.POINTER(ctypes.c_int32))]
+
+
+class KernelStatsC(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("milliseconds", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class SolveOptsC(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
+                ("max_cycles", ctypes.c_int32), ("tol", ctypes.c_double), ("omega", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("tail_levels", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+        L.msg_default_opts.argtypes = [ctypes.POINTER(SolveOptsC)]
+        L.msg_default_opts.restype = None
+        L.msg_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.msg_destroy.argtypes = [vp]
+        L.msg_destroy.restype = None
+        L.msg_last_error.restype = ctypes.c_char_p
+        L.msg_layout.argtypes = [ctypes.POINTER(BatchDescC), i64p, i64p, i64p, i64p]
+        L.msg_workspace_size.argtypes = [vp, ctypes.POINTER(BatchDescC), ctypes.POINTER(SolveOptsC),
+                                         ctypes.POINTER(ctypes.c_size_t)]
+        L.msg_sample_field.argtypes = [vp, ctypes.POINTER(FieldSpecC), ctypes.POINTER(BatchDescC),
+                                       vp, vp, vp, vp, vp, vp]
+        L.msg_solve_batch.argtypes = [vp, ctypes.POINTER(BatchDescC), ctypes.POINTER(SolveOptsC),
+                                      vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.mimc_delta_q.argtypes = [ctypes.POINTER(BatchDescC), vp, vp, vp]
+        L.msg_set_profiling.argtypes = [vp, ctypes.c_int]
+        L.msg_get_profile.argtypes = [vp, ctypes.c_int, ctypes.POINTER(KernelStatsC)]
+        for n in ("msg_create", "msg_layout", "msg_workspace_size", "msg_sample_field", "msg_solve_batch",
+                  "mimc_delta_q", "msg_set_profiling", "msg_get_profile"):
+            getattr(L, n).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().msg_last_error().decode()
+
+
+def _check(code, where):
+    if code != MSG_OK:
+        raise MsgError(code, where, last_error())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------- descriptors
+class Batch:
+    """A batch descriptor: coarsest cells c and per-sample finest (P, Q)."""
+
+    def __init__(self, c: int, P: Sequence[int], Q: Sequence[int]):
+        self.c = int(c)
+        self.P = np.ascontiguousarray(P, dtype=np.int32)
+        self.Q = np.ascontiguousarray(Q, dtype=np.int32)
+        if self.P.shape != self.Q.shape or self.P.ndim != 1:
+            raise ValueError("P and Q must be 1-D and of equal length")
+        self.c_struct = BatchDescC(len(self.P), self.c,
+                                   self.P.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   self.Q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+
+    @property
+    def n(self):
+        return len(self.P)
+
+    def layout(self):
+        n = self.n + 1
+        cell, xf, yf, grid = (np.zeros(n, dtype=np.int64) for _ in range(4))
+        p = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        _check(lib().msg_layout(ctypes.byref(self.c_struct), p(cell), p(xf), p(yf), p(grid)), "msg_layout")
+        return {"cell": cell, "xface": xf, "yface": yf, "grid": grid}
+
+
+@dataclasses.dataclass
+class SolveOpts:
+    mu: int = 2
+    nu1: int = 2
+    nu2: int = 2
+    max_cycles: int = 50
+    tol: float = 1e-10
+    omega: float = 1.0
+    precision: int = FP64
+    tail_levels: int = -1
+
+    def c_struct(self):
+        return SolveOptsC(self.mu, self.nu1, self.nu2, self.max_cycles, self.tol, self.omega, self.precision,
+                          self.tail_levels)
+
+
+def default_opts() -> SolveOpts:
+    o = SolveOptsC()
+    lib().msg_default_opts(ctypes.byref(o))
+    return SolveOpts(o.mu, o.nu1, o.nu2, o.max_cycles, o.tol, o.omega, o.precision, o.tail_levels)
+
+
+class FieldSpec:
+    """msg_field_spec from an inputs.FieldSpec-like object."""
+
+    def __init__(self, spec):
+        self._keep = []
+        if spec.kind == "cos":
+            a = np.ascontiguousarray(spec.a, dtype=np.int32)
+            b = np.ascontiguousarray(spec.b, dtype=np.int32)
+            amp = np.ascontiguousarray(spec.amp, dtype=np.float64)
+            self._keep = [a, b, amp]
+            self.c_struct = FieldSpecC(FIELD_COS_TABLE, len(a), a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       amp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0, 0, 0.0, 0.0, 0.0)
+        else:
+            self.c_struct = FieldSpecC(FIELD_SEPARABLE_SE, spec.mx * spec.my, None, None, None, spec.mx, spec.my,
+                                       spec.lx, spec.ly, spec.sigma2)
+
+
+def workspace_size(batch: Batch, opts: SolveOpts, handle=None) -> int:
+    n = ctypes.c_size_t(0)
+    o = opts.c_struct()
+    _check(lib().msg_workspace_size(handle, ctypes.byref(batch.c_struct), ctypes.byref(o), ctypes.byref(n)),
+           "msg_workspace_size")
+    return n.value
+
+
+class Handle:
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().msg_create(ctypes.byref(h), device), "msg_create")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().msg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_profiling(self, on: bool):
+        _check(lib().msg_set_profiling(self.h, int(bool(on))), "msg_set_profiling")
+
+    def profile(self):
+        """{kernel name: (launches, milliseconds, algorithmic bytes)}"""
+        out = {}
+        for k, name in enumerate(KERNEL_NAMES):
+            st = KernelStatsC()
+            _check(lib().msg_get_profile(self.h, k, ctypes.byref(st)), "msg_get_profile")
+            out[name] = (st.launches, st.milliseconds, st.bytes)
+        return out
+
+    # ---- raw entry points (device tensors in, device tensors out)
+    def sample_field(self, spec: FieldSpec, batch: Batch, xi, kx, ky, kx32=None, ky32=None, stream=None):
+        _check(lib().msg_sample_field(self.h, ctypes.byref(spec.c_struct), ctypes.byref(batch.c_struct), _ptr(xi),
+                                      _ptr(kx), _ptr(ky), _ptr(kx32), _ptr(ky32), _stream(stream)),
+               "msg_sample_field")
+
+    def solve_batch(self, batch: Batch, opts: SolveOpts, kx, ky, kx32, ky32, rhs, u, q, status, cycles, ws,
+                    stream=None):
+        o = opts.c_struct()
+        _check(lib().msg_solve_batch(self.h, ctypes.byref(batch.c_struct), ctypes.byref(o), _ptr(kx), _ptr(ky),
+                                     _ptr(kx32), _ptr(ky32), _ptr(rhs), _ptr(u), _ptr(q), _ptr(status),
+                                     _ptr(cycles), _ptr(ws), ws.numel() * ws.element_size() if ws is not None else 0,
+                                     _stream(stream)),
+               "msg_solve_batch")
+
+
+def delta_q(batch: Batch, q, dq, stream=None):
+    _check(lib().mimc_delta_q(ctypes.byref(batch.c_struct), _ptr(q), _ptr(dq), _stream(stream)), "mimc_delta_q")
+
+
+# ---------------------------------------------------------------- convenience
+class Buffers:
+    """Device buffers of one batch: fields, outputs and workspace (torch)."""
+
+    def __init__(self, batch: Batch, opts: SolveOpts, device="cuda:0", mixed_fields=None):
+        import torch
+        lay = batch.layout()
+        self.layout = lay
+        dev = torch.device(device)
+        mixed = opts.precision == MIXED if mixed_fields is None else mixed_fields
+        self.kx = torch.empty(int(lay["xface"][-1]), dtype=torch.float64, device=dev)
+        self.ky = torch.empty(int(lay["yface"][-1]), dtype=torch.float64, device=dev)
+        self.kx32 = torch.empty(int(lay["xface"][-1]), dtype=torch.float32, device=dev) if mixed else None
+        self.ky32 = torch.empty(int(lay["yface"][-1]), dtype=torch.float32, device=dev) if mixed else None
+        self.u = torch.empty(int(lay["cell"][-1]), dtype=torch.float64, device=dev)
+        self.q = torch.empty(int(lay["grid"][-1]), dtype=torch.float64, device=dev)
+        self.dq = torch.empty(int(lay["grid"][-1]), dtype=torch.float64, device=dev)
+        self.cycles = torch.empty(int(lay["grid"][-1]), dtype=torch.int32, device=dev)
+        self.status = torch.empty(batch.n, dtype=torch.int32, device=dev)
+        nbytes = workspace_size(batch, opts)
+        self.ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=dev)
+
+
+def run(handle: Handle, spec, batch: Batch, opts: SolveOpts, xi, bufs: Optional[Buffers] = None, rhs=None,
+        stream=None, field=True):
+    """Field synthesis, full-MSG solve of every sample, multi-index differences."""
+    bufs = bufs or Buffers(batch, opts)
+    if field:
+        handle.sample_field(FieldSpec(spec), batch, xi, bufs.kx, bufs.ky, bufs.kx32, bufs.ky32, stream)
+    handle.solve_batch(batch, opts, bufs.kx, bufs.ky, bufs.kx32, bufs.ky32, rhs, bufs.u, bufs.q, bufs.status,
+                       bufs.cycles, bufs.ws, stream)
+    delta_q(batch, bufs.q, bufs.dq, stream)
+    return bufs

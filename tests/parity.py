@@ -1,0 +1,77 @@
+"""Run the HIP path (through the C-ABI) and the oracle on the same seeded
+inputs and compare them grid by grid (test helper)."""
+import numpy as np
+
+from oracle import binding as O
+from paper_1907_12334_amd import inputs as I
+from paper_1907_12334_amd import msg
+
+
+def gpu_solve(c, P, Q, spec, xi, opts, rhs=None, handle=None):
+    import torch
+    h = handle or msg.Handle(0)
+    b = msg.Batch(c, P, Q)
+    bufs = msg.Buffers(b, opts)
+    xi_d = torch.tensor(np.ascontiguousarray(xi), dtype=torch.float64, device="cuda:0")
+    rhs_d = torch.tensor(rhs, dtype=torch.float64, device="cuda:0") if rhs is not None else None
+    msg.run(h, spec, b, opts, xi_d, bufs, rhs=rhs_d)
+    torch.cuda.synchronize()
+    out = {k: getattr(bufs, k).cpu().numpy() for k in ("kx", "ky", "u", "q", "dq", "cycles", "status")}
+    out["layout"] = bufs.layout
+    return out
+
+
+def per_sample(out, s):
+    lay = out["layout"]
+    return {
+        "u": out["u"][lay["cell"][s]:lay["cell"][s + 1]],
+        "q": out["q"][lay["grid"][s]:lay["grid"][s + 1]],
+        "dq": out["dq"][lay["grid"][s]:lay["grid"][s + 1]],
+        "cycles": out["cycles"][lay["grid"][s]:lay["grid"][s + 1]],
+        "kx": out["kx"][lay["xface"][s]:lay["xface"][s + 1]],
+        "ky": out["ky"][lay["yface"][s]:lay["yface"][s + 1]],
+        "status": int(out["status"][s]),
+    }
+
+
+def oracle_solve(c, P, Q, spec, xi, tol=1e-10, max_cycles=50, forced=None, rhs=None, omega=1.0):
+    kx, ky = O.hierarchy_field(c, P, Q, spec.as_dict(), xi)
+    r = O.fmsg_solve(c, P, Q, kx, ky, O.opts(tol=tol, max_cycles=max_cycles, omega=omega), rhs_top=rhs,
+                     forced_cycles=forced)
+    r["kx"], r["ky"] = kx, ky
+    r["dq"] = O.delta_q(P, Q, r["q"])
+    return r
+
+
+def grid_errors(c, P, Q, u_gpu, u_ora):
+    """max over grids of ||u_gpu - u_ora||_2 / ||u_ora||_2"""
+    G = O.split_cells(u_gpu, c, P, Q)
+    R = O.split_cells(u_ora, c, P, Q)
+    worst = 0.0
+    for key in R:
+        d = np.linalg.norm(G[key] - R[key]) / max(np.linalg.norm(R[key]), 1e-300)
+        worst = max(worst, d)
+    return worst
+
+
+def compare_sample(c, P, Q, spec, xi, g, tol=1e-10, max_cycles=50, rhs=None, omega=1.0):
+    """Oracle on the same inputs; where a per-grid cycle count differs (a tie
+    at the tolerance), the oracle is rerun at the GPU's counts so iterates are
+    compared at equal counts.  Returns (u_err, q_err, dq_err, oracle result);
+    the oracle's status is always that of its own adaptive run."""
+    ora = oracle_solve(c, P, Q, spec, xi, tol=tol, max_cycles=max_cycles, rhs=rhs, omega=omega)
+    if not np.array_equal(ora["cycles"], g["cycles"]):
+        status = ora["status"]
+        ora = oracle_solve(c, P, Q, spec, xi, tol=tol, max_cycles=max_cycles, forced=g["cycles"], rhs=rhs,
+                           omega=omega)
+        ora["status"] = status
+    eu = grid_errors(c, P, Q, g["u"], ora["u"])
+    eq = np.max(np.abs(g["q"] - ora["q"]) / np.maximum(np.abs(ora["q"]), 1e-300))
+    # differences are compared against the size of the four quantities they combine
+    qm = ora["q"].reshape(P + 1, Q + 1)
+    scale = np.abs(qm).copy()
+    scale[1:, :] = np.maximum(scale[1:, :], np.abs(qm[:-1, :]))
+    scale[:, 1:] = np.maximum(scale[:, 1:], np.abs(qm[:, :-1]))
+    scale[1:, 1:] = np.maximum(scale[1:, 1:], np.abs(qm[:-1, :-1]))
+    edq = np.max(np.abs(g["dq"] - ora["dq"]) / np.maximum(scale.ravel(), 1e-300))
+    return eu, eq, edq, ora

@@ -1,0 +1,107 @@
+"""Host-side checks of the C-ABI: the library loads, exports every function
+include/msg.h declares, computes the documented layout, and rejects bad
+arguments before touching a device.  No kernel runs here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1907_12334_amd import msg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "msg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(msg_[a-z_]+|mimc_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_function():
+    names = declared_functions()
+    assert set(names) == set(msg.EXPORTS)
+    L = msg.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _independent_layout(c, P, Q):
+    cell = [0]
+    xf = [0]
+    yf = [0]
+    grid = [0]
+    for p_, q_ in zip(P, Q):
+        ncell = nxf = nyf = 0
+        for a in range(p_ + 1):
+            for b in range(q_ + 1):
+                nx, ny = c << a, c << b
+                ncell += nx * ny
+                nxf += (nx + 1) * ny
+                nyf += nx * (ny + 1)
+        cell.append(cell[-1] + ncell)
+        xf.append(xf[-1] + nxf)
+        yf.append(yf[-1] + nyf)
+        grid.append(grid[-1] + (p_ + 1) * (q_ + 1))
+    return cell, xf, yf, grid
+
+
+@pytest.mark.parametrize("c", [1, 2, 4, 3])
+def test_layout_matches_definition(c):
+    rng = np.random.default_rng(c)
+    P = rng.integers(0, 7, size=23)
+    Q = rng.integers(0, 7, size=23)
+    lay = msg.Batch(c, P, Q).layout()
+    cell, xf, yf, grid = _independent_layout(c, P.tolist(), Q.tolist())
+    assert lay["cell"].tolist() == cell
+    assert lay["xface"].tolist() == xf
+    assert lay["yface"].tolist() == yf
+    assert lay["grid"].tolist() == grid
+
+
+def test_bad_batches_are_rejected():
+    for c, P, Q, code in [(0, [1], [1], msg.MSG_ERR_LAYOUT), (9, [1], [1], msg.MSG_ERR_LAYOUT),
+                          (4, [15], [0], msg.MSG_ERR_LAYOUT), (4, [-1], [0], msg.MSG_ERR_LAYOUT),
+                          (8, [13], [0], msg.MSG_ERR_LAYOUT)]:
+        with pytest.raises(msg.MsgError) as e:
+            msg.Batch(c, P, Q).layout()
+        assert e.value.code == code
+        assert msg.last_error()
+
+
+def test_workspace_size_and_options():
+    o = msg.default_opts()
+    assert (o.mu, o.nu1, o.nu2, o.max_cycles, o.tol, o.omega, o.precision) == (2, 2, 2, 50, 1e-10, 1.0, msg.FP64)
+    b = msg.Batch(4, [3] * 8, [3] * 8)
+    n64 = msg.workspace_size(b, o)
+    om = msg.SolveOpts(precision=msg.MIXED)
+    assert msg.workspace_size(b, om) > n64 > 0
+    assert msg.workspace_size(msg.Batch(4, [3] * 16, [3] * 16), o) > n64
+    with pytest.raises(msg.MsgError):
+        msg.workspace_size(b, msg.SolveOpts(mu=0))
+    with pytest.raises(msg.MsgError):
+        msg.workspace_size(b, msg.SolveOpts(tail_levels=9))
+
+
+def test_entry_points_reject_null_handle_without_device_work():
+    b = msg.Batch(4, [1], [1])
+    o = msg.SolveOpts().c_struct()
+    L = msg.lib()
+    code = L.msg_solve_batch(None, ctypes.byref(b.c_struct), ctypes.byref(o), *([None] * 10), 0, None)
+    assert code == msg.MSG_ERR_ARG
+    spec = msg.FieldSpec(type("S", (), {"kind": "cos", "a": [0], "b": [0], "amp": [1.0]})())
+    code = L.msg_sample_field(None, ctypes.byref(spec.c_struct), ctypes.byref(b.c_struct), *([None] * 6))
+    assert code == msg.MSG_ERR_ARG
+    code = L.mimc_delta_q(ctypes.byref(b.c_struct), None, None, None)
+    assert code == msg.MSG_ERR_ARG
+
+
+def test_create_reports_missing_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    code = msg.lib().msg_create(ctypes.byref(h), 0)
+    assert code in (msg.MSG_ERR_HIP, msg.MSG_ERR_ARG)
+    assert msg.last_error()

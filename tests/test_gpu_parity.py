@@ -1,0 +1,184 @@
+"""HIP path (through the C-ABI) against the oracle on the same seeded inputs.
+
+FP64 bar: per grid ||u_gpu - u_oracle||_2 / ||u_oracle||_2 <= 1e-10, Q within
+1e-10 relative, Delta Q within 1e-10 of the largest |Q| it combines, with the
+oracle run at the GPU's per-grid cycle counts (a tie at the tolerance may
+change a count by one; the iterates are then compared at equal counts).
+Mixed precision: the same quantities within 1e-8 of the FP64 oracle run to
+1e-10.
+"""
+import numpy as np
+import pytest
+
+from oracle import binding as O
+from paper_1907_12334_amd import inputs as I
+from paper_1907_12334_amd import msg
+
+from . import parity as PR
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def handle():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return msg.Handle(0)
+
+
+def _check_batch(handle, c, P, Q, spec, opts, seed=I.BASE_SEED, tol=FP64_TOL, ids=None, xi=None):
+    xi = I.draw_xi(spec.n_terms, range(len(P)), seed) if xi is None else xi
+    out = PR.gpu_solve(c, P, Q, spec, xi, opts, handle=handle)
+    ids = range(len(P)) if ids is None else ids
+    worst = 0.0
+    for s in ids:
+        g = PR.per_sample(out, s)
+        eu, eq, edq, ora = PR.compare_sample(c, int(P[s]), int(Q[s]), spec, xi[s], g, tol=opts.tol,
+                                             max_cycles=opts.max_cycles, omega=opts.omega)
+        assert g["status"] == ora["status"], (s, g["status"], ora["status"])
+        assert eu <= tol and eq <= tol and edq <= tol, (s, eu, eq, edq)
+        worst = max(worst, eu)
+    return out, worst
+
+
+def test_field_matches_oracle(handle):
+    for spec, c, P, Q in [(I.KL10, 4, 3, 2), (I.separable(0.3, 0.03, 1.0, m=20), 2, 4, 5)]:
+        xi = I.draw_xi(spec.n_terms, range(3))
+        out = PR.gpu_solve(c, [P] * 3, [Q] * 3, spec, xi, msg.SolveOpts(max_cycles=0), handle=handle)
+        for s in range(3):
+            g = PR.per_sample(out, s)
+            kx, ky = O.hierarchy_field(c, P, Q, spec.as_dict(), xi[s])
+            assert np.max(np.abs(g["kx"] / kx - 1)) <= 1e-13
+            assert np.max(np.abs(g["ky"] / ky - 1)) <= 1e-13
+
+
+def test_config1_all_samples(handle):
+    w = I.config(1)
+    out, worst = _check_batch(handle, w.c, w.P, w.Q, w.field, msg.SolveOpts(), seed=w.seed)
+    assert np.all(out["status"] == 0)
+
+
+@pytest.mark.parametrize("max_cycles", [0, 1, 2])
+def test_unconverged_iterates_match_step_by_step(handle, max_cycles):
+    """Cycle caps of 0, 1, 2 stop every grid early, so the returned iterates
+    expose the nested-iteration guess and single cycles, not just the
+    converged solution."""
+    opts = msg.SolveOpts(max_cycles=max_cycles)
+    for c, P, Q, spec in [(4, 3, 3, I.KL10), (2, 4, 3, I.separable(0.3, 0.03, 1.0, m=10))]:
+        _check_batch(handle, c, [P] * 3, [Q] * 3, spec, opts, tol=1e-12)
+
+
+@pytest.mark.parametrize("fields", ["kl10", "se"])
+def test_multi_tile_grids_step_by_step(handle, fields):
+    """Grids wider and taller than one smoother tile (128x64 and 16x256 finest
+    grids, every level on the batched kernels with tail_levels = 0, then with
+    the automatic tail) after one and two cycles."""
+    spec = I.KL10 if fields == "kl10" else I.separable(0.3, 0.03, 1.0, m=10)
+    for tail in (0, -1):
+        for mc in (1, 2):
+            opts = msg.SolveOpts(max_cycles=mc, tail_levels=tail)
+            _check_batch(handle, 4, [5, 2], [4, 6], spec, opts, tol=1e-12)
+
+
+@pytest.mark.parametrize("tail", [0, 1, 3, -1])
+def test_tail_depth_does_not_change_results(handle, tail):
+    c, P, Q, spec = 2, 4, 4, I.KL10
+    opts = msg.SolveOpts(tail_levels=tail, max_cycles=2)
+    _check_batch(handle, c, [P] * 2, [Q] * 2, spec, opts, tol=1e-12)
+
+
+def test_ragged_batch_and_batch_invariance(handle):
+    rng = np.random.default_rng(5)
+    P = rng.integers(0, 5, size=12)
+    Q = rng.integers(0, 5, size=12)
+    P[0], Q[0] = 0, 0
+    P[1], Q[1] = 5, 0
+    P[2], Q[2] = 0, 5
+    spec = I.KL10
+    xi = I.draw_xi(10, range(12))
+    out, _ = _check_batch(handle, 4, P, Q, spec, msg.SolveOpts(), xi=xi)
+    # the same sample alone gives the same bits
+    for s in (0, 3, 7):
+        alone = PR.gpu_solve(4, [P[s]], [Q[s]], spec, xi[s:s + 1], msg.SolveOpts(), handle=handle)
+        a = PR.per_sample(alone, 0)
+        b = PR.per_sample(out, s)
+        assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["q"], b["q"])
+        assert np.array_equal(a["cycles"], b["cycles"])
+
+
+def test_mixed_precision_against_fp64_oracle(handle):
+    c, P, Q = 4, 5, 2
+    spec = I.separable(1.0, 0.01, 2.0, m=20)
+    xi = I.draw_xi(spec.n_terms, range(4))
+    opts = msg.SolveOpts(precision=msg.MIXED, tol=1e-8, max_cycles=1000)
+    out = PR.gpu_solve(c, [P] * 4, [Q] * 4, spec, xi, opts, handle=handle)
+    for s in range(4):
+        g = PR.per_sample(out, s)
+        ora = PR.oracle_solve(c, P, Q, spec, xi[s], tol=1e-10, max_cycles=1000)
+        assert g["status"] == 0 and ora["status"] == 0
+        # coefficients in FP64 match; solutions within the mixed bar
+        assert PR.grid_errors(c, P, Q, g["u"], ora["u"]) <= MIXED_TOL
+        assert np.max(np.abs(g["q"] - ora["q"]) / np.abs(ora["q"])) <= MIXED_TOL
+
+
+def test_delta_q_on_device(handle):
+    import torch
+    b = msg.Batch(4, [2, 3, 0], [3, 1, 4])
+    n = int(b.layout()["grid"][-1])
+    q = torch.tensor(np.random.default_rng(3).standard_normal(n), dtype=torch.float64, device="cuda:0")
+    dq = torch.empty_like(q)
+    msg.delta_q(b, q, dq)
+    torch.cuda.synchronize()
+    qh, dqh = q.cpu().numpy(), dq.cpu().numpy()
+    lay = b.layout()["grid"]
+    for s, (P, Q) in enumerate(zip(b.P, b.Q)):
+        want = O.delta_q(int(P), int(Q), qh[lay[s]:lay[s + 1]])
+        assert np.allclose(dqh[lay[s]:lay[s + 1]], want, rtol=0, atol=1e-15)
+
+
+def test_failure_paths_are_per_sample(handle):
+    c, P, Q, spec = 4, 2, 2, I.KL10
+    xi = I.draw_xi(10, range(3))
+    xi[1, 4] = np.nan
+    out = PR.gpu_solve(c, [P] * 3, [Q] * 3, spec, xi, msg.SolveOpts(), handle=handle)
+    assert list(out["status"]) == [0, 2, 0]
+    bad = PR.per_sample(out, 1)
+    assert np.all(np.isnan(bad["u"])) and np.all(np.isnan(bad["q"]))
+    for s in (0, 2):
+        alone = PR.gpu_solve(c, [P], [Q], spec, xi[s:s + 1], msg.SolveOpts(), handle=handle)
+        assert np.array_equal(PR.per_sample(alone, 0)["u"], PR.per_sample(out, s)["u"])
+    capped = PR.gpu_solve(c, [P], [Q], spec, xi[:1], msg.SolveOpts(max_cycles=1), handle=handle)
+    assert int(capped["status"][0]) == 1
+
+
+def test_rhs_argument_manufactured_sine(handle):
+    """A caller right-hand side on the finest grid (sine, constant k): every
+    returned grid matches the oracle."""
+    c, P, Q = 4, 2, 3
+    spec = I.constant_field()
+    nx, ny = c << P, c << Q
+    X, Y = np.meshgrid((np.arange(nx) + 0.5) / nx, (np.arange(ny) + 0.5) / ny)
+    rhs = (2 * np.pi**2 * np.sin(np.pi * X) * np.sin(np.pi * Y)).ravel()
+    xi = np.zeros((1, 1))
+    out = PR.gpu_solve(c, [P], [Q], spec, xi, msg.SolveOpts(), rhs=rhs, handle=handle)
+    g = PR.per_sample(out, 0)
+    eu, eq, edq, _ = PR.compare_sample(c, P, Q, spec, xi[0], g, rhs=rhs)
+    assert eu <= FP64_TOL and eq <= FP64_TOL
+
+
+def test_full_size_config2_sampled(handle):
+    """The 256x256 (c = 2, 64 grids) separable field at full size in the
+    benchmark's launch shape, on a 32-sample slice: every sample converges,
+    and two sampled solves match the oracle grid by grid."""
+    w = I.config(2).subset(32)
+    xi = w.xi()
+    out = PR.gpu_solve(w.c, w.P, w.Q, w.field, xi, msg.SolveOpts(max_cycles=w.max_cycles), handle=handle)
+    assert np.all(out["status"] == 0)
+    for s in (0, 31):
+        g = PR.per_sample(out, s)
+        eu, eq, edq, _ = PR.compare_sample(w.c, 7, 7, w.field, xi[s], g, max_cycles=w.max_cycles)
+        assert eu <= FP64_TOL and eq <= FP64_TOL and edq <= FP64_TOL, (s, eu, eq, edq)
