@@ -81,6 +81,8 @@ struct KTailGrid {
     int64_t aoff;              // arena offset (used for the top level)
     int16_t cx, cy;            // tail index of child (p-1,q) / (p,q-1), -1 if none
     int16_t px, py;            // tail index of parent (p+1,q) / (p,q+1), -1 if none
+    int16_t sh;                // log2(nx) when nx is a power of two, else -1
+    int16_t pad[3];
 };
 
 struct KTail {

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -116,7 +117,9 @@ BatchLayout make_layout(const msg_batch_desc* b)
 
 // ---------------------------------------------------------------- plans
 int g_fuse = 2;              // smoother sweeps fused per pass (1 or 2)
-int g_tail_lds = 65536;      // LDS budget of the automatic tail choice
+int g_tail_lds = 20480;      // LDS budget of the W-cycle tail (sets its depth)
+int g_solve_lds = 65536;     // LDS budget under which a class is solved entirely in one kernel
+bool g_debug_stages = false; // per-level timing on stderr
 
 void rbgs_tile(int nx, int ny, int H, int& tw, int& th)
 {
@@ -133,6 +136,7 @@ void rbgs_tile(int nx, int ny, int H, int& tw, int& th)
 
 struct ClassPlan {
     int pc, qc, L;
+    int ci = 0;                    // index of the class inside its level
     int K = 0;
     int first = 0;                 // first problem of the class in the stage table
     int64_t arena = 0;             // arena offset of the class
@@ -141,6 +145,9 @@ struct ClassPlan {
     int tail_top = 0;
     KTail tail;
     size_t tail_lds = 0;
+    bool solve_in_tail = false;    // the whole adaptive level runs in one kernel (FP64)
+    KTail tail64;
+    size_t tail64_lds = 0;
     KLevel top1d;                  // the finest grid, 1-D tiles
     std::vector<KLevel> rb, pro, res;   // per level: smoother tiles, prolongation, restriction into level-1
     int64_t part0 = 0;             // first partial-sum slot
@@ -234,6 +241,7 @@ size_t tail_layout(int c, int pc, int qc, int m, const std::vector<int64_t>& gof
             G.ny = c << b;
             G.p = a;
             G.q = b;
+            G.sh = (G.nx & (G.nx - 1)) == 0 ? (int16_t)__builtin_ctz(G.nx) : (int16_t)-1;
             const int64_t n = (int64_t)G.nx * G.ny;
             G.lv = (int)off; off += n;
             G.lb = (int)off; off += n;
@@ -304,8 +312,17 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
             C.arena = SP.arena_cells;
             SP.K += C.K;
             SP.arena_cells += C.stride * C.K;
-            C.tail_top = o.precision == MSG_MIXED ? choose_tail<float>(c, pc, qc, L, o.tail_levels, C.goff)
-                                                   : choose_tail<double>(c, pc, qc, L, o.tail_levels, C.goff);
+            // classes whose whole rectangle fits in LDS run their adaptive
+            // cycles inside one FP64 kernel; the others cycle on the host
+            // down to a tail of levels 0..tail_top < L
+            const size_t b64 = L <= 8 ? tail_layout<double>(c, pc, qc, L, C.goff, C.tail64) : 0;
+            C.tail64_lds = b64;
+            if (o.tail_levels >= 0) C.solve_in_tail = L <= o.tail_levels && b64 > 0;
+            else C.solve_in_tail = b64 > 0 && b64 <= (size_t)g_solve_lds;
+            if (L == 0) C.solve_in_tail = b64 > 0;
+            const int mcap = std::max(0, L - 1);
+            C.tail_top = o.precision == MSG_MIXED ? choose_tail<float>(c, pc, qc, mcap, o.tail_levels, C.goff)
+                                                   : choose_tail<double>(c, pc, qc, mcap, o.tail_levels, C.goff);
             C.tail_lds = o.precision == MSG_MIXED ? tail_layout<float>(c, pc, qc, C.tail_top, C.goff, C.tail)
                                                    : tail_layout<double>(c, pc, qc, C.tail_top, C.goff, C.tail);
             C.top1d = level_1d(c, pc, qc, L, C.goff, 1, qc);
@@ -319,6 +336,7 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
             }
             C.part0 = SP.part_slots;
             SP.part_slots += (int64_t)C.top1d.ntiles * C.K;
+            C.ci = (int)SP.classes.size();
             SP.classes.push_back(std::move(C));
         }
     }
@@ -328,7 +346,7 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
 // ---------------------------------------------------------------- workspace
 struct Ws {
     size_t bpyr, chol, a64v, a64v2, a64b, a32v, a32v2, a32b, part, active, pcycles, dead, nactive, sbase, gbase, rbase, probs,
-        pyrprobs, total;
+        pyrprobs, tails, cls, total;
 };
 
 Ws ws_layout(const BatchLayout& BL, const std::vector<StagePlan>& plans, bool mixed)
@@ -361,6 +379,8 @@ Ws ws_layout(const BatchLayout& BL, const std::vector<StagePlan>& plans, bool mi
     w.rbase = take(sizeof(int64_t) * BL.S);
     w.probs = take(sizeof(KProb) * std::max<int64_t>(probs, 1));
     w.pyrprobs = take(sizeof(KProb) * BL.S);
+    w.tails = take(sizeof(KTail) * 2 * (kMaxIndex + 1));
+    w.cls = take(sizeof(int32_t) * std::max<int64_t>(probs, 1));
     w.total = off;
     return w;
 }
@@ -478,6 +498,8 @@ msg_status msg_create(msg_handle* h, int device)
     HIPCHK(hipSetDevice(device));
     if (const char* f = std::getenv("MSG_RBGS_FUSE")) g_fuse = std::atoi(f) == 1 ? 1 : 2;
     if (const char* t = std::getenv("MSG_TAIL_LDS")) g_tail_lds = std::max(1024, std::atoi(t));
+    if (const char* t = std::getenv("MSG_SOLVE_LDS")) g_solve_lds = std::max(0, std::atoi(t));
+    if (const char* t = std::getenv("MSG_DEBUG_STAGES")) g_debug_stages = std::atoi(t) != 0;
     *h = new msg_handle_s{device};
     return MSG_OK;
 }
@@ -651,6 +673,7 @@ struct Ctx {
     int32_t* active;
     Profiler* prof;
     int64_t kact;       // problems of the current class still cycling
+    const KTail* tails; // device: per class of the level, [2 ci] cycle tail, [2 ci + 1] whole-class tail
 };
 
 // algorithmic bytes: data a kernel must touch at least once per active problem
@@ -720,8 +743,9 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, int lev, Iter<T>& it, T* B
         bytes = bytes * sizeof(T) * (double)X.kact;
         return timed(X, MSG_KERNEL_TAIL, bytes, [&] {
             return chunked(C.top1d, C.K, [&](int k0, int kn) {
-                return launch_tail<T>(C.tail, C.tail_lds, kn, pr + k0, act + k0, X.c, X.o->mu, X.o->nu1, X.o->nu2,
-                                      (T)X.o->omega, count, V, B, KX, KY, X.chol, X.s);
+                return launch_tail<T>(X.tails, nullptr, 2 * C.ci, 64, C.tail_lds, kn, pr + k0, act + k0, X.c, X.o->mu,
+                                      X.o->nu1, X.o->nu2, (T)X.o->omega, count, V, B, KX, KY, X.chol, TailSolve{},
+                                      X.s);
             });
         });
     };
@@ -799,9 +823,12 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
     if (ws_bytes < W.total) return fail(MSG_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, W.total);
     if ((uintptr_t)d_ws % kAlign) return fail(MSG_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
     for (const StagePlan& SP : plans)
-        for (const ClassPlan& C : SP.classes)
-            if (C.tail_lds == 0 || C.tail_lds > 160 * 1024)
+        for (const ClassPlan& C : SP.classes) {
+            if (!C.solve_in_tail && (C.tail_lds == 0 || C.tail_lds > 160 * 1024))
                 return fail(MSG_ERR_UNSUPPORTED, "tail of class (%d,%d) does not fit LDS; lower tail_levels", C.pc, C.qc);
+            if (C.solve_in_tail && C.tail64_lds > 160 * 1024)
+                return fail(MSG_ERR_UNSUPPORTED, "class (%d,%d) does not fit LDS; lower tail_levels", C.pc, C.qc);
+        }
     HIPCHK(hipSetDevice(h->device));
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)d_ws;
@@ -893,8 +920,14 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
     X.active = (int32_t*)(ws + W.active);
     int32_t* pcycles = (int32_t*)(ws + W.pcycles);
 
+    // host staging of the per-level tables; they live until the stream has
+    // consumed them (every level synchronises before the next reuses them)
     std::vector<KProb> probs;
+    std::vector<KTail> tails;
+    std::vector<int32_t> cls;
+    X.tails = (const KTail*)(ws + W.tails);
     for (const StagePlan& SP : plans) {
+        const auto t_stage = std::chrono::steady_clock::now();
         // problems of this F-cycle level (the previous level's table copy has
         // completed: the stream was synchronised at its last convergence check)
         HIPCHK(hipStreamSynchronize(s));
@@ -913,6 +946,12 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
                 p.grid_index = C.pc * (BL.Q[smp] + 1) + C.qc;
             }
         HIPCHK(hipMemcpyAsync(X.probs, probs.data(), sizeof(KProb) * SP.K, hipMemcpyHostToDevice, s));
+        tails.assign(2 * SP.classes.size(), KTail{});
+        for (const ClassPlan& C : SP.classes) {
+            tails[2 * C.ci] = C.tail;
+            tails[2 * C.ci + 1] = C.tail64;
+        }
+        HIPCHK(hipMemcpyAsync(ws + W.tails, tails.data(), sizeof(KTail) * tails.size(), hipMemcpyHostToDevice, s));
         {
             hipError_t e = launch_activate(SP.K, X.probs, dead, SP.L, X.active, pcycles, s);
             if (e != hipSuccess) return fail(MSG_ERR_HIP, "activate: %s", hipGetErrorString(e));
@@ -931,12 +970,54 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
             });
             if (st != MSG_OK) return st;
         }
+        // classes that fit in LDS: the whole adaptive loop in one kernel, all
+        // such classes of the level in one launch so that their slowest
+        // problems overlap
+        {
+            cls.assign(SP.K, -1);
+            size_t lds = 0;
+            double bytes = 0.0;
+            int64_t nsolve = 0;
+            for (const ClassPlan& C : SP.classes) {
+                if (!C.solve_in_tail) continue;
+                for (int k = 0; k < C.K; ++k) cls[C.first + k] = 2 * C.ci + 1;
+                lds = std::max(lds, C.tail64_lds);
+                double per = 3.0 * grid_cells(c, C.pc, C.qc);
+                for (int g = 0; g < C.tail64.ngrids; ++g) {
+                    const KTailGrid& G = C.tail64.g[g];
+                    per += (double)(G.nx + 1) * G.ny + (double)G.nx * (G.ny + 1);
+                }
+                bytes += per * sizeof(double) * C.K;
+                nsolve += C.K;
+            }
+            if (nsolve > 0) {
+                HIPCHK(hipMemcpyAsync(ws + W.cls, cls.data(), sizeof(int32_t) * SP.K, hipMemcpyHostToDevice, s));
+                const int threads = lds >= 24576 ? 256 : 64;
+                st = timed(X, MSG_KERNEL_TAIL, bytes, [&]() -> msg_status {
+                    const int64_t per = (int64_t)1 << 30;
+                    for (int64_t k0 = 0; k0 < SP.K; k0 += per) {
+                        const int kn = (int)std::min<int64_t>(per, SP.K - k0);
+                        TailSolve ad{opts->tol, opts->max_cycles, SP.L, pcycles + k0, d_status, dead};
+                        hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls) + k0, 0, threads, lds,
+                                                           kn, X.probs + k0, X.active + k0, c, opts->mu, opts->nu1,
+                                                           opts->nu2, opts->omega, -1, it64.v[0], a64b, d_kx, d_ky,
+                                                           chol, ad, s);
+                        if (e != hipSuccess) return fail(MSG_ERR_HIP, "tail launch: %s", hipGetErrorString(e));
+                    }
+                    return MSG_OK;
+                });
+                if (st != MSG_OK) return st;
+            }
+        }
         // adaptive number of cycles per problem (Section 2): check, then cycle
         std::vector<int32_t> host_active(ncls, 0);
+        int iters = 0;
         for (int it = 0; it <= opts->max_cycles + 1; ++it) {
             HIPCHK(hipMemsetAsync(nact, 0, sizeof(int32_t) * ncls, s));
+            iters = it;
             for (int ci = 0; ci < ncls; ++ci) {
                 const ClassPlan& C = SP.classes[ci];
+                if (C.solve_in_tail) continue;                 // solved above
                 if (it > 0 && host_active[ci] == 0) continue;   // this class has stopped
                 if (mixed) i32[ci].cur[SP.L] = 0;          // the check writes the FP32 top iterate (zero)
                 const double nb = (3.0 * grid_cells(c, C.pc, C.qc) + (double)((c << C.pc) + 1) * (c << C.qc) +
@@ -991,6 +1072,16 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
             hipError_t e = launch_qreduce(C.K, C.top1d.ntiles, cells, X.probs + C.first, pcycles + C.first,
                                           (const int64_t*)(ws + W.gbase), part, d_q_out, d_cycles, s);
             if (e != hipSuccess) return fail(MSG_ERR_HIP, "qreduce: %s", hipGetErrorString(e));
+        }
+        if (g_debug_stages) {
+            HIPCHK(hipStreamSynchronize(s));
+            int in_tail = 0;
+            for (const ClassPlan& C : SP.classes) in_tail += C.solve_in_tail;
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_stage).count();
+            std::fprintf(stderr, "[msg] level %2d: %2d classes (%d in one kernel, tail top %d), %6d problems, "
+                                 "%4d host iterations, %9.2f ms\n",
+                         SP.L, ncls, in_tail, SP.classes.back().tail_top, SP.K, iters, ms);
         }
     }
     HIPCHK(hipStreamSynchronize(s));

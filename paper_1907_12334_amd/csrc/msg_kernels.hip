@@ -634,85 +634,160 @@ k_rhs_top(KLevel L, const KProb* __restrict__ probs, double* __restrict__ BP, co
 
 // ------------------------------------------------------------------------
 // Tail: the mu-cycles of levels 0..top of one problem run inside one
-// workgroup, with every grid of those levels (iterate, right-hand side and
+// wavefront, with every grid of those levels (iterate, right-hand side and
 // face coefficients) held in LDS; the coarsest grid is solved with the
 // sample's FP64 Cholesky factor.  The top level's iterate and right-hand
-// side come from the arena and the iterate goes back there.
+// side come from the arena and the iterate goes back there.  A single wave
+// per problem keeps every phase barrier local to the wave, and many small
+// workgroups per CU hide the latency of the short dependent phases.
 // ------------------------------------------------------------------------
+// (i,j) of linear cell index idx on a grid of width nx (log2 width sh, or -1)
+__device__ __forceinline__ void cell_ij(int idx, int nx, int sh, int& i, int& j)
+{
+    if (sh >= 0) { j = idx >> sh; i = idx & (nx - 1); }
+    else { j = idx / nx; i = idx - j * nx; }
+}
+
+// The grid a lane works on inside one level, picked out of the (uniform)
+// descriptors by selection so that no lane indexes kernel arguments itself.
+struct TG {
+    int nx, ny, lv, lb, lkx, lky, sh;
+    int cx, cy, px, py;
+};
+
+// Slot s of a level whose grid k owns cnt(k) consecutive slots (half the
+// cells when `half` and nx is even -- one colour -- else all cells); returns
+// the grid and the index inside it.
+__device__ __forceinline__ TG level_pick(const KTail& TL, int g0, int g1, int s, bool half, int& local)
+{
+    TG t{};
+    int base = 0;
+    local = 0;
+    for (int k = g0; k < g1; ++k) {
+        const KTailGrid& G = TL.g[k];
+        const int n = (half && !(G.nx & 1)) ? (G.nx * G.ny) >> 1 : G.nx * G.ny;
+        if (s >= base && s < base + n) {
+            t.nx = G.nx; t.ny = G.ny; t.lv = G.lv; t.lb = G.lb; t.lkx = G.lkx; t.lky = G.lky; t.sh = G.sh;
+            t.cx = G.cx; t.cy = G.cy; t.px = G.px; t.py = G.py;
+            local = s - base;
+        }
+        base += n;
+    }
+    return t;
+}
+
+__device__ __forceinline__ int level_slots(const KTail& TL, int g0, int g1, bool half)
+{
+    int n = 0;
+    for (int k = g0; k < g1; ++k) n += (half && !(TL.g[k].nx & 1)) ? (TL.g[k].nx * TL.g[k].ny) >> 1 : TL.g[k].nx * TL.g[k].ny;
+    return n;
+}
+
+// the same fields of a grid reached through a (uniform) tail index
+__device__ __forceinline__ TG tail_grid(const KTail& TL, int k)
+{
+    const KTailGrid& G = TL.g[k];
+    return TG{G.nx, G.ny, G.lv, G.lb, G.lkx, G.lky, G.sh, G.cx, G.cy, G.px, G.py};
+}
+
+// lane-selected fields of grid k (k may differ across lanes; its candidates
+// are the grids of one level, g0..g1-1)
+__device__ __forceinline__ TG pick_index(const KTail& TL, int g0, int g1, int k)
+{
+    TG t{};
+    for (int m = g0; m < g1; ++m)
+        if (m == k) t = tail_grid(TL, m);
+    return t;
+}
+
 template <typename T>
-__device__ void tail_smooth(const KTail& TL, T* sm, int lev, int sweeps)
+__device__ __forceinline__ void tail_update(const TG& G, T* sm, int i, int j)
+{
+    T* v = sm + G.lv;
+    const int off = j * G.nx + i;
+    const T ihx2 = T(G.nx) * T(G.nx), ihy2 = T(G.ny) * T(G.ny);
+    const Stencil<T> st = stencil_at(sm + G.lkx, sm + G.lky, G.nx, G.ny, i, j, ihx2, ihy2);
+    const T uW = i > 0 ? v[off - 1] : T(0);
+    const T uE = i < G.nx - 1 ? v[off + 1] : T(0);
+    const T uS = j > 0 ? v[off - G.nx] : T(0);
+    const T uN = j < G.ny - 1 ? v[off + G.nx] : T(0);
+    const T num = sm[G.lb + off] + st.wW * uW + st.wE * uE + st.wS * uS + st.wN * uN;
+    v[off] = num / (st.wW + st.wE + st.wS + st.wN);
+}
+
+// every grid of level lev, sweeps red-then-black sweeps; the cells of one
+// colour of all the level's grids are spread over all lanes
+template <typename T, int NT>
+__device__ __forceinline__ void tail_smooth(const KTail& TL, T* sm, int lev, int sweeps)
 {
     const int g0 = TL.level_begin[lev], g1 = TL.level_begin[lev + 1];
-    int total = 0;
-    for (int g = g0; g < g1; ++g) total += TL.g[g].nx * TL.g[g].ny;
+    const int total = level_slots(TL, g0, g1, true);
     for (int s = 0; s < sweeps; ++s)
         for (int colour = 0; colour < 2; ++colour) {
-            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-                int g = g0, off = idx;
-                while (off >= TL.g[g].nx * TL.g[g].ny) { off -= TL.g[g].nx * TL.g[g].ny; ++g; }
-                const KTailGrid& G = TL.g[g];
-                const int i = off % G.nx, j = off / G.nx;
-                if (((i + j) & 1) != colour) continue;
-                T* v = sm + G.lv;
-                const T ihx2 = T(G.nx) * T(G.nx), ihy2 = T(G.ny) * T(G.ny);
-                const Stencil<T> st = stencil_at(sm + G.lkx, sm + G.lky, G.nx, G.ny, i, j, ihx2, ihy2);
-                const T uW = i > 0 ? v[off - 1] : T(0);
-                const T uE = i < G.nx - 1 ? v[off + 1] : T(0);
-                const T uS = j > 0 ? v[off - G.nx] : T(0);
-                const T uN = j < G.ny - 1 ? v[off + G.nx] : T(0);
-                const T num = sm[G.lb + off] + st.wW * uW + st.wE * uE + st.wS * uS + st.wN * uN;
-                v[off] = num / (st.wW + st.wE + st.wS + st.wN);
+            for (int sl = threadIdx.x; sl < total; sl += NT) {
+                int local;
+                const TG G = level_pick(TL, g0, g1, sl, true, local);
+                if (!(G.nx & 1)) {
+                    // pair k of row j holds (2k + ((colour + j) & 1), j)
+                    int k, j;
+                    cell_ij(local, G.nx >> 1, G.sh - 1, k, j);
+                    tail_update(G, sm, 2 * k + ((colour + j) & 1), j);
+                } else {
+                    int i, j;
+                    cell_ij(local, G.nx, -1, i, j);
+                    if (((i + j) & 1) == colour) tail_update(G, sm, i, j);
+                }
             }
             __syncthreads();
         }
 }
 
-template <typename T>
-__device__ void tail_restrict(const KTail& TL, T* sm, int lev)   // level lev -> lev-1
+template <typename T, int NT>
+__device__ __forceinline__ void tail_restrict(const KTail& TL, T* sm, int lev)   // level lev -> lev-1
 {
     const int g0 = TL.level_begin[lev - 1], g1 = TL.level_begin[lev];
-    int total = 0;
-    for (int g = g0; g < g1; ++g) total += TL.g[g].nx * TL.g[g].ny;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        int g = g0, off = idx;
-        while (off >= TL.g[g].nx * TL.g[g].ny) { off -= TL.g[g].nx * TL.g[g].ny; ++g; }
-        const KTailGrid& G = TL.g[g];
-        const int I = off % G.nx, J = off / G.nx;
+    const int f0 = TL.level_begin[lev], f1 = TL.level_begin[lev + 1];
+    const int total = level_slots(TL, g0, g1, false);
+    for (int sl = threadIdx.x; sl < total; sl += NT) {
+        int off;
+        const TG G = level_pick(TL, g0, g1, sl, false, off);
+        int I, J;
+        cell_ij(off, G.nx, G.sh, I, J);
+        const bool hx = G.px >= 0, hy = G.py >= 0;
         T rx = T(0), ry = T(0);
-        if (G.px >= 0) {
-            const KTailGrid& F = TL.g[G.px];
+        if (hx) {
+            const TG F = pick_index(TL, f0, f1, G.px);
             const T ihx2 = T(F.nx) * T(F.nx), ihy2 = T(F.ny) * T(F.ny);
             rx = T(0.5) * (residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, 2 * I, J, ihx2, ihy2) +
                            residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, 2 * I + 1, J, ihx2, ihy2));
         }
-        if (G.py >= 0) {
-            const KTailGrid& F = TL.g[G.py];
+        if (hy) {
+            const TG F = pick_index(TL, f0, f1, G.py);
             const T ihx2 = T(F.nx) * T(F.nx), ihy2 = T(F.ny) * T(F.ny);
             ry = T(0.5) * (residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, I, 2 * J, ihx2, ihy2) +
                            residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, I, 2 * J + 1, ihx2, ihy2));
         }
-        const bool hx = G.px >= 0, hy = G.py >= 0;
         sm[G.lb + off] = (hx && hy) ? T(0.5) * rx + T(0.5) * ry : (hx ? rx : ry);
         sm[G.lv + off] = T(0);
     }
     __syncthreads();
 }
 
-template <typename T>
-__device__ void tail_prolong(const KTail& TL, T* sm, int lev, T omega)
+template <typename T, int NT>
+__device__ __forceinline__ void tail_prolong(const KTail& TL, T* sm, int lev, T omega)
 {
     const int g0 = TL.level_begin[lev], g1 = TL.level_begin[lev + 1];
-    int total = 0;
-    for (int g = g0; g < g1; ++g) total += TL.g[g].nx * TL.g[g].ny;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        int g = g0, off = idx;
-        while (off >= TL.g[g].nx * TL.g[g].ny) { off -= TL.g[g].nx * TL.g[g].ny; ++g; }
-        const KTailGrid& G = TL.g[g];
-        const int i = off % G.nx, j = off / G.nx;
+    const int c0 = TL.level_begin[lev - 1], c1 = TL.level_begin[lev];
+    const int total = level_slots(TL, g0, g1, false);
+    for (int sl = threadIdx.x; sl < total; sl += NT) {
+        int off;
+        const TG G = level_pick(TL, g0, g1, sl, false, off);
+        int i, j;
+        cell_ij(off, G.nx, G.sh, i, j);
         const bool hx = G.cx >= 0, hy = G.cy >= 0;
         T ex = T(0), ey = T(0);
-        if (hx) ex = linear_at(sm + TL.g[G.cx].lv + j * (G.nx / 2), (int64_t)1, G.nx / 2, i);
-        if (hy) ey = linear_at(sm + TL.g[G.cy].lv + i, (int64_t)G.nx, G.ny / 2, j);
+        if (hx) ex = linear_at(sm + pick_index(TL, c0, c1, G.cx).lv + j * (G.nx / 2), (int64_t)1, G.nx / 2, i);
+        if (hy) ey = linear_at(sm + pick_index(TL, c0, c1, G.cy).lv + i, (int64_t)G.nx, G.ny / 2, j);
         T corr;
         if (hx && hy) {
             const T ka = kappa_x_at(sm + G.lkx, sm + G.lky, G.nx, G.ny, i, j, T(G.nx) * T(G.nx), T(G.ny) * T(G.ny));
@@ -725,9 +800,10 @@ __device__ void tail_prolong(const KTail& TL, T* sm, int lev, T omega)
     __syncthreads();
 }
 
-// v^(0,0) = L^-T L^-1 b^(0,0), computed in FP64 by the first wavefront
+// v^(0,0) = L^-T L^-1 b^(0,0) in FP64 by the first wavefront, lane k holding
+// unknown k (c^2 <= 64)
 template <typename T>
-__device__ void tail_coarse(const KTail& TL, T* sm, const double* Lc, int n)
+__device__ __forceinline__ void tail_coarse(const KTail& TL, T* sm, const double* Lc, int n)
 {
     const KTailGrid& G = TL.g[0];
     if (threadIdx.x < 64) {
@@ -750,43 +826,17 @@ __device__ void tail_coarse(const KTail& TL, T* sm, const double* Lc, int n)
     __syncthreads();
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_tail(KTail TL, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c, int mu, int nu1,
-       int nu2, T omega, int count, T* __restrict__ V, T* __restrict__ B, const T* __restrict__ KX,
-       const T* __restrict__ KY, const double* __restrict__ chol)
+// count mu-cycles on the tail's top level; the recursion is unrolled with
+// the cycles still to run on each level kept two bits per level in a register
+template <typename T, int NT>
+__device__ __forceinline__ void tail_cycles(const KTail& TL, T* sm, const double* Lc, int n0, int mu, int nu1, int nu2, T omega,
+                            int count)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    T* sm = reinterpret_cast<T*>(smem);
-    double* Lc = reinterpret_cast<double*>(smem + TL.chol_off);
-    const int k = blockIdx.x;
-    if (!active[k]) return;
-    const KProb pr = probs[k];
-    const int n0 = c * c;
-    // stage in: coefficients of every tail grid, top-level iterate and rhs, factor
-    for (int g = 0; g < TL.ngrids; ++g) {
-        const KTailGrid& G = TL.g[g];
-        const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
-        const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
-        const int nfx = (G.nx + 1) * G.ny, nfy = G.nx * (G.ny + 1);
-        for (int idx = threadIdx.x; idx < nfx; idx += blockDim.x) sm[G.lkx + idx] = kx[idx];
-        for (int idx = threadIdx.x; idx < nfy; idx += blockDim.x) sm[G.lky + idx] = ky[idx];
-        if (G.p + G.q == TL.top) {
-            const int n = G.nx * G.ny;
-            for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-                sm[G.lv + idx] = V[pr.arena_base + G.aoff + idx];
-                sm[G.lb + idx] = B[pr.arena_base + G.aoff + idx];
-            }
-        }
-    }
-    for (int idx = threadIdx.x; idx < n0 * n0; idx += blockDim.x) Lc[idx] = chol[(int64_t)pr.sample * n0 * n0 + idx];
-    __syncthreads();
-
-    // iterative form of the recursive mu-cycle: left[l] counts the cycles
-    // still to run on level l before returning to level l+1
-    int left[kMaxIndex * 2 + 2];
+    uint64_t left = 0;
+    auto get = [&](int l) { return (int)((left >> (2 * l)) & 3u); };
+    auto set = [&](int l, int v) { left = (left & ~((uint64_t)3 << (2 * l))) | ((uint64_t)v << (2 * l)); };
     int lev = TL.top;
-    left[lev] = count;
+    set(lev, count);
     bool down = true;
     for (;;) {
         if (down) {
@@ -795,24 +845,131 @@ k_tail(KTail TL, const KProb* __restrict__ probs, const int32_t* __restrict__ ac
                 down = false;
                 continue;
             }
-            tail_smooth(TL, sm, lev, nu1);
-            tail_restrict(TL, sm, lev);
+            tail_smooth<T, NT>(TL, sm, lev, nu1);
+            tail_restrict<T, NT>(TL, sm, lev);
             --lev;
-            left[lev] = mu;
+            set(lev, mu);
         } else {
             // one cycle on level lev just finished
-            if (--left[lev] > 0) { down = true; continue; }
+            const int l = get(lev) - 1;
+            set(lev, l);
+            if (l > 0) { down = true; continue; }
             if (lev == TL.top) break;
             ++lev;
-            tail_prolong(TL, sm, lev, omega);
-            tail_smooth(TL, sm, lev, nu2);
+            tail_prolong<T, NT>(TL, sm, lev, omega);
+            tail_smooth<T, NT>(TL, sm, lev, nu2);
         }
+    }
+}
+
+// ||b - A v||_2^2 and ||b||_2^2 of the (single) top grid over the workgroup
+template <typename T, int NT>
+__device__ __forceinline__ void tail_norms(const KTail& TL, T* sm, double& rr, double& bb)
+{
+    __shared__ double red[2][NT / 64];
+    const TG G = tail_grid(TL, TL.level_begin[TL.top]);
+    const T ihx2 = T(G.nx) * T(G.nx), ihy2 = T(G.ny) * T(G.ny);
+    rr = 0.0;
+    bb = 0.0;
+    for (int off = threadIdx.x; off < G.nx * G.ny; off += NT) {
+        int i, j;
+        cell_ij(off, G.nx, G.sh, i, j);
+        const double r = (double)residual_at(sm + G.lv, sm + G.lb, sm + G.lkx, sm + G.lky, G.nx, G.ny, i, j, ihx2, ihy2);
+        const double b = (double)sm[G.lb + off];
+        rr += r * r;
+        bb += b * b;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        rr += __shfl_xor(rr, o, 64);
+        bb += __shfl_xor(bb, o, 64);
+    }
+    if (NT > 64) {
+        if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = rr; red[1][threadIdx.x >> 6] = bb; }
+        __syncthreads();
+        rr = red[0][0];
+        bb = red[1][0];
+        for (int w = 1; w < NT / 64; ++w) { rr += red[0][w]; bb += red[1][w]; }
+        __syncthreads();
+    }
+}
+
+// count > 0: that many mu-cycles on the top level.  count < 0: the whole
+// adaptive loop of one F-cycle level (Section 2: cycle until ||r|| <= tol ||b||,
+// checked before every cycle) for problems whose rectangle fits in LDS,
+// updating cycle counts, status and the non-finite level like k_converge.
+// Block b works on problem b of the launch with class descriptor
+// tables[cls[b]] (cls given: several classes in one launch, -1 = skip) or
+// tables[tidx].
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT)
+k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int tidx,
+       const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c, int mu, int nu1,
+       int nu2, T omega, int count, T* __restrict__ V, T* __restrict__ B, const T* __restrict__ KX,
+       const T* __restrict__ KY, const double* __restrict__ chol, TailSolve ad)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int k = blockIdx.x;
+    const int t = cls ? cls[k] : tidx;
+    if (t < 0 || !active[k]) return;
+    const KTail& TL = tables[t];
+    T* sm = reinterpret_cast<T*>(smem);
+    double* Lc = reinterpret_cast<double*>(smem + TL.chol_off);
+    const KProb pr = probs[k];
+    const int n0 = c * c;
+    // stage in: coefficients of every tail grid, top-level iterate and rhs, factor
+    for (int g = 0; g < TL.ngrids; ++g) {
+        const KTailGrid& G = TL.g[g];
+        const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
+        const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
+        const int nfx = (G.nx + 1) * G.ny, nfy = G.nx * (G.ny + 1);
+        const int lkx = G.lkx, lky = G.lky;
+        for (int idx = threadIdx.x; idx < nfx; idx += NT) sm[lkx + idx] = kx[idx];
+        for (int idx = threadIdx.x; idx < nfy; idx += NT) sm[lky + idx] = ky[idx];
+        if (G.p + G.q == TL.top) {
+            const int n = G.nx * G.ny;
+            const int lv = G.lv, lb = G.lb;
+            const int64_t a = pr.arena_base + G.aoff;
+            for (int idx = threadIdx.x; idx < n; idx += NT) {
+                sm[lv + idx] = V[a + idx];
+                sm[lb + idx] = B[a + idx];
+            }
+        }
+    }
+    for (int idx = threadIdx.x; idx < n0 * n0; idx += NT) Lc[idx] = chol[(int64_t)pr.sample * n0 * n0 + idx];
+    __syncthreads();
+
+    if (count > 0) {
+        tail_cycles<T, NT>(TL, sm, Lc, n0, mu, nu1, nu2, omega, count);
+    } else {
+        int ncyc = 0;
+        for (;;) {
+            double rr, bb;
+            tail_norms<T, NT>(TL, sm, rr, bb);
+            const double rn = sqrt(rr), bn = sqrt(bb);
+            if (!isfinite(rn) || !isfinite(bn)) {
+                if (threadIdx.x == 0) {
+                    atomicMax(&ad.status[pr.sample], (int)MSG_ST_NONFINITE);
+                    atomicMin(&ad.dead_level[pr.sample], ad.level);
+                }
+                break;
+            }
+            if (rn <= ad.tol * bn) break;
+            if (ncyc >= ad.max_cycles) {
+                if (threadIdx.x == 0) atomicMax(&ad.status[pr.sample], (int)MSG_ST_MAXITER);
+                break;
+            }
+            tail_cycles<T, NT>(TL, sm, Lc, n0, mu, nu1, nu2, omega, 1);
+            ++ncyc;
+        }
+        if (threadIdx.x == 0) ad.pcycles[k] = ncyc;
     }
     // stage out the top level's iterates
     for (int g = TL.level_begin[TL.top]; g < TL.level_begin[TL.top + 1]; ++g) {
         const KTailGrid& G = TL.g[g];
         const int n = G.nx * G.ny;
-        for (int idx = threadIdx.x; idx < n; idx += blockDim.x) V[pr.arena_base + G.aoff + idx] = sm[G.lv + idx];
+        const int lv = G.lv;
+        const int64_t a = pr.arena_base + G.aoff;
+        for (int idx = threadIdx.x; idx < n; idx += NT) V[a + idx] = sm[lv + idx];
     }
 }
 
@@ -896,16 +1053,22 @@ hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int3
 }
 
 template <typename T>
-hipError_t launch_tail(const KTail& TL, size_t lds_bytes, int K, const KProb* probs, const int32_t* active, int c,
-                       int mu, int nu1, int nu2, T omega, int count, T* V, T* B, const T* KX, const T* KY,
-                       const double* chol, hipStream_t st)
+hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int threads, size_t lds_bytes, int K,
+                       const KProb* probs, const int32_t* active, int c, int mu, int nu1, int nu2, T omega,
+                       int count, T* V, T* B, const T* KX, const T* KY, const double* chol, const TailSolve& ad,
+                       hipStream_t st)
 {
+    const void* fn = threads == 256 ? (const void*)k_tail<T, 256> : (const void*)k_tail<T, 64>;
     if (lds_bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_tail<T>), dim3(K), dim3(kBlock), lds_bytes, st, TL, probs, active, c, mu, nu1, nu2, omega,
-                       count, V, B, KX, KY, chol);
+    if (threads == 256)
+        hipLaunchKernelGGL((k_tail<T, 256>), dim3(K), dim3(256), lds_bytes, st, tables, cls, tidx, probs, active, c,
+                           mu, nu1, nu2, omega, count, V, B, KX, KY, chol, ad);
+    else
+        hipLaunchKernelGGL((k_tail<T, 64>), dim3(K), dim3(64), lds_bytes, st, tables, cls, tidx, probs, active, c,
+                           mu, nu1, nu2, omega, count, V, B, KX, KY, chol, ad);
     return LAUNCH_CHECK();
 }
 
@@ -991,11 +1154,11 @@ template hipError_t launch_prolong<double>(const KLevel&, int, const KProb*, con
                                            const double*, double*, const double*, const double*, hipStream_t);
 template hipError_t launch_prolong<float>(const KLevel&, int, const KProb*, const int32_t*, int, float, const float*,
                                           float*, const float*, const float*, hipStream_t);
-template hipError_t launch_tail<double>(const KTail&, size_t, int, const KProb*, const int32_t*, int, int, int, int,
-                                        double, int, double*, double*, const double*, const double*, const double*,
-                                        hipStream_t);
-template hipError_t launch_tail<float>(const KTail&, size_t, int, const KProb*, const int32_t*, int, int, int, int,
-                                       float, int, float*, float*, const float*, const float*, const double*,
-                                       hipStream_t);
+template hipError_t launch_tail<double>(const KTail*, const int32_t*, int, int, size_t, int, const KProb*,
+                                        const int32_t*, int, int, int, int, double, int, double*, double*,
+                                        const double*, const double*, const double*, const TailSolve&, hipStream_t);
+template hipError_t launch_tail<float>(const KTail*, const int32_t*, int, int, size_t, int, const KProb*,
+                                       const int32_t*, int, int, int, int, float, int, float*, float*, const float*,
+                                       const float*, const double*, const TailSolve&, hipStream_t);
 
 }  // namespace msg

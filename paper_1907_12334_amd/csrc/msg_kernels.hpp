@@ -16,6 +16,16 @@ struct SampleBase {
     int32_t P, Q;
 };
 
+// adaptive cycling inside the tail kernel (count < 0)
+struct TailSolve {
+    double tol;
+    int32_t max_cycles;
+    int32_t level;
+    int32_t* pcycles;      // per problem, offset like the problem table
+    int32_t* status;       // per sample
+    int32_t* dead_level;   // per sample
+};
+
 // one launch of the field synthesis: one face kind of one grid (p,q) for a
 // list of samples sharing that grid
 struct FieldArgs {
@@ -42,10 +52,13 @@ hipError_t launch_restrict(bool rhs, const KLevel& L, int K, const KProb* probs,
 template <typename T>
 hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, T omega,
                           const T* Vc, T* Vf, const T* KX, const T* KY, hipStream_t st);
+// block b uses class descriptor tables[cls[b]] (cls given, -1 skips the
+// block) or tables[tidx]; threads is 64 or 256
 template <typename T>
-hipError_t launch_tail(const KTail& TL, size_t lds_bytes, int K, const KProb* probs, const int32_t* active, int c,
-                       int mu, int nu1, int nu2, T omega, int count, T* V, T* B, const T* KX, const T* KY,
-                       const double* chol, hipStream_t st);
+hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int threads, size_t lds_bytes, int K,
+                       const KProb* probs, const int32_t* active, int c, int mu, int nu1, int nu2, T omega,
+                       int count, T* V, T* B, const T* KX, const T* KY, const double* chol, const TailSolve& ad,
+                       hipStream_t st);
 hipError_t launch_fmg(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, double* V, double* B,
                       const double* U, const double* BP, const double* KX, const double* KY, hipStream_t st);
 hipError_t launch_resnorm(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, const double* V,
