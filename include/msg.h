@@ -99,9 +99,13 @@ typedef struct {
     int32_t precision;          /* MSG_FP64, or MSG_MIXED: FP32 inner cycles refined in FP64 */
     int32_t tail_levels;        /* -1 = automatic; else levels 0..tail_levels run in one
                                    workgroup per grid from on-chip memory */
+    int32_t handoff;            /* -1 = automatic; 0 = never; n: once at most n problems of a
+                                   class still cycle and its rectangle fits on chip, their
+                                   remaining cycles run inside one kernel */
 } msg_solve_opts;
 
-/* Fill opts with the defaults: W(2,2), 50 cycles, tol 1e-10, omega 1, FP64. */
+/* Fill opts with the defaults: W(2,2), 50 cycles, tol 1e-10, omega 1, FP64,
+ * automatic tail depth and handoff. */
 void msg_default_opts(msg_solve_opts *opts);
 
 /* Create a handle bound to HIP device `device`.  Returns MSG_OK or MSG_ERR_HIP. */

@@ -10,7 +10,6 @@ namespace msg {
 
 constexpr int kMaxIndex = 14;          // largest p or q of a grid
 constexpr int kMaxLevelGrids = kMaxIndex + 1;
-constexpr int kMaxTailGrids = 45;      // grids with p + q <= 8
 constexpr int kMaxCosTerms = 64;
 constexpr int kMaxModes = 64;
 constexpr int kBlock = 256;            // threads per block of the level kernels
@@ -70,28 +69,36 @@ struct KGrid {
 struct KLevel {
     int32_t ngrids;
     int32_t ntiles;        // blocks per problem
+    int32_t nblocks;       // real blocks of the launch (ntiles * problems); set by the launcher
+    int32_t pad;
     KGrid g[kMaxLevelGrids];
 };
 
 // The grids of levels 0..top of a problem class held in LDS by the tail
-// kernel; grids are ordered by level, then p.
-struct KTailGrid {
-    int32_t nx, ny, p, q;
-    int32_t lv, lb, lkx, lky;  // LDS element offsets of v, b, x-faces, y-faces
-    int64_t aoff;              // arena offset (used for the top level)
-    int16_t cx, cy;            // tail index of child (p-1,q) / (p,q-1), -1 if none
-    int16_t px, py;            // tail index of parent (p+1,q) / (p,q+1), -1 if none
-    int16_t sh;                // log2(nx) when nx is a power of two, else -1
-    int16_t pad[3];
+// kernel.  Every grid of level l of a class has c^2 2^l cells and grid index
+// p = pmin + g (q = l - p), so a level is described by a handful of numbers:
+// its grids' iterates, right-hand sides and inverse diagonals sit in blocks of
+// `cells` elements; its x-face conductances follow each other (grid g starts
+// at x0 + g*cells + c*(2^(qmax+1) - 2^(qmax+1-g)), qmax = l - pmin) and so do
+// its y-face conductances (y0 + g*cells + c*2^pmin*(2^g - 1)).
+struct KTailLevel {
+    int32_t pmin, ng;          // grids p = pmin .. pmin+ng-1
+    int32_t cells, csh;        // cells per grid and its log2 (or -1)
+    int32_t v0, b0, d0;        // LDS element offsets: iterates, right-hand sides, inverse diagonals
+    int32_t x0, y0;            // LDS element offsets of the face conductance runs
 };
 
+constexpr int kMaxTailLevels = 9;        // levels 0..8
+
 struct KTail {
-    int32_t ngrids;
     int32_t top;               // level the cycles start on
-    int32_t lds_elems;         // LDS elements of type T (chol factor in doubles after them)
+    int32_t pc, qc;            // the class rectangle
+    int32_t c, lc;             // coarsest cells per direction and its log2 (or -1)
+    int32_t lds_elems;         // LDS elements of type T (the Cholesky factor in doubles follows)
     int32_t chol_off;          // byte offset of the coarsest factor in LDS
-    int32_t level_begin[32];
-    KTailGrid g[kMaxTailGrids];
+    int32_t pad;
+    KTailLevel lvl[kMaxTailLevels];
+    int64_t top_aoff[kMaxLevelGrids];    // arena offsets of the top level's grids
 };
 
 struct KCosTable {

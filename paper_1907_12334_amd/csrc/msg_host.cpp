@@ -79,6 +79,7 @@ msg_status check_opts(const msg_solve_opts* o)
     if (!std::isfinite(o->omega)) return fail(MSG_ERR_ARG, "omega must be finite");
     if (o->precision != MSG_FP64 && o->precision != MSG_MIXED) return fail(MSG_ERR_ARG, "unknown precision");
     if (o->tail_levels < -1 || o->tail_levels > 8) return fail(MSG_ERR_ARG, "tail_levels must be -1..8");
+    if (o->handoff < -1) return fail(MSG_ERR_ARG, "handoff must be >= -1");
     return MSG_OK;
 }
 
@@ -117,7 +118,8 @@ BatchLayout make_layout(const msg_batch_desc* b)
 
 // ---------------------------------------------------------------- plans
 int g_fuse = 2;              // smoother sweeps fused per pass (1 or 2)
-int g_tail_lds = 20480;      // LDS budget of the W-cycle tail (sets its depth)
+int g_tail_lds = 40960;      // LDS budget of the W-cycle tail (sets its depth)
+int g_handoff = 1024;        // hand a class's last cycling problems to one kernel at or below this count
 int g_solve_lds = 65536;     // LDS budget under which a class is solved entirely in one kernel
 bool g_debug_stages = false; // per-level timing on stderr
 
@@ -221,50 +223,54 @@ KLevel level_rbgs(int c, int pc, int qc, int lev, const std::vector<int64_t>& go
     return K;
 }
 
-// LDS layout of the tail of class (pc,qc) with top level m; returns bytes
+// LDS layout of the tail of class (pc,qc) with top level m (see KTail);
+// returns its bytes, or 0 if it does not fit the descriptor
 template <typename T>
 size_t tail_layout(int c, int pc, int qc, int m, const std::vector<int64_t>& goff, KTail& TL)
 {
     std::memset(&TL, 0, sizeof TL);
+    if (m >= kMaxTailLevels) return 0;
     TL.top = m;
+    TL.pc = pc;
+    TL.qc = qc;
+    TL.c = c;
+    TL.lc = (c & (c - 1)) == 0 ? __builtin_ctz(c) : -1;
     int64_t off = 0;
-    std::map<std::pair<int, int>, int> idx;
     for (int lev = 0; lev <= m; ++lev) {
-        TL.level_begin[lev] = TL.ngrids;
-        for (int a = 0; a <= pc; ++a) {
-            const int b = lev - a;
-            if (b < 0 || b > qc) continue;
-            if (TL.ngrids >= kMaxTailGrids) return 0;
-            KTailGrid& G = TL.g[TL.ngrids];
-            idx[{a, b}] = TL.ngrids++;
-            G.nx = c << a;
-            G.ny = c << b;
-            G.p = a;
-            G.q = b;
-            G.sh = (G.nx & (G.nx - 1)) == 0 ? (int16_t)__builtin_ctz(G.nx) : (int16_t)-1;
-            const int64_t n = (int64_t)G.nx * G.ny;
-            G.lv = (int)off; off += n;
-            G.lb = (int)off; off += n;
-            G.lkx = (int)off; off += (int64_t)(G.nx + 1) * G.ny;
-            G.lky = (int)off; off += (int64_t)G.nx * (G.ny + 1);
-            G.aoff = goff[a * (qc + 1) + b];
-        }
+        KTailLevel& L = TL.lvl[lev];
+        const int pmin = std::max(0, lev - qc), pmax = std::min(pc, lev);
+        L.pmin = pmin;
+        L.ng = pmax - pmin + 1;
+        const int64_t cells = grid_cells(c, 0, lev);
+        L.cells = (int)cells;
+        L.csh = (cells & (cells - 1)) == 0 ? __builtin_ctzll(cells) : -1;
+        L.v0 = (int)off; off += cells * L.ng;
+        L.b0 = (int)off; off += cells * L.ng;
+        L.d0 = (int)off; off += cells * L.ng;
+        L.x0 = (int)off;
+        for (int g = 0; g < L.ng; ++g) off += cells + ((int64_t)c << (lev - pmin - g));      // (nx+1) ny
+        L.y0 = (int)off;
+        for (int g = 0; g < L.ng; ++g) off += cells + ((int64_t)c << (pmin + g));            // nx (ny+1)
+        if (lev == m)
+            for (int g = 0; g < L.ng; ++g) TL.top_aoff[g] = goff[(pmin + g) * (qc + 1) + (lev - pmin - g)];
     }
-    TL.level_begin[m + 1] = TL.ngrids;
-    for (int g = 0; g < TL.ngrids; ++g) {
-        KTailGrid& G = TL.g[g];
-        auto find = [&](int a, int b) -> int16_t {
-            auto it = idx.find({a, b});
-            return it == idx.end() ? (int16_t)-1 : (int16_t)it->second;
-        };
-        G.cx = G.p > 0 ? find(G.p - 1, G.q) : (int16_t)-1;
-        G.cy = G.q > 0 ? find(G.p, G.q - 1) : (int16_t)-1;
-        G.px = G.p + 1 <= pc ? find(G.p + 1, G.q) : (int16_t)-1;
-        G.py = G.q + 1 <= qc ? find(G.p, G.q + 1) : (int16_t)-1;
-    }
+    if (off > (int64_t)1 << 30) return 0;
     TL.lds_elems = (int)off;
     TL.chol_off = (int)(((size_t)off * sizeof(T) + 15) / 16 * 16);
     return (size_t)TL.chol_off + sizeof(double) * (size_t)c * c * c * c;
+}
+
+// faces of every tail grid plus the top level's cells (bytes of type T per problem)
+double tail_bytes(const KTail& TL, size_t elem)
+{
+    double per = 0.0;
+    for (int lev = 0; lev <= TL.top; ++lev) {
+        const KTailLevel& L = TL.lvl[lev];
+        per += (double)(TL.lvl[lev].y0 - TL.lvl[lev].x0);                 // x-faces
+        per += (double)((lev < TL.top ? TL.lvl[lev + 1].v0 : TL.lds_elems) - L.y0);   // y-faces
+        if (lev == TL.top) per += 3.0 * L.cells * L.ng;
+    }
+    return per * elem;
 }
 
 template <typename T>
@@ -273,7 +279,7 @@ int choose_tail(int c, int pc, int qc, int L, int req, const std::vector<int64_t
     KTail TL;
     if (req >= 0) return std::min(req, L);
     int best = 0;
-    for (int m = 0; m <= std::min(L, 8); ++m) {
+    for (int m = 0; m <= std::min(L, kMaxTailLevels - 1); ++m) {
         const size_t bytes = tail_layout<T>(c, pc, qc, m, goff, TL);
         if (bytes == 0 || bytes > (size_t)g_tail_lds) break;
         best = m;
@@ -315,7 +321,7 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
             // classes whose whole rectangle fits in LDS run their adaptive
             // cycles inside one FP64 kernel; the others cycle on the host
             // down to a tail of levels 0..tail_top < L
-            const size_t b64 = L <= 8 ? tail_layout<double>(c, pc, qc, L, C.goff, C.tail64) : 0;
+            const size_t b64 = L < kMaxTailLevels ? tail_layout<double>(c, pc, qc, L, C.goff, C.tail64) : 0;
             C.tail64_lds = b64;
             if (o.tail_levels >= 0) C.solve_in_tail = L <= o.tail_levels && b64 > 0;
             else C.solve_in_tail = b64 > 0 && b64 <= (size_t)g_solve_lds;
@@ -485,6 +491,7 @@ void msg_default_opts(msg_solve_opts* o)
     o->omega = 1.0;
     o->precision = MSG_FP64;
     o->tail_levels = -1;
+    o->handoff = -1;
 }
 
 const char* msg_last_error(void) { return g_err.c_str(); }
@@ -500,6 +507,7 @@ msg_status msg_create(msg_handle* h, int device)
     if (const char* t = std::getenv("MSG_TAIL_LDS")) g_tail_lds = std::max(1024, std::atoi(t));
     if (const char* t = std::getenv("MSG_SOLVE_LDS")) g_solve_lds = std::max(0, std::atoi(t));
     if (const char* t = std::getenv("MSG_DEBUG_STAGES")) g_debug_stages = std::atoi(t) != 0;
+    if (const char* t = std::getenv("MSG_HANDOFF")) g_handoff = std::max(0, std::atoi(t));
     *h = new msg_handle_s{device};
     return MSG_OK;
 }
@@ -734,13 +742,7 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, int lev, Iter<T>& it, T* B
     msg_status st;
     auto tail = [&](int count) {
         T* V = it.now(C.tail_top);
-        double bytes = 0.0;
-        for (int g = 0; g < C.tail.ngrids; ++g) {
-            const KTailGrid& G = C.tail.g[g];
-            bytes += (double)(G.nx + 1) * G.ny + (double)G.nx * (G.ny + 1);
-            if (G.p + G.q == C.tail.top) bytes += 3.0 * G.nx * G.ny;
-        }
-        bytes = bytes * sizeof(T) * (double)X.kact;
+        const double bytes = tail_bytes(C.tail, sizeof(T)) * (double)X.kact;
         return timed(X, MSG_KERNEL_TAIL, bytes, [&] {
             return chunked(C.top1d, C.K, [&](int k0, int kn) {
                 return launch_tail<T>(X.tails, nullptr, 2 * C.ci, 64, C.tail_lds, kn, pr + k0, act + k0, X.c, X.o->mu,
@@ -982,12 +984,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
                 if (!C.solve_in_tail) continue;
                 for (int k = 0; k < C.K; ++k) cls[C.first + k] = 2 * C.ci + 1;
                 lds = std::max(lds, C.tail64_lds);
-                double per = 3.0 * grid_cells(c, C.pc, C.qc);
-                for (int g = 0; g < C.tail64.ngrids; ++g) {
-                    const KTailGrid& G = C.tail64.g[g];
-                    per += (double)(G.nx + 1) * G.ny + (double)G.nx * (G.ny + 1);
-                }
-                bytes += per * sizeof(double) * C.K;
+                bytes += tail_bytes(C.tail64, sizeof(double)) * C.K;
                 nsolve += C.K;
             }
             if (nsolve > 0) {
@@ -1011,13 +1008,47 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
         }
         // adaptive number of cycles per problem (Section 2): check, then cycle
         std::vector<int32_t> host_active(ncls, 0);
+        std::vector<char> handed(ncls, 0);
         int iters = 0;
         for (int it = 0; it <= opts->max_cycles + 1; ++it) {
+            // classes down to a few slow problems whose rectangle fits in LDS:
+            // the rest of their adaptive loop runs in one kernel (all such
+            // classes together), continuing from their current iterates
+            const int handoff = opts->handoff >= 0 ? opts->handoff : g_handoff;
+            if (it > 0 && handoff > 0) {
+                // one launch per iterate buffer the handed classes are on
+                for (int buf = 0; buf < 2; ++buf) {
+                    size_t lds = 0;
+                    int64_t n = 0;
+                    for (int ci = 0; ci < ncls; ++ci) {
+                        const ClassPlan& C = SP.classes[ci];
+                        if (C.solve_in_tail || handed[ci] || host_active[ci] == 0 || host_active[ci] > handoff)
+                            continue;
+                        if (C.tail64_lds == 0 || C.tail64_lds > 160 * 1024 || i64[ci].cur[SP.L] != buf) continue;
+                        if (n == 0) cls.assign(SP.K, -1);
+                        for (int k = 0; k < C.K; ++k) cls[C.first + k] = 2 * C.ci + 1;
+                        lds = std::max(lds, C.tail64_lds);
+                        n += host_active[ci];
+                        handed[ci] = 1;
+                        host_active[ci] = 0;
+                    }
+                    if (n == 0) continue;
+                    HIPCHK(hipMemcpyAsync(ws + W.cls, cls.data(), sizeof(int32_t) * SP.K, hipMemcpyHostToDevice, s));
+                    TailSolve ad{opts->tol, opts->max_cycles, SP.L, pcycles, d_status, dead};
+                    hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls), 0,
+                                                       lds >= 24576 ? 256 : 64, lds, SP.K, X.probs, X.active, c,
+                                                       opts->mu, opts->nu1, opts->nu2, opts->omega, -1, it64.v[buf],
+                                                       a64b, d_kx, d_ky, chol, ad, s);
+                    if (e != hipSuccess) return fail(MSG_ERR_HIP, "handoff launch: %s", hipGetErrorString(e));
+                    // the device copy of cls must be consumed before the host vector is rebuilt
+                    HIPCHK(hipStreamSynchronize(s));
+                }
+            }
             HIPCHK(hipMemsetAsync(nact, 0, sizeof(int32_t) * ncls, s));
             iters = it;
             for (int ci = 0; ci < ncls; ++ci) {
                 const ClassPlan& C = SP.classes[ci];
-                if (C.solve_in_tail) continue;                 // solved above
+                if (C.solve_in_tail || handed[ci]) continue;   // solved in one kernel
                 if (it > 0 && host_active[ci] == 0) continue;   // this class has stopped
                 if (mixed) i32[ci].cur[SP.L] = 0;          // the check writes the FP32 top iterate (zero)
                 const double nb = (3.0 * grid_cells(c, C.pc, C.qc) + (double)((c << C.pc) + 1) * (c << C.qc) +

@@ -275,10 +275,16 @@ struct Where {
     int t;       // tile inside the grid
 };
 
+// Blocks are dealt to the 8 XCDs round-robin (block i on XCD i mod 8); the
+// grid is padded to a multiple of 8 and block i works on logical block
+// (i mod 8) * (n/8) + i/8, so each XCD gets one contiguous run of tiles and
+// neighbouring tiles share that XCD's L2.  Padding blocks get k = -1.
 __device__ __forceinline__ Where locate(const KLevel& L)
 {
     Where w;
-    const int b = blockIdx.x;
+    const int per = gridDim.x >> 3;
+    const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (b >= L.nblocks) { w.k = -1; w.gi = 0; w.t = 0; return w; }
     w.k = b / L.ntiles;
     int t = b - w.k * L.ntiles;
     int gi = 0;
@@ -306,7 +312,7 @@ k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ ac
     constexpr int H = 2 * NS;
     __shared__ T sv[kRbgsLds];
     const Where w = locate(L);
-    if (!active[w.k]) return;
+    if (w.k < 0 || !active[w.k]) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
     const int nx = G.nx, ny = G.ny, tw = G.tw, th = G.th;
@@ -363,7 +369,7 @@ k_restrict(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict_
            const T* __restrict__ KY)
 {
     const Where w = locate(L);
-    if (active && !active[w.k]) return;
+    if (w.k < 0 || (active && !active[w.k])) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
     const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
@@ -415,7 +421,7 @@ k_prolong(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__
           const T* __restrict__ Vc, T* __restrict__ Vf, const T* __restrict__ KX, const T* __restrict__ KY)
 {
     const Where w = locate(L);
-    if (!active[w.k]) return;
+    if (w.k < 0 || !active[w.k]) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
     const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
@@ -450,7 +456,7 @@ k_fmg(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ act
       const double* __restrict__ BP, const double* __restrict__ KX, const double* __restrict__ KY)
 {
     const Where w = locate(L);
-    if (!active[w.k]) return;
+    if (w.k < 0 || !active[w.k]) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
     const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
@@ -489,7 +495,7 @@ k_resnorm(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__
           float* __restrict__ B32)
 {
     const Where w = locate(L);
-    if (!active[w.k]) return;
+    if (w.k < 0 || !active[w.k]) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
     const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
@@ -571,7 +577,7 @@ k_ir_update(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict
             double* __restrict__ V, const float* __restrict__ V32)
 {
     const Where w = locate(L);
-    if (!active[w.k]) return;
+    if (w.k < 0 || !active[w.k]) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
     const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
@@ -589,6 +595,7 @@ k_snapshot(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict_
            const double* __restrict__ V, double* __restrict__ U, double* __restrict__ part)
 {
     const Where w = locate(L);
+    if (w.k < 0) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
     const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
@@ -625,6 +632,7 @@ k_rhs_top(KLevel L, const KProb* __restrict__ probs, double* __restrict__ BP, co
           const int64_t* __restrict__ rhs_base)
 {
     const Where w = locate(L);
+    if (w.k < 0) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
     const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
@@ -648,154 +656,162 @@ __device__ __forceinline__ void cell_ij(int idx, int nx, int sh, int& i, int& j)
     else { j = idx / nx; i = idx - j * nx; }
 }
 
-// The grid a lane works on inside one level, picked out of the (uniform)
-// descriptors by selection so that no lane indexes kernel arguments itself.
-struct TG {
-    int nx, ny, lv, lb, lkx, lky, sh;
-    int cx, cy, px, py;
+// One grid of a tail level as seen by one lane: its shape and where its
+// arrays sit in LDS (closed forms of the level layout, see KTail).
+struct TGrid {
+    int p, q, nx, ny, sh;      // sh = log2(nx) or -1
+    int v, b, d, x, y;         // LDS element offsets
 };
 
-// Slot s of a level whose grid k owns cnt(k) consecutive slots (half the
-// cells when `half` and nx is even -- one colour -- else all cells); returns
-// the grid and the index inside it.
-__device__ __forceinline__ TG level_pick(const KTail& TL, int g0, int g1, int s, bool half, int& local)
+__device__ __forceinline__ TGrid tgrid(const KTail& TL, const KTailLevel& L, int lev, int g)
 {
-    TG t{};
-    int base = 0;
-    local = 0;
-    for (int k = g0; k < g1; ++k) {
-        const KTailGrid& G = TL.g[k];
-        const int n = (half && !(G.nx & 1)) ? (G.nx * G.ny) >> 1 : G.nx * G.ny;
-        if (s >= base && s < base + n) {
-            t.nx = G.nx; t.ny = G.ny; t.lv = G.lv; t.lb = G.lb; t.lkx = G.lkx; t.lky = G.lky; t.sh = G.sh;
-            t.cx = G.cx; t.cy = G.cy; t.px = G.px; t.py = G.py;
-            local = s - base;
-        }
-        base += n;
-    }
-    return t;
+    TGrid G;
+    G.p = L.pmin + g;
+    G.q = lev - G.p;
+    G.nx = TL.c << G.p;
+    G.ny = TL.c << G.q;
+    G.sh = TL.lc >= 0 ? TL.lc + G.p : -1;
+    G.v = L.v0 + g * L.cells;
+    G.b = L.b0 + g * L.cells;
+    G.d = L.d0 + g * L.cells;
+    const int qmax = lev - L.pmin;
+    G.x = L.x0 + g * L.cells + TL.c * ((2 << qmax) - (2 << qmax >> g));
+    G.y = L.y0 + g * L.cells + (TL.c << L.pmin) * ((1 << g) - 1);
+    return G;
 }
 
-__device__ __forceinline__ int level_slots(const KTail& TL, int g0, int g1, bool half)
+// slot -> (grid, index inside the grid) when every grid owns `per` slots
+__device__ __forceinline__ void split_slot(int sl, int per, int psh, int& g, int& local)
 {
-    int n = 0;
-    for (int k = g0; k < g1; ++k) n += (half && !(TL.g[k].nx & 1)) ? (TL.g[k].nx * TL.g[k].ny) >> 1 : TL.g[k].nx * TL.g[k].ny;
-    return n;
+    if (psh >= 0) { g = sl >> psh; local = sl & (per - 1); }
+    else { g = sl / per; local = sl - g * per; }
 }
 
-// the same fields of a grid reached through a (uniform) tail index
-__device__ __forceinline__ TG tail_grid(const KTail& TL, int k)
-{
-    const KTailGrid& G = TL.g[k];
-    return TG{G.nx, G.ny, G.lv, G.lb, G.lkx, G.lky, G.sh, G.cx, G.cy, G.px, G.py};
-}
-
-// lane-selected fields of grid k (k may differ across lanes; its candidates
-// are the grids of one level, g0..g1-1)
-__device__ __forceinline__ TG pick_index(const KTail& TL, int g0, int g1, int k)
-{
-    TG t{};
-    for (int m = g0; m < g1; ++m)
-        if (m == k) t = tail_grid(TL, m);
-    return t;
-}
-
+// b - A v at (i,j) from LDS, conductances already scaled by 1/h^2 with the
+// wall faces doubled
 template <typename T>
-__device__ __forceinline__ void tail_update(const TG& G, T* sm, int i, int j)
+__device__ __forceinline__ T tresid(const T* sm, const TGrid& G, int i, int j)
 {
-    T* v = sm + G.lv;
+    const T* v = sm + G.v;
     const int off = j * G.nx + i;
-    const T ihx2 = T(G.nx) * T(G.nx), ihy2 = T(G.ny) * T(G.ny);
-    const Stencil<T> st = stencil_at(sm + G.lkx, sm + G.lky, G.nx, G.ny, i, j, ihx2, ihy2);
+    const T cW = sm[G.x + j * (G.nx + 1) + i], cE = sm[G.x + j * (G.nx + 1) + i + 1];
+    const T cS = sm[G.y + j * G.nx + i], cN = sm[G.y + (j + 1) * G.nx + i];
+    const T u = v[off];
     const T uW = i > 0 ? v[off - 1] : T(0);
     const T uE = i < G.nx - 1 ? v[off + 1] : T(0);
     const T uS = j > 0 ? v[off - G.nx] : T(0);
     const T uN = j < G.ny - 1 ? v[off + G.nx] : T(0);
-    const T num = sm[G.lb + off] + st.wW * uW + st.wE * uE + st.wS * uS + st.wN * uN;
-    v[off] = num / (st.wW + st.wE + st.wS + st.wN);
+    return sm[G.b + off] - (cW * (u - uW) + cE * (u - uE) + cS * (u - uS) + cN * (u - uN));
 }
 
-// every grid of level lev, sweeps red-then-black sweeps; the cells of one
-// colour of all the level's grids are spread over all lanes
+// every grid of level lev, `sweeps` red-then-black sweeps; one colour of all
+// the level's grids is spread over the lanes
 template <typename T, int NT>
 __device__ __forceinline__ void tail_smooth(const KTail& TL, T* sm, int lev, int sweeps)
 {
-    const int g0 = TL.level_begin[lev], g1 = TL.level_begin[lev + 1];
-    const int total = level_slots(TL, g0, g1, true);
+    const KTailLevel L = TL.lvl[lev];
+    const bool pairs = !(TL.c & 1);                 // nx even on every grid
+    const int per = pairs ? L.cells >> 1 : L.cells;
+    const int psh = L.csh >= 0 ? (pairs ? L.csh - 1 : L.csh) : -1;
+    const int total = per * L.ng;
     for (int s = 0; s < sweeps; ++s)
         for (int colour = 0; colour < 2; ++colour) {
             for (int sl = threadIdx.x; sl < total; sl += NT) {
-                int local;
-                const TG G = level_pick(TL, g0, g1, sl, true, local);
-                if (!(G.nx & 1)) {
-                    // pair k of row j holds (2k + ((colour + j) & 1), j)
-                    int k, j;
-                    cell_ij(local, G.nx >> 1, G.sh - 1, k, j);
-                    tail_update(G, sm, 2 * k + ((colour + j) & 1), j);
+                int g, local;
+                split_slot(sl, per, psh, g, local);
+                const TGrid G = tgrid(TL, L, lev, g);
+                int i, j;
+                if (pairs) {
+                    int k;
+                    cell_ij(local, G.nx >> 1, G.sh >= 1 ? G.sh - 1 : -1, k, j);
+                    i = 2 * k + ((colour + j) & 1);     // pair k of row j holds this colour's cell
                 } else {
-                    int i, j;
-                    cell_ij(local, G.nx, -1, i, j);
-                    if (((i + j) & 1) == colour) tail_update(G, sm, i, j);
+                    cell_ij(local, G.nx, G.sh, i, j);
+                    if (((i + j) & 1) != colour) continue;
                 }
+                T* v = sm + G.v;
+                const int off = j * G.nx + i;
+                const T cW = sm[G.x + j * (G.nx + 1) + i], cE = sm[G.x + j * (G.nx + 1) + i + 1];
+                const T cS = sm[G.y + j * G.nx + i], cN = sm[G.y + (j + 1) * G.nx + i];
+                const T uW = i > 0 ? v[off - 1] : T(0);
+                const T uE = i < G.nx - 1 ? v[off + 1] : T(0);
+                const T uS = j > 0 ? v[off - G.nx] : T(0);
+                const T uN = j < G.ny - 1 ? v[off + G.nx] : T(0);
+                v[off] = (sm[G.b + off] + cW * uW + cE * uE + cS * uS + cN * uN) * sm[G.d + off];
             }
             __syncthreads();
         }
 }
 
+// residual of level lev restricted to level lev-1 (eq. restriction); the
+// coarse iterate is zeroed
 template <typename T, int NT>
-__device__ __forceinline__ void tail_restrict(const KTail& TL, T* sm, int lev)   // level lev -> lev-1
+__device__ __forceinline__ void tail_restrict(const KTail& TL, T* sm, int lev)
 {
-    const int g0 = TL.level_begin[lev - 1], g1 = TL.level_begin[lev];
-    const int f0 = TL.level_begin[lev], f1 = TL.level_begin[lev + 1];
-    const int total = level_slots(TL, g0, g1, false);
+    const KTailLevel C = TL.lvl[lev - 1], F = TL.lvl[lev];
+    const int total = C.cells * C.ng;
     for (int sl = threadIdx.x; sl < total; sl += NT) {
-        int off;
-        const TG G = level_pick(TL, g0, g1, sl, false, off);
+        int g, off;
+        split_slot(sl, C.cells, C.csh, g, off);
+        const TGrid G = tgrid(TL, C, lev - 1, g);
         int I, J;
         cell_ij(off, G.nx, G.sh, I, J);
-        const bool hx = G.px >= 0, hy = G.py >= 0;
+        const bool hx = G.p + 1 <= TL.pc, hy = G.q + 1 <= TL.qc;
         T rx = T(0), ry = T(0);
         if (hx) {
-            const TG F = pick_index(TL, f0, f1, G.px);
-            const T ihx2 = T(F.nx) * T(F.nx), ihy2 = T(F.ny) * T(F.ny);
-            rx = T(0.5) * (residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, 2 * I, J, ihx2, ihy2) +
-                           residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, 2 * I + 1, J, ihx2, ihy2));
+            const TGrid P = tgrid(TL, F, lev, G.p + 1 - F.pmin);
+            rx = T(0.5) * (tresid(sm, P, 2 * I, J) + tresid(sm, P, 2 * I + 1, J));
         }
         if (hy) {
-            const TG F = pick_index(TL, f0, f1, G.py);
-            const T ihx2 = T(F.nx) * T(F.nx), ihy2 = T(F.ny) * T(F.ny);
-            ry = T(0.5) * (residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, I, 2 * J, ihx2, ihy2) +
-                           residual_at(sm + F.lv, sm + F.lb, sm + F.lkx, sm + F.lky, F.nx, F.ny, I, 2 * J + 1, ihx2, ihy2));
+            const TGrid P = tgrid(TL, F, lev, G.p - F.pmin);
+            ry = T(0.5) * (tresid(sm, P, I, 2 * J) + tresid(sm, P, I, 2 * J + 1));
         }
-        sm[G.lb + off] = (hx && hy) ? T(0.5) * rx + T(0.5) * ry : (hx ? rx : ry);
-        sm[G.lv + off] = T(0);
+        sm[G.b + off] = (hx && hy) ? T(0.5) * rx + T(0.5) * ry : (hx ? rx : ry);
+        sm[G.v + off] = T(0);
     }
     __syncthreads();
 }
 
+// eq. interpolation on level lev from level lev-1, weights from the scaled
+// conductances: an interior face contributes 2c to lambda, a wall face c
 template <typename T, int NT>
 __device__ __forceinline__ void tail_prolong(const KTail& TL, T* sm, int lev, T omega)
 {
-    const int g0 = TL.level_begin[lev], g1 = TL.level_begin[lev + 1];
-    const int c0 = TL.level_begin[lev - 1], c1 = TL.level_begin[lev];
-    const int total = level_slots(TL, g0, g1, false);
+    const KTailLevel F = TL.lvl[lev], C = TL.lvl[lev - 1];
+    const int total = F.cells * F.ng;
     for (int sl = threadIdx.x; sl < total; sl += NT) {
-        int off;
-        const TG G = level_pick(TL, g0, g1, sl, false, off);
+        int g, off;
+        split_slot(sl, F.cells, F.csh, g, off);
+        const TGrid G = tgrid(TL, F, lev, g);
         int i, j;
         cell_ij(off, G.nx, G.sh, i, j);
-        const bool hx = G.cx >= 0, hy = G.cy >= 0;
+        const bool hx = G.p > 0, hy = G.q > 0;
         T ex = T(0), ey = T(0);
-        if (hx) ex = linear_at(sm + pick_index(TL, c0, c1, G.cx).lv + j * (G.nx / 2), (int64_t)1, G.nx / 2, i);
-        if (hy) ey = linear_at(sm + pick_index(TL, c0, c1, G.cy).lv + i, (int64_t)G.nx, G.ny / 2, j);
+        if (hx) {
+            const TGrid X = tgrid(TL, C, lev - 1, G.p - 1 - C.pmin);
+            ex = linear_at(sm + X.v + j * (G.nx / 2), (int64_t)1, G.nx / 2, i);
+        }
+        if (hy) {
+            const TGrid Y = tgrid(TL, C, lev - 1, G.p - C.pmin);
+            ey = linear_at(sm + Y.v + i, (int64_t)G.nx, G.ny / 2, j);
+        }
         T corr;
         if (hx && hy) {
-            const T ka = kappa_x_at(sm + G.lkx, sm + G.lky, G.nx, G.ny, i, j, T(G.nx) * T(G.nx), T(G.ny) * T(G.ny));
+            const T cW = sm[G.x + j * (G.nx + 1) + i], cE = sm[G.x + j * (G.nx + 1) + i + 1];
+            const T cS = sm[G.y + j * G.nx + i], cN = sm[G.y + (j + 1) * G.nx + i];
+            T lx = (i == 0 ? cW : T(2) * cW) + (i == G.nx - 1 ? cE : T(2) * cE);
+            T ly = (j == 0 ? cS : T(2) * cS) + (j == G.ny - 1 ? cN : T(2) * cN);
+            if (j == 0) lx += cS;
+            if (j == G.ny - 1) lx += cN;
+            if (i == 0) ly += cW;
+            if (i == G.nx - 1) ly += cE;
+            const T a = lx * lx, b = ly * ly;
+            const T ka = a / (a + b);
             corr = ka * ex + (T(1) - ka) * ey;
         } else {
             corr = hx ? ex : ey;
         }
-        sm[G.lv + off] += omega * corr;
+        sm[G.v + off] += omega * corr;
     }
     __syncthreads();
 }
@@ -805,10 +821,10 @@ __device__ __forceinline__ void tail_prolong(const KTail& TL, T* sm, int lev, T 
 template <typename T>
 __device__ __forceinline__ void tail_coarse(const KTail& TL, T* sm, const double* Lc, int n)
 {
-    const KTailGrid& G = TL.g[0];
+    const KTailLevel L0 = TL.lvl[0];
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
-        double r = lane < n ? (double)sm[G.lb + lane] : 0.0;
+        double r = lane < n ? (double)sm[L0.b0 + lane] : 0.0;
         double y = 0.0;
         for (int k = 0; k < n; ++k) {                  // forward: L y = b
             const double yk = __shfl(r, k, 64) / Lc[k * n + k];
@@ -821,7 +837,7 @@ __device__ __forceinline__ void tail_coarse(const KTail& TL, T* sm, const double
             if (lane == k) x = xk;
             if (lane < k) s -= Lc[k * n + lane] * xk;
         }
-        if (lane < n) sm[G.lv + lane] = (T)x;
+        if (lane < n) sm[L0.v0 + lane] = (T)x;
     }
     __syncthreads();
 }
@@ -829,8 +845,8 @@ __device__ __forceinline__ void tail_coarse(const KTail& TL, T* sm, const double
 // count mu-cycles on the tail's top level; the recursion is unrolled with
 // the cycles still to run on each level kept two bits per level in a register
 template <typename T, int NT>
-__device__ __forceinline__ void tail_cycles(const KTail& TL, T* sm, const double* Lc, int n0, int mu, int nu1, int nu2, T omega,
-                            int count)
+__device__ __forceinline__ void tail_cycles(const KTail& TL, T* sm, const double* Lc, int n0, int mu, int nu1,
+                                            int nu2, T omega, int count)
 {
     uint64_t left = 0;
     auto get = [&](int l) { return (int)((left >> (2 * l)) & 3u); };
@@ -867,15 +883,15 @@ template <typename T, int NT>
 __device__ __forceinline__ void tail_norms(const KTail& TL, T* sm, double& rr, double& bb)
 {
     __shared__ double red[2][NT / 64];
-    const TG G = tail_grid(TL, TL.level_begin[TL.top]);
-    const T ihx2 = T(G.nx) * T(G.nx), ihy2 = T(G.ny) * T(G.ny);
+    const KTailLevel L = TL.lvl[TL.top];
+    const TGrid G = tgrid(TL, L, TL.top, 0);
     rr = 0.0;
     bb = 0.0;
-    for (int off = threadIdx.x; off < G.nx * G.ny; off += NT) {
+    for (int off = threadIdx.x; off < L.cells; off += NT) {
         int i, j;
         cell_ij(off, G.nx, G.sh, i, j);
-        const double r = (double)residual_at(sm + G.lv, sm + G.lb, sm + G.lkx, sm + G.lky, G.nx, G.ny, i, j, ihx2, ihy2);
-        const double b = (double)sm[G.lb + off];
+        const double r = (double)tresid(sm, G, i, j);
+        const double b = (double)sm[G.b + off];
         rr += r * r;
         bb += b * b;
     }
@@ -916,32 +932,57 @@ k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int ti
     double* Lc = reinterpret_cast<double*>(smem + TL.chol_off);
     const KProb pr = probs[k];
     const int n0 = c * c;
-    // stage in: coefficients of every tail grid, top-level iterate and rhs, factor
-    for (int g = 0; g < TL.ngrids; ++g) {
-        const KTailGrid& G = TL.g[g];
-        const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
-        const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
-        const int nfx = (G.nx + 1) * G.ny, nfy = G.nx * (G.ny + 1);
-        const int lkx = G.lkx, lky = G.lky;
-        for (int idx = threadIdx.x; idx < nfx; idx += NT) sm[lkx + idx] = kx[idx];
-        for (int idx = threadIdx.x; idx < nfy; idx += NT) sm[lky + idx] = ky[idx];
-        if (G.p + G.q == TL.top) {
-            const int n = G.nx * G.ny;
-            const int lv = G.lv, lb = G.lb;
-            const int64_t a = pr.arena_base + G.aoff;
-            for (int idx = threadIdx.x; idx < n; idx += NT) {
-                sm[lv + idx] = V[a + idx];
-                sm[lb + idx] = B[a + idx];
+    // stage in: face conductances (k/h^2, wall faces doubled) of every grid,
+    // the top level's iterates and right-hand sides, the coarsest factor
+    for (int lev = 0; lev <= TL.top; ++lev) {
+        const KTailLevel L = TL.lvl[lev];
+        for (int g = 0; g < L.ng; ++g) {
+            const TGrid G = tgrid(TL, L, lev, g);
+            const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
+            const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
+            const T ihx2 = T(G.nx) * T(G.nx), ihy2 = T(G.ny) * T(G.ny);
+            const int nfx = (G.nx + 1) * G.ny, nfy = G.nx * (G.ny + 1);
+            for (int idx = threadIdx.x; idx < nfx; idx += NT) {
+                const int i = idx % (G.nx + 1);
+                const T w = kx[idx] * ihx2;
+                sm[G.x + idx] = (i == 0 || i == G.nx) ? T(2) * w : w;
+            }
+            for (int idx = threadIdx.x; idx < nfy; idx += NT) {
+                const int j = idx / G.nx;
+                const T w = ky[idx] * ihy2;
+                sm[G.y + idx] = (j == 0 || j == G.ny) ? T(2) * w : w;
+            }
+            if (lev == TL.top) {
+                const int64_t a = pr.arena_base + TL.top_aoff[g];
+                for (int idx = threadIdx.x; idx < L.cells; idx += NT) {
+                    sm[G.v + idx] = V[a + idx];
+                    sm[G.b + idx] = B[a + idx];
+                }
             }
         }
     }
     for (int idx = threadIdx.x; idx < n0 * n0; idx += NT) Lc[idx] = chol[(int64_t)pr.sample * n0 * n0 + idx];
     __syncthreads();
+    // inverse diagonals
+    for (int lev = 0; lev <= TL.top; ++lev) {
+        const KTailLevel L = TL.lvl[lev];
+        for (int sl = threadIdx.x; sl < L.cells * L.ng; sl += NT) {
+            int g, off;
+            split_slot(sl, L.cells, L.csh, g, off);
+            const TGrid G = tgrid(TL, L, lev, g);
+            int i, j;
+            cell_ij(off, G.nx, G.sh, i, j);
+            const T cW = sm[G.x + j * (G.nx + 1) + i], cE = sm[G.x + j * (G.nx + 1) + i + 1];
+            const T cS = sm[G.y + j * G.nx + i], cN = sm[G.y + (j + 1) * G.nx + i];
+            sm[G.d + off] = T(1) / (cW + cE + cS + cN);
+        }
+    }
+    __syncthreads();
 
     if (count > 0) {
         tail_cycles<T, NT>(TL, sm, Lc, n0, mu, nu1, nu2, omega, count);
     } else {
-        int ncyc = 0;
+        int ncyc = ad.pcycles[k];                // cycles already run on this level
         for (;;) {
             double rr, bb;
             tail_norms<T, NT>(TL, sm, rr, bb);
@@ -964,12 +1005,13 @@ k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int ti
         if (threadIdx.x == 0) ad.pcycles[k] = ncyc;
     }
     // stage out the top level's iterates
-    for (int g = TL.level_begin[TL.top]; g < TL.level_begin[TL.top + 1]; ++g) {
-        const KTailGrid& G = TL.g[g];
-        const int n = G.nx * G.ny;
-        const int lv = G.lv;
-        const int64_t a = pr.arena_base + G.aoff;
-        for (int idx = threadIdx.x; idx < n; idx += NT) V[a + idx] = sm[lv + idx];
+    {
+        const KTailLevel L = TL.lvl[TL.top];
+        for (int g = 0; g < L.ng; ++g) {
+            const int64_t a = pr.arena_base + TL.top_aoff[g];
+            const int v0 = L.v0 + g * L.cells;
+            for (int idx = threadIdx.x; idx < L.cells; idx += NT) V[a + idx] = sm[v0 + idx];
+        }
     }
 }
 
@@ -1020,16 +1062,23 @@ hipError_t launch_chol(int S, int c, const SampleBase* bases, const double* kx, 
     return LAUNCH_CHECK();
 }
 
-static dim3 level_grid(const KLevel& L, int K) { return dim3((unsigned)((int64_t)L.ntiles * K)); }
+static dim3 level_grid(const KLevel& L, int K) { return dim3((unsigned)(((int64_t)L.ntiles * K + 7) / 8 * 8)); }
+
+static KLevel with_blocks(const KLevel& L, int K)
+{
+    KLevel c = L;
+    c.nblocks = L.ntiles * K;
+    return c;
+}
 
 template <typename T>
 hipError_t launch_rbgs(int ns, const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
                        const T* Vin, T* Vout, const T* B, const T* KX, const T* KY, hipStream_t st)
 {
     if (ns == 1)
-        hipLaunchKernelGGL((k_rbgs<T, 1>), level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, Vin, Vout, B, KX, KY);
+        hipLaunchKernelGGL((k_rbgs<T, 1>), level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, Vin, Vout, B, KX, KY);
     else
-        hipLaunchKernelGGL((k_rbgs<T, 2>), level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, Vin, Vout, B, KX, KY);
+        hipLaunchKernelGGL((k_rbgs<T, 2>), level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, Vin, Vout, B, KX, KY);
     return LAUNCH_CHECK();
 }
 
@@ -1038,9 +1087,9 @@ hipError_t launch_restrict(bool rhs, const KLevel& L, int K, const KProb* probs,
                            const T* Vf, T* Vc, T* B, const T* KX, const T* KY, hipStream_t st)
 {
     if (rhs)
-        hipLaunchKernelGGL((k_restrict<T, true>), level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, Vf, Vc, B, KX, KY);
+        hipLaunchKernelGGL((k_restrict<T, true>), level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, Vf, Vc, B, KX, KY);
     else
-        hipLaunchKernelGGL((k_restrict<T, false>), level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, Vf, Vc, B, KX, KY);
+        hipLaunchKernelGGL((k_restrict<T, false>), level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, Vf, Vc, B, KX, KY);
     return LAUNCH_CHECK();
 }
 
@@ -1048,7 +1097,7 @@ template <typename T>
 hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, T omega,
                           const T* Vc, T* Vf, const T* KX, const T* KY, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_prolong<T>), level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, omega, Vc, Vf, KX, KY);
+    hipLaunchKernelGGL((k_prolong<T>), level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, omega, Vc, Vf, KX, KY);
     return LAUNCH_CHECK();
 }
 
@@ -1075,7 +1124,7 @@ hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int th
 hipError_t launch_fmg(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, double* V, double* B,
                       const double* U, const double* BP, const double* KX, const double* KY, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fmg, level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, V, B, U, BP, KX, KY);
+    hipLaunchKernelGGL(k_fmg, level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, V, B, U, BP, KX, KY);
     return LAUNCH_CHECK();
 }
 
@@ -1083,7 +1132,7 @@ hipError_t launch_resnorm(const KLevel& L, int K, const KProb* probs, const int3
                           const double* B, const double* KX, const double* KY, double* part, float* V32, float* B32,
                           hipStream_t st)
 {
-    hipLaunchKernelGGL(k_resnorm, level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, c, V, B, KX, KY, part, V32, B32);
+    hipLaunchKernelGGL(k_resnorm, level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, V, B, KX, KY, part, V32, B32);
     return LAUNCH_CHECK();
 }
 
@@ -1099,14 +1148,14 @@ hipError_t launch_converge(int K, int ntiles, const KProb* probs, int32_t* activ
 hipError_t launch_ir_update(const KLevel& L, int K, const KProb* probs, const int32_t* active, double* V,
                             const float* V32, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ir_update, level_grid(L, K), dim3(kBlock), 0, st, L, probs, active, V, V32);
+    hipLaunchKernelGGL(k_ir_update, level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, V, V32);
     return LAUNCH_CHECK();
 }
 
 hipError_t launch_snapshot(const KLevel& L, int K, const KProb* probs, const int32_t* dead_level, int level, int c,
                            const double* V, double* U, double* part, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_snapshot, level_grid(L, K), dim3(kBlock), 0, st, L, probs, dead_level, level, c, V, U, part);
+    hipLaunchKernelGGL(k_snapshot, level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, dead_level, level, c, V, U, part);
     return LAUNCH_CHECK();
 }
 
@@ -1122,7 +1171,7 @@ hipError_t launch_qreduce(int K, int ntiles, int64_t cells, const KProb* probs, 
 hipError_t launch_rhs_top(const KLevel& L, int K, const KProb* probs, double* BP, const double* rhs,
                           const int64_t* rhs_base, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_rhs_top, level_grid(L, K), dim3(kBlock), 0, st, L, probs, BP, rhs, rhs_base);
+    hipLaunchKernelGGL(k_rhs_top, level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, BP, rhs, rhs_base);
     return LAUNCH_CHECK();
 }
 

@@ -54,7 +54,7 @@ class KernelStatsC(ctypes.Structure):
 class SolveOptsC(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
                 ("max_cycles", ctypes.c_int32), ("tol", ctypes.c_double), ("omega", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("tail_levels", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("tail_levels", ctypes.c_int32), ("handoff", ctypes.c_int32)]
 
 
 _lib = None
@@ -145,16 +145,17 @@ class SolveOpts:
     omega: float = 1.0
     precision: int = FP64
     tail_levels: int = -1
+    handoff: int = -1
 
     def c_struct(self):
         return SolveOptsC(self.mu, self.nu1, self.nu2, self.max_cycles, self.tol, self.omega, self.precision,
-                          self.tail_levels)
+                          self.tail_levels, self.handoff)
 
 
 def default_opts() -> SolveOpts:
     o = SolveOptsC()
     lib().msg_default_opts(ctypes.byref(o))
-    return SolveOpts(o.mu, o.nu1, o.nu2, o.max_cycles, o.tol, o.omega, o.precision, o.tail_levels)
+    return SolveOpts(o.mu, o.nu1, o.nu2, o.max_cycles, o.tol, o.omega, o.precision, o.tail_levels, o.handoff)
 
 
 class FieldSpec:

@@ -62,12 +62,14 @@ def test_config1_all_samples(handle):
     assert np.all(out["status"] == 0)
 
 
+@pytest.mark.parametrize("handoff", [0, -1])
 @pytest.mark.parametrize("max_cycles", [0, 1, 2])
-def test_unconverged_iterates_match_step_by_step(handle, max_cycles):
+def test_unconverged_iterates_match_step_by_step(handle, max_cycles, handoff):
     """Cycle caps of 0, 1, 2 stop every grid early, so the returned iterates
     expose the nested-iteration guess and single cycles, not just the
-    converged solution."""
-    opts = msg.SolveOpts(max_cycles=max_cycles)
+    converged solution (with the host loop alone, and with the handoff of
+    the last cycling problems to one kernel)."""
+    opts = msg.SolveOpts(max_cycles=max_cycles, handoff=handoff)
     for c, P, Q, spec in [(4, 3, 3, I.KL10), (2, 4, 3, I.separable(0.3, 0.03, 1.0, m=10))]:
         _check_batch(handle, c, [P] * 3, [Q] * 3, spec, opts, tol=1e-12)
 
@@ -79,9 +81,10 @@ def test_multi_tile_grids_step_by_step(handle, fields):
     the automatic tail) after one and two cycles."""
     spec = I.KL10 if fields == "kl10" else I.separable(0.3, 0.03, 1.0, m=10)
     for tail in (0, -1):
-        for mc in (1, 2):
-            opts = msg.SolveOpts(max_cycles=mc, tail_levels=tail)
-            _check_batch(handle, 4, [5, 2], [4, 6], spec, opts, tol=1e-12)
+        for mc in (1, 2, 3):
+            for handoff in (0, -1):
+                opts = msg.SolveOpts(max_cycles=mc, tail_levels=tail, handoff=handoff)
+                _check_batch(handle, 4, [5, 2], [4, 6], spec, opts, tol=1e-12)
 
 
 @pytest.mark.parametrize("tail", [0, 1, 3, -1])
@@ -89,6 +92,14 @@ def test_tail_depth_does_not_change_results(handle, tail):
     c, P, Q, spec = 2, 4, 4, I.KL10
     opts = msg.SolveOpts(tail_levels=tail, max_cycles=2)
     _check_batch(handle, c, [P] * 2, [Q] * 2, spec, opts, tol=1e-12)
+
+
+@pytest.mark.parametrize("handoff", [0, 1, -1])
+def test_converged_with_and_without_handoff(handle, handoff):
+    """Converged solves through the host loop only, with a handoff once a
+    single problem of a class is left, and with the default threshold."""
+    c, P, Q, spec = 2, 5, 4, I.separable(0.3, 0.03, 1.0, m=20)
+    _check_batch(handle, c, [P] * 6, [Q] * 6, spec, msg.SolveOpts(max_cycles=1000, handoff=handoff))
 
 
 def test_ragged_batch_and_batch_invariance(handle):
