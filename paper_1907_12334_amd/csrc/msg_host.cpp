@@ -151,7 +151,8 @@ struct ClassPlan {
     KTail tail64;
     size_t tail64_lds = 0;
     KLevel top1d;                  // the finest grid, 1-D tiles
-    std::vector<KLevel> rb, pro, res;   // per level: smoother tiles, prolongation, restriction into level-1
+    std::vector<KLevel> rb, rbc, pro, res;   // per level: smoother tiles (rbc: with the correction's
+                                             // children), prolongation, restriction into level-1
     int64_t part0 = 0;             // first partial-sum slot
     std::vector<int> samples;
 };
@@ -333,10 +334,17 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
                                                    : tail_layout<double>(c, pc, qc, C.tail_top, C.goff, C.tail);
             C.top1d = level_1d(c, pc, qc, L, C.goff, 1, qc);
             C.rb.resize(L + 1);
+            C.rbc.resize(L + 1);
             C.pro.resize(L + 1);
             C.res.resize(L + 1);
             for (int lev = 1; lev <= L; ++lev) {
                 C.rb[lev] = level_rbgs(c, pc, qc, lev, C.goff, H);
+                C.rbc[lev] = C.rb[lev];
+                for (int g = 0; g < C.rbc[lev].ngrids; ++g) {
+                    KGrid& G = C.rbc[lev].g[g];
+                    G.aoff_x = G.p > 0 ? C.goff[(G.p - 1) * (qc + 1) + G.q] : -1;
+                    G.aoff_y = G.q > 0 ? C.goff[G.p * (qc + 1) + G.q - 1] : -1;
+                }
                 C.pro[lev] = level_1d(c, pc, qc, lev, C.goff, 1, qc);
                 C.res[lev] = level_1d(c, pc, qc, lev - 1, C.goff, 2, qc);
             }
@@ -686,7 +694,8 @@ struct Ctx {
 
 // algorithmic bytes: data a kernel must touch at least once per active problem
 template <typename T>
-double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolong*/, int64_t K)
+double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolong, 3 correction children*/,
+                   int64_t K)
 {
     double per = 0.0;
     for (int g = 0; g < L.ngrids; ++g) {
@@ -699,9 +708,12 @@ double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolo
             per += 2 * cells;                                 // coarse b and v written
             if (G.aoff_x >= 0) per += 2 * (2 * cells) + ((2 * G.nx + 1.0) * G.ny + 2.0 * G.nx * (G.ny + 1));
             if (G.aoff_y >= 0) per += 2 * (2 * cells) + ((G.nx + 1.0) * 2 * G.ny + G.nx * (2.0 * G.ny + 1));
-        } else {
+        } else if (kind_rel == 2) {
             per += 2 * cells + faces;                         // fine v read and written, faces read
             if (G.aoff_x >= 0) per += cells / 2;
+            if (G.aoff_y >= 0) per += cells / 2;
+        } else {
+            if (G.aoff_x >= 0) per += cells / 2;              // coarse iterates of the children
             if (G.aoff_y >= 0) per += cells / 2;
         }
     }
@@ -752,25 +764,32 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, int lev, Iter<T>& it, T* B
         });
     };
     if (lev <= C.tail_top) return tail(1);
-    auto smooth = [&](int sweeps) -> msg_status {
+    // sweeps red-black sweeps on level lev, two fused per pass; with `corr`
+    // the first pass also applies the coarse-grid correction (eq. interpolation)
+    auto smooth = [&](int sweeps, bool corr) -> msg_status {
         while (sweeps > 0) {
             // tiles are planned for the configured fusion; one sweep fits the same tile
             const int ns = (sweeps >= 2 && g_fuse == 2) ? 2 : 1;
-            const KLevel& L = C.rb[lev];
+            const KLevel& L = corr ? C.rbc[lev] : C.rb[lev];
             const T* vin = it.now(lev);
             T* vout = it.v[1 - it.cur[lev]];
-            msg_status r = timed(X, MSG_KERNEL_SMOOTH, level_bytes<T>(L, 0, X.kact), [&] {
+            const T* vc = corr ? it.now(lev - 1) : nullptr;
+            // smoother bytes, plus the coarse iterates the correction reads
+            const double bytes = level_bytes<T>(L, 0, X.kact) + (corr ? level_bytes<T>(L, 3, X.kact) : 0.0);
+            msg_status r = timed(X, MSG_KERNEL_SMOOTH, bytes, [&] {
                 return chunked(L, C.K, [&](int k0, int kn) {
-                    return launch_rbgs<T>(ns, L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, X.s);
+                    return launch_rbgs<T>(ns, L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, vc, (T)X.o->omega,
+                                          X.s);
                 });
             });
             if (r != MSG_OK) return r;
             it.cur[lev] ^= 1;
             sweeps -= ns;
+            corr = false;
         }
         return MSG_OK;
     };
-    if ((st = smooth(X.o->nu1)) != MSG_OK) return st;
+    if ((st = smooth(X.o->nu1, false)) != MSG_OK) return st;
     {
         const KLevel& L = C.res[lev];
         const T* vf = it.now(lev);
@@ -789,18 +808,15 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, int lev, Iter<T>& it, T* B
         for (int m = 0; m < X.o->mu; ++m)
             if ((st = mu_cycle<T>(X, C, lev - 1, it, B, KX, KY)) != MSG_OK) return st;
     }
-    {
-        const KLevel& L = C.pro[lev];
-        const T* vc = it.now(lev - 1);
-        T* vf = it.now(lev);
-        st = timed(X, MSG_KERNEL_PROLONG, level_bytes<T>(L, 2, X.kact), [&] {
-            return chunked(L, C.K, [&](int k0, int kn) {
-                return launch_prolong<T>(L, kn, pr + k0, act + k0, X.c, (T)X.o->omega, vc, vf, KX, KY, X.s);
-            });
+    if (X.o->nu2 > 0) return smooth(X.o->nu2, true);      // correction fused into the first pass
+    const KLevel& L = C.pro[lev];
+    const T* vc = it.now(lev - 1);
+    T* vf = it.now(lev);
+    return timed(X, MSG_KERNEL_PROLONG, level_bytes<T>(L, 2, X.kact), [&] {
+        return chunked(L, C.K, [&](int k0, int kn) {
+            return launch_prolong<T>(L, kn, pr + k0, act + k0, X.c, (T)X.o->omega, vc, vf, KX, KY, X.s);
         });
-        if (st != MSG_OK) return st;
-    }
-    return smooth(X.o->nu2);
+    });
 }
 
 }  // namespace

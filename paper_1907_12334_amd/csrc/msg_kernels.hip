@@ -303,11 +303,31 @@ __device__ __forceinline__ Where locate(const KLevel& L)
 // read their halos from Vin while this tile writes, so an in-place update
 // would race.
 // ------------------------------------------------------------------------
-template <typename T, int NS>
+//
+// CORR: the pass starts from v + omega * (coarse-grid correction of eq.
+// interpolation), computed while the tile and its halo are loaded, so the
+// correction needs no pass of its own (same arithmetic as k_prolong).
+template <typename T>
+__device__ __forceinline__ T correction_at(const KGrid& G, const KProb& pr, int c, const T* __restrict__ Vc,
+                                           const T* __restrict__ kx, const T* __restrict__ ky, int i, int j)
+{
+    const int nx = G.nx, ny = G.ny;
+    const bool hx = G.aoff_x >= 0, hy = G.aoff_y >= 0;
+    T ex = T(0), ey = T(0);
+    if (hx) ex = linear_at(Vc + pr.arena_base + G.aoff_x + (int64_t)j * (nx / 2), (int64_t)1, nx / 2, i);
+    if (hy) ey = linear_at(Vc + pr.arena_base + G.aoff_y + i, (int64_t)nx, ny / 2, j);
+    if (hx && hy) {
+        const T ka = kappa_x_at(kx, ky, nx, ny, i, j, T(nx) * T(nx), T(ny) * T(ny));
+        return ka * ex + (T(1) - ka) * ey;
+    }
+    return hx ? ex : ey;
+}
+
+template <typename T, int NS, bool CORR>
 __global__ void __launch_bounds__(kBlock)
 k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c,
        const T* __restrict__ Vin, T* __restrict__ Vout, const T* __restrict__ B, const T* __restrict__ KX,
-       const T* __restrict__ KY)
+       const T* __restrict__ KY, const T* __restrict__ Vc, T omega)
 {
     constexpr int H = 2 * NS;
     __shared__ T sv[kRbgsLds];
@@ -327,7 +347,12 @@ k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ ac
 
     for (int idx = threadIdx.x; idx < RW * RH; idx += blockDim.x) {
         const int i = i0 - H + idx % RW, j = j0 - H + idx / RW;
-        sv[idx] = (i >= 0 && i < nx && j >= 0 && j < ny) ? v[(int64_t)j * nx + i] : T(0);
+        T x = T(0);
+        if (i >= 0 && i < nx && j >= 0 && j < ny) {
+            x = v[(int64_t)j * nx + i];
+            if (CORR) x += omega * correction_at(G, pr, c, Vc, kx, ky, i, j);
+        }
+        sv[idx] = x;
     }
     __syncthreads();
     for (int s = 0; s < NS; ++s) {
@@ -689,6 +714,23 @@ __device__ __forceinline__ void split_slot(int sl, int per, int psh, int& g, int
 
 // b - A v at (i,j) from LDS, conductances already scaled by 1/h^2 with the
 // wall faces doubled
+// The four neighbours of (i,j) read without branches: each load goes to a
+// valid cell of the grid (the centre where the neighbour is a wall) and the
+// wall value zero is selected afterwards, so all loads issue together.
+template <typename T>
+struct Nbr {
+    T W, E, S, N;
+};
+
+template <typename T>
+__device__ __forceinline__ Nbr<T> neighbours(const T* v, int off, int i, int j, int nx, int ny)
+{
+    const bool w = i > 0, e = i < nx - 1, s = j > 0, n = j < ny - 1;
+    const T xW = v[w ? off - 1 : off], xE = v[e ? off + 1 : off];
+    const T xS = v[s ? off - nx : off], xN = v[n ? off + nx : off];
+    return Nbr<T>{w ? xW : T(0), e ? xE : T(0), s ? xS : T(0), n ? xN : T(0)};
+}
+
 template <typename T>
 __device__ __forceinline__ T tresid(const T* sm, const TGrid& G, int i, int j)
 {
@@ -696,12 +738,9 @@ __device__ __forceinline__ T tresid(const T* sm, const TGrid& G, int i, int j)
     const int off = j * G.nx + i;
     const T cW = sm[G.x + j * (G.nx + 1) + i], cE = sm[G.x + j * (G.nx + 1) + i + 1];
     const T cS = sm[G.y + j * G.nx + i], cN = sm[G.y + (j + 1) * G.nx + i];
-    const T u = v[off];
-    const T uW = i > 0 ? v[off - 1] : T(0);
-    const T uE = i < G.nx - 1 ? v[off + 1] : T(0);
-    const T uS = j > 0 ? v[off - G.nx] : T(0);
-    const T uN = j < G.ny - 1 ? v[off + G.nx] : T(0);
-    return sm[G.b + off] - (cW * (u - uW) + cE * (u - uE) + cS * (u - uS) + cN * (u - uN));
+    const T u = v[off], bb = sm[G.b + off];
+    const Nbr<T> nb = neighbours(v, off, i, j, G.nx, G.ny);
+    return bb - (cW * (u - nb.W) + cE * (u - nb.E) + cS * (u - nb.S) + cN * (u - nb.N));
 }
 
 // every grid of level lev, `sweeps` red-then-black sweeps; one colour of all
@@ -733,11 +772,9 @@ __device__ __forceinline__ void tail_smooth(const KTail& TL, T* sm, int lev, int
                 const int off = j * G.nx + i;
                 const T cW = sm[G.x + j * (G.nx + 1) + i], cE = sm[G.x + j * (G.nx + 1) + i + 1];
                 const T cS = sm[G.y + j * G.nx + i], cN = sm[G.y + (j + 1) * G.nx + i];
-                const T uW = i > 0 ? v[off - 1] : T(0);
-                const T uE = i < G.nx - 1 ? v[off + 1] : T(0);
-                const T uS = j > 0 ? v[off - G.nx] : T(0);
-                const T uN = j < G.ny - 1 ? v[off + G.nx] : T(0);
-                v[off] = (sm[G.b + off] + cW * uW + cE * uE + cS * uS + cN * uN) * sm[G.d + off];
+                const T bb = sm[G.b + off], dd = sm[G.d + off];
+                const Nbr<T> nb = neighbours(v, off, i, j, G.nx, G.ny);
+                v[off] = (bb + cW * nb.W + cE * nb.E + cS * nb.S + cN * nb.N) * dd;
             }
             __syncthreads();
         }
@@ -1073,12 +1110,22 @@ static KLevel with_blocks(const KLevel& L, int K)
 
 template <typename T>
 hipError_t launch_rbgs(int ns, const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
-                       const T* Vin, T* Vout, const T* B, const T* KX, const T* KY, hipStream_t st)
+                       const T* Vin, T* Vout, const T* B, const T* KX, const T* KY, const T* Vc, T omega,
+                       hipStream_t st)
 {
-    if (ns == 1)
-        hipLaunchKernelGGL((k_rbgs<T, 1>), level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, Vin, Vout, B, KX, KY);
-    else
-        hipLaunchKernelGGL((k_rbgs<T, 2>), level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, Vin, Vout, B, KX, KY);
+    const dim3 grid = level_grid(L, K);
+    const KLevel Lb = with_blocks(L, K);
+    if (Vc) {
+        if (ns == 1)
+            hipLaunchKernelGGL((k_rbgs<T, 1, true>), grid, dim3(kBlock), 0, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+        else
+            hipLaunchKernelGGL((k_rbgs<T, 2, true>), grid, dim3(kBlock), 0, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+    } else {
+        if (ns == 1)
+            hipLaunchKernelGGL((k_rbgs<T, 1, false>), grid, dim3(kBlock), 0, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+        else
+            hipLaunchKernelGGL((k_rbgs<T, 2, false>), grid, dim3(kBlock), 0, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+    }
     return LAUNCH_CHECK();
 }
 
@@ -1191,9 +1238,11 @@ hipError_t launch_delta_q(int S, int max_grids, const int32_t* PQ, const int64_t
 }
 
 template hipError_t launch_rbgs<double>(int, const KLevel&, int, const KProb*, const int32_t*, int, const double*,
-                                        double*, const double*, const double*, const double*, hipStream_t);
+                                        double*, const double*, const double*, const double*, const double*, double,
+                                        hipStream_t);
 template hipError_t launch_rbgs<float>(int, const KLevel&, int, const KProb*, const int32_t*, int, const float*,
-                                       float*, const float*, const float*, const float*, hipStream_t);
+                                       float*, const float*, const float*, const float*, const float*, float,
+                                       hipStream_t);
 template hipError_t launch_restrict<double>(bool, const KLevel&, int, const KProb*, const int32_t*, int,
                                             const double*, double*, double*, const double*, const double*,
                                             hipStream_t);

@@ -43,9 +43,12 @@ hipError_t launch_field(const FieldArgs& A, int nsamples, const int32_t* samples
                         const double* xi, double* kx, double* ky, float* kx32, float* ky32, hipStream_t st);
 hipError_t launch_chol(int S, int c, const SampleBase* bases, const double* kx, const double* ky, double* chol,
                        hipStream_t st);
+// Vc != nullptr: the pass first adds omega * (coarse-grid correction from the
+// grids at L.g[].aoff_x / aoff_y of Vc) to the iterate (eq. interpolation)
 template <typename T>
 hipError_t launch_rbgs(int ns, const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
-                       const T* Vin, T* Vout, const T* B, const T* KX, const T* KY, hipStream_t st);
+                       const T* Vin, T* Vout, const T* B, const T* KX, const T* KY, const T* Vc, T omega,
+                       hipStream_t st);
 template <typename T>
 hipError_t launch_restrict(bool rhs, const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
                            const T* Vf, T* Vc, T* B, const T* KX, const T* KY, hipStream_t st);
