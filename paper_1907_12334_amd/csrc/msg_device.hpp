@@ -77,14 +77,16 @@ struct KLevel {
 // The grids of levels 0..top of a problem class held in LDS by the tail
 // kernel.  Every grid of level l of a class has c^2 2^l cells and grid index
 // p = pmin + g (q = l - p), so a level is described by a handful of numbers:
-// its grids' iterates, right-hand sides and inverse diagonals sit in blocks of
-// `cells` elements; its x-face conductances follow each other (grid g starts
-// at x0 + g*cells + c*(2^(qmax+1) - 2^(qmax+1-g)), qmax = l - pmin) and so do
-// its y-face conductances (y0 + g*cells + c*2^pmin*(2^g - 1)).
+// its grids' iterates and right-hand sides sit in blocks of `cells` elements;
+// its x-face conductances follow each other (grid g starts at
+// x0 + g*cells + c*(2^(qmax+1) - 2^(qmax+1-g)), qmax = l - pmin) and so do its
+// y-face conductances (y0 + g*cells + c*2^pmin*(2^g - 1)).  The conductance
+// runs of all levels come first, so that they form one image that can be
+// prepared once per F-cycle stage and copied in whole.
 struct KTailLevel {
     int32_t pmin, ng;          // grids p = pmin .. pmin+ng-1
     int32_t cells, csh;        // cells per grid and its log2 (or -1)
-    int32_t v0, b0, d0;        // LDS element offsets: iterates, right-hand sides, inverse diagonals
+    int32_t v0, b0;            // LDS element offsets: iterates, right-hand sides
     int32_t x0, y0;            // LDS element offsets of the face conductance runs
 };
 
@@ -94,9 +96,9 @@ struct KTail {
     int32_t top;               // level the cycles start on
     int32_t pc, qc;            // the class rectangle
     int32_t c, lc;             // coarsest cells per direction and its log2 (or -1)
-    int32_t lds_elems;         // LDS elements of type T (the Cholesky factor in doubles follows)
-    int32_t chol_off;          // byte offset of the coarsest factor in LDS
-    int32_t pad;
+    int32_t lds_elems;         // LDS elements of type T (the coarsest inverse in doubles follows)
+    int32_t chol_off;          // byte offset of the coarsest-grid inverse in LDS
+    int32_t nstat;             // elements [0, nstat): every face conductance run (a multiple of 4)
     KTailLevel lvl[kMaxTailLevels];
     int64_t top_aoff[kMaxLevelGrids];    // arena offsets of the top level's grids
 };

@@ -154,6 +154,7 @@ struct ClassPlan {
     std::vector<KLevel> rb, rbc, pro, res;   // per level: smoother tiles (rbc: with the correction's
                                              // children), prolongation, restriction into level-1
     int64_t part0 = 0;             // first partial-sum slot
+    int64_t tpack = -1;            // element offset of the class's tail conductance images, -1 if none
     std::vector<int> samples;
 };
 
@@ -163,6 +164,7 @@ struct StagePlan {
     int K = 0;
     int64_t arena_cells = 0;
     int64_t part_slots = 0;
+    int64_t tpack_elems = 0;       // tail conductance images of the classes cycled on the host
 };
 
 int64_t grid_cells(int c, int a, int b) { return ((int64_t)c << a) * ((int64_t)c << b); }
@@ -236,6 +238,8 @@ size_t tail_layout(int c, int pc, int qc, int m, const std::vector<int64_t>& gof
     TL.qc = qc;
     TL.c = c;
     TL.lc = (c & (c - 1)) == 0 ? __builtin_ctz(c) : -1;
+    // the face conductances of every level first (the image prepared per
+    // stage), then the iterates and right-hand sides
     int64_t off = 0;
     for (int lev = 0; lev <= m; ++lev) {
         KTailLevel& L = TL.lvl[lev];
@@ -245,15 +249,19 @@ size_t tail_layout(int c, int pc, int qc, int m, const std::vector<int64_t>& gof
         const int64_t cells = grid_cells(c, 0, lev);
         L.cells = (int)cells;
         L.csh = (cells & (cells - 1)) == 0 ? __builtin_ctzll(cells) : -1;
-        L.v0 = (int)off; off += cells * L.ng;
-        L.b0 = (int)off; off += cells * L.ng;
-        L.d0 = (int)off; off += cells * L.ng;
         L.x0 = (int)off;
         for (int g = 0; g < L.ng; ++g) off += cells + ((int64_t)c << (lev - pmin - g));      // (nx+1) ny
         L.y0 = (int)off;
         for (int g = 0; g < L.ng; ++g) off += cells + ((int64_t)c << (pmin + g));            // nx (ny+1)
         if (lev == m)
             for (int g = 0; g < L.ng; ++g) TL.top_aoff[g] = goff[(pmin + g) * (qc + 1) + (lev - pmin - g)];
+    }
+    off = (off + 3) / 4 * 4;
+    TL.nstat = (int)off;
+    for (int lev = 0; lev <= m; ++lev) {
+        KTailLevel& L = TL.lvl[lev];
+        L.v0 = (int)off; off += (int64_t)L.cells * L.ng;
+        L.b0 = (int)off; off += (int64_t)L.cells * L.ng;
     }
     if (off > (int64_t)1 << 30) return 0;
     TL.lds_elems = (int)off;
@@ -267,8 +275,10 @@ double tail_bytes(const KTail& TL, size_t elem)
     double per = 0.0;
     for (int lev = 0; lev <= TL.top; ++lev) {
         const KTailLevel& L = TL.lvl[lev];
-        per += (double)(TL.lvl[lev].y0 - TL.lvl[lev].x0);                 // x-faces
-        per += (double)((lev < TL.top ? TL.lvl[lev + 1].v0 : TL.lds_elems) - L.y0);   // y-faces
+        for (int g = 0; g < L.ng; ++g) {
+            const int p = L.pmin + g, q = lev - p;
+            per += 2.0 * L.cells + (double)(TL.c << p) + (double)(TL.c << q);   // (nx+1) ny + nx (ny+1)
+        }
         if (lev == TL.top) per += 3.0 * L.cells * L.ng;
     }
     return per * elem;
@@ -350,6 +360,10 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
             }
             C.part0 = SP.part_slots;
             SP.part_slots += (int64_t)C.top1d.ntiles * C.K;
+            if (!C.solve_in_tail && C.tail_lds > 0) {
+                C.tpack = SP.tpack_elems;
+                SP.tpack_elems += (int64_t)C.tail.nstat * C.K;
+            }
             C.ci = (int)SP.classes.size();
             SP.classes.push_back(std::move(C));
         }
@@ -360,13 +374,14 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
 // ---------------------------------------------------------------- workspace
 struct Ws {
     size_t bpyr, chol, a64v, a64v2, a64b, a32v, a32v2, a32b, part, active, pcycles, dead, nactive, sbase, gbase, rbase, probs,
-        pyrprobs, tails, cls, total;
+        pyrprobs, tails, cls, tpack, total;
 };
 
 Ws ws_layout(const BatchLayout& BL, const std::vector<StagePlan>& plans, bool mixed)
 {
-    int64_t arena = 0, parts = 0, probs = 0;
+    int64_t arena = 0, parts = 0, probs = 0, tpack = 0;
     for (const StagePlan& SP : plans) {
+        tpack = std::max(tpack, SP.tpack_elems);
         arena = std::max(arena, SP.arena_cells);
         parts = std::max(parts, SP.part_slots);
         probs = std::max<int64_t>(probs, SP.K);
@@ -395,6 +410,7 @@ Ws ws_layout(const BatchLayout& BL, const std::vector<StagePlan>& plans, bool mi
     w.pyrprobs = take(sizeof(KProb) * BL.S);
     w.tails = take(sizeof(KTail) * 2 * (kMaxIndex + 1));
     w.cls = take(sizeof(int32_t) * std::max<int64_t>(probs, 1));
+    w.tpack = take((mixed ? sizeof(float) : sizeof(double)) * std::max<int64_t>(tpack, 1));
     w.total = off;
     return w;
 }
@@ -690,6 +706,7 @@ struct Ctx {
     Profiler* prof;
     int64_t kact;       // problems of the current class still cycling
     const KTail* tails; // device: per class of the level, [2 ci] cycle tail, [2 ci + 1] whole-class tail
+    void* tpack;        // device: tail conductance images of the stage (type of the cycles)
 };
 
 // algorithmic bytes: data a kernel must touch at least once per active problem
@@ -754,12 +771,13 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, int lev, Iter<T>& it, T* B
     msg_status st;
     auto tail = [&](int count) {
         T* V = it.now(C.tail_top);
+        const T* pack = C.tpack >= 0 ? (const T*)X.tpack + C.tpack : nullptr;
         const double bytes = tail_bytes(C.tail, sizeof(T)) * (double)X.kact;
         return timed(X, MSG_KERNEL_TAIL, bytes, [&] {
             return chunked(C.top1d, C.K, [&](int k0, int kn) {
                 return launch_tail<T>(X.tails, nullptr, 2 * C.ci, 64, C.tail_lds, kn, pr + k0, act + k0, X.c, X.o->mu,
-                                      X.o->nu1, X.o->nu2, (T)X.o->omega, count, V, B, KX, KY, X.chol, TailSolve{},
-                                      X.s);
+                                      X.o->nu1, X.o->nu2, (T)X.o->omega, count, V, B, KX, KY,
+                                      pack ? pack + (int64_t)k0 * C.tail.nstat : nullptr, X.chol, TailSolve{}, X.s);
             });
         });
     };
@@ -868,7 +886,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
     int32_t* nact = (int32_t*)(ws + W.nactive);
     double* part = (double*)(ws + W.part);
 
-    // coarsest factors, one per sample
+    // coarsest-grid inverses, one per sample (from the Cholesky factor)
     {
         hipError_t e = launch_chol(S, c, d_bases, d_kx, d_ky, chol, s);
         if (e != hipSuccess) return fail(MSG_ERR_HIP, "cholesky launch: %s", hipGetErrorString(e));
@@ -944,6 +962,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
     std::vector<KTail> tails;
     std::vector<int32_t> cls;
     X.tails = (const KTail*)(ws + W.tails);
+    X.tpack = ws + W.tpack;
     for (const StagePlan& SP : plans) {
         const auto t_stage = std::chrono::steady_clock::now();
         // problems of this F-cycle level (the previous level's table copy has
@@ -973,6 +992,15 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
         {
             hipError_t e = launch_activate(SP.K, X.probs, dead, SP.L, X.active, pcycles, s);
             if (e != hipSuccess) return fail(MSG_ERR_HIP, "activate: %s", hipGetErrorString(e));
+        }
+        // the conductance images of the tails the host cycles will visit
+        for (const ClassPlan& C : SP.classes) {
+            if (C.tpack < 0) continue;
+            const KTail* tab = X.tails + 2 * C.ci;
+            const KProb* pr = X.probs + C.first;
+            hipError_t e = mixed ? launch_tail_pack<float>(tab, C.K, pr, c, d_kx32, d_ky32, (float*)X.tpack + C.tpack, s)
+                                 : launch_tail_pack<double>(tab, C.K, pr, c, d_kx, d_ky, (double*)X.tpack + C.tpack, s);
+            if (e != hipSuccess) return fail(MSG_ERR_HIP, "tail image: %s", hipGetErrorString(e));
         }
         // which buffer holds each level's current iterate, per class
         const int ncls = (int)SP.classes.size();
@@ -1014,7 +1042,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
                         hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls) + k0, 0, threads, lds,
                                                            kn, X.probs + k0, X.active + k0, c, opts->mu, opts->nu1,
                                                            opts->nu2, opts->omega, -1, it64.v[0], a64b, d_kx, d_ky,
-                                                           chol, ad, s);
+                                                           nullptr, chol, ad, s);
                         if (e != hipSuccess) return fail(MSG_ERR_HIP, "tail launch: %s", hipGetErrorString(e));
                     }
                     return MSG_OK;
@@ -1054,7 +1082,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
                     hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls), 0,
                                                        lds >= 24576 ? 256 : 64, lds, SP.K, X.probs, X.active, c,
                                                        opts->mu, opts->nu1, opts->nu2, opts->omega, -1, it64.v[buf],
-                                                       a64b, d_kx, d_ky, chol, ad, s);
+                                                       a64b, d_kx, d_ky, nullptr, chol, ad, s);
                     if (e != hipSuccess) return fail(MSG_ERR_HIP, "handoff launch: %s", hipGetErrorString(e));
                     // the device copy of cls must be consumed before the host vector is rebuilt
                     HIPCHK(hipStreamSynchronize(s));

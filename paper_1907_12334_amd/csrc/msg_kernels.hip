@@ -218,13 +218,15 @@ k_field(FieldArgs A, const int32_t* __restrict__ samples, const SampleBase* __re
 
 // ------------------------------------------------------------------------
 // Coarsest grid: dense Cholesky of A^(0,0) (c^2 unknowns) once per sample,
-// assembled column by column from the stencil; one wavefront per sample.
+// assembled column by column from the stencil, then the inverse from the
+// factor (L^-T L^-1, one column per lane); one wavefront per sample.  Every
+// coarsest solve of the cycles is then one small matrix-vector product.
 // ------------------------------------------------------------------------
 __global__ void __launch_bounds__(64)
 k_chol(int S, int c, const SampleBase* __restrict__ bases, const double* __restrict__ KX,
        const double* __restrict__ KY, double* __restrict__ chol)
 {
-    extern __shared__ double A[];                 // n*n
+    extern __shared__ double A[];                 // n*n factor, then n*n inverse columns
     const int s = blockIdx.x;
     if (s >= S) return;
     const int n = c * c;
@@ -260,10 +262,23 @@ k_chol(int S, int c, const SampleBase* __restrict__ bases, const double* __restr
         }
         __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int i = idx / n, j = idx % n;
-        L[idx] = j <= i ? A[idx] : 0.0;
+    // column j of A^-1: L y = e_j, then L^T x = y (lane j, n <= 64)
+    double* X = A + n * n;
+    const int j = threadIdx.x;
+    if (j < n) {
+        for (int i = 0; i < n; ++i) {
+            double t = i == j ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) t -= A[i * n + k] * X[k * n + j];
+            X[i * n + j] = t / A[i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double t = X[i * n + j];
+            for (int k = i + 1; k < n; ++k) t -= A[k * n + i] * X[k * n + j];
+            X[i * n + j] = t / A[i * n + i];
+        }
     }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) L[idx] = X[idx];
 }
 
 // ------------------------------------------------------------------------
@@ -669,7 +684,7 @@ k_rhs_top(KLevel L, const KProb* __restrict__ probs, double* __restrict__ BP, co
 // Tail: the mu-cycles of levels 0..top of one problem run inside one
 // wavefront, with every grid of those levels (iterate, right-hand side and
 // face coefficients) held in LDS; the coarsest grid is solved with the
-// sample's FP64 Cholesky factor.  The top level's iterate and right-hand
+// sample's FP64 inverse.  The top level's iterate and right-hand
 // side come from the arena and the iterate goes back there.  A single wave
 // per problem keeps every phase barrier local to the wave, and many small
 // workgroups per CU hide the latency of the short dependent phases.
@@ -685,7 +700,7 @@ __device__ __forceinline__ void cell_ij(int idx, int nx, int sh, int& i, int& j)
 // arrays sit in LDS (closed forms of the level layout, see KTail).
 struct TGrid {
     int p, q, nx, ny, sh;      // sh = log2(nx) or -1
-    int v, b, d, x, y;         // LDS element offsets
+    int v, b, x, y;            // LDS element offsets
 };
 
 __device__ __forceinline__ TGrid tgrid(const KTail& TL, const KTailLevel& L, int lev, int g)
@@ -698,7 +713,6 @@ __device__ __forceinline__ TGrid tgrid(const KTail& TL, const KTailLevel& L, int
     G.sh = TL.lc >= 0 ? TL.lc + G.p : -1;
     G.v = L.v0 + g * L.cells;
     G.b = L.b0 + g * L.cells;
-    G.d = L.d0 + g * L.cells;
     const int qmax = lev - L.pmin;
     G.x = L.x0 + g * L.cells + TL.c * ((2 << qmax) - (2 << qmax >> g));
     G.y = L.y0 + g * L.cells + (TL.c << L.pmin) * ((1 << g) - 1);
@@ -743,6 +757,46 @@ __device__ __forceinline__ T tresid(const T* sm, const TGrid& G, int i, int j)
     return bb - (cW * (u - nb.W) + cE * (u - nb.E) + cS * (u - nb.S) + cN * (u - nb.N));
 }
 
+// the face conductances of every tail grid of problem pr, k/h^2 with the wall
+// faces doubled, written to dst in the tail layout (LDS or the prepared image)
+template <typename T, int NT>
+__device__ __forceinline__ void tail_faces(const KTail& TL, const KProb& pr, int c, const T* __restrict__ KX,
+                                           const T* __restrict__ KY, T* dst)
+{
+    for (int lev = 0; lev <= TL.top; ++lev) {
+        const KTailLevel L = TL.lvl[lev];
+        for (int g = 0; g < L.ng; ++g) {
+            const TGrid G = tgrid(TL, L, lev, g);
+            const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
+            const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
+            const T ihx2 = T(G.nx) * T(G.nx), ihy2 = T(G.ny) * T(G.ny);
+            const int nfx = (G.nx + 1) * G.ny, nfy = G.nx * (G.ny + 1);
+            for (int idx = threadIdx.x; idx < nfx; idx += NT) {
+                const int i = idx % (G.nx + 1);
+                const T w = kx[idx] * ihx2;
+                dst[G.x + idx] = (i == 0 || i == G.nx) ? T(2) * w : w;
+            }
+            for (int idx = threadIdx.x; idx < nfy; idx += NT) {
+                const int j = idx / G.nx;
+                const T w = ky[idx] * ihy2;
+                dst[G.y + idx] = (j == 0 || j == G.ny) ? T(2) * w : w;
+            }
+        }
+    }
+}
+
+// The conductance image of the tail of every problem of a class, prepared
+// once per F-cycle stage: pack[k*nstat ...] is what k_tail copies into LDS.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_tail_pack(const KTail* __restrict__ table, const KProb* __restrict__ probs, int c, const T* __restrict__ KX,
+            const T* __restrict__ KY, T* __restrict__ pack)
+{
+    const KTail& TL = *table;
+    const int k = blockIdx.x;
+    tail_faces<T, kBlock>(TL, probs[k], c, KX, KY, pack + (int64_t)k * TL.nstat);
+}
+
 // every grid of level lev, `sweeps` red-then-black sweeps; one colour of all
 // the level's grids is spread over the lanes
 template <typename T, int NT>
@@ -772,9 +826,9 @@ __device__ __forceinline__ void tail_smooth(const KTail& TL, T* sm, int lev, int
                 const int off = j * G.nx + i;
                 const T cW = sm[G.x + j * (G.nx + 1) + i], cE = sm[G.x + j * (G.nx + 1) + i + 1];
                 const T cS = sm[G.y + j * G.nx + i], cN = sm[G.y + (j + 1) * G.nx + i];
-                const T bb = sm[G.b + off], dd = sm[G.d + off];
+                const T bb = sm[G.b + off];
                 const Nbr<T> nb = neighbours(v, off, i, j, G.nx, G.ny);
-                v[off] = (bb + cW * nb.W + cE * nb.E + cS * nb.S + cN * nb.N) * dd;
+                v[off] = (bb + cW * nb.W + cE * nb.E + cS * nb.S + cN * nb.N) / (cW + cE + cS + cN);
             }
             __syncthreads();
         }
@@ -853,28 +907,18 @@ __device__ __forceinline__ void tail_prolong(const KTail& TL, T* sm, int lev, T 
     __syncthreads();
 }
 
-// v^(0,0) = L^-T L^-1 b^(0,0) in FP64 by the first wavefront, lane k holding
-// unknown k (c^2 <= 64)
+// v^(0,0) = (A^(0,0))^-1 b^(0,0) in FP64, lane k computing unknown k (c^2 <= 64)
+// from the sample's inverse
 template <typename T>
-__device__ __forceinline__ void tail_coarse(const KTail& TL, T* sm, const double* Lc, int n)
+__device__ __forceinline__ void tail_coarse(const KTail& TL, T* sm, const double* Ai, int n)
 {
     const KTailLevel L0 = TL.lvl[0];
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        double r = lane < n ? (double)sm[L0.b0 + lane] : 0.0;
-        double y = 0.0;
-        for (int k = 0; k < n; ++k) {                  // forward: L y = b
-            const double yk = __shfl(r, k, 64) / Lc[k * n + k];
-            if (lane == k) y = yk;
-            if (lane > k && lane < n) r -= Lc[lane * n + k] * yk;
-        }
-        double s = y, x = 0.0;
-        for (int k = n - 1; k >= 0; --k) {             // backward: L^T x = y
-            const double xk = __shfl(s, k, 64) / Lc[k * n + k];
-            if (lane == k) x = xk;
-            if (lane < k) s -= Lc[k * n + lane] * xk;
-        }
-        if (lane < n) sm[L0.v0 + lane] = (T)x;
+    const int k = threadIdx.x;
+    if (k < n) {
+        const T* b = sm + L0.b0;
+        double x = 0.0;
+        for (int j = 0; j < n; ++j) x += Ai[k * n + j] * (double)b[j];
+        sm[L0.v0 + k] = (T)x;
     }
     __syncthreads();
 }
@@ -958,7 +1002,7 @@ __global__ void __launch_bounds__(NT)
 k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int tidx,
        const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c, int mu, int nu1,
        int nu2, T omega, int count, T* __restrict__ V, T* __restrict__ B, const T* __restrict__ KX,
-       const T* __restrict__ KY, const double* __restrict__ chol, TailSolve ad)
+       const T* __restrict__ KY, const T* __restrict__ pack, const double* __restrict__ chol, TailSolve ad)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int k = blockIdx.x;
@@ -969,51 +1013,29 @@ k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int ti
     double* Lc = reinterpret_cast<double*>(smem + TL.chol_off);
     const KProb pr = probs[k];
     const int n0 = c * c;
-    // stage in: face conductances (k/h^2, wall faces doubled) of every grid,
-    // the top level's iterates and right-hand sides, the coarsest factor
-    for (int lev = 0; lev <= TL.top; ++lev) {
-        const KTailLevel L = TL.lvl[lev];
+    // stage in: the face conductances of every grid (the prepared image, or
+    // computed here from the coefficients), the top level's iterates and
+    // right-hand sides, the coarsest inverse
+    if (pack) {
+        const uint4* src = reinterpret_cast<const uint4*>(pack + (int64_t)k * TL.nstat);
+        uint4* dst = reinterpret_cast<uint4*>(sm);
+        const int n16 = TL.nstat * (int)sizeof(T) / 16;
+        for (int idx = threadIdx.x; idx < n16; idx += NT) dst[idx] = src[idx];
+    } else {
+        tail_faces<T, NT>(TL, pr, c, KX, KY, sm);
+    }
+    {
+        const KTailLevel L = TL.lvl[TL.top];
         for (int g = 0; g < L.ng; ++g) {
-            const TGrid G = tgrid(TL, L, lev, g);
-            const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
-            const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
-            const T ihx2 = T(G.nx) * T(G.nx), ihy2 = T(G.ny) * T(G.ny);
-            const int nfx = (G.nx + 1) * G.ny, nfy = G.nx * (G.ny + 1);
-            for (int idx = threadIdx.x; idx < nfx; idx += NT) {
-                const int i = idx % (G.nx + 1);
-                const T w = kx[idx] * ihx2;
-                sm[G.x + idx] = (i == 0 || i == G.nx) ? T(2) * w : w;
-            }
-            for (int idx = threadIdx.x; idx < nfy; idx += NT) {
-                const int j = idx / G.nx;
-                const T w = ky[idx] * ihy2;
-                sm[G.y + idx] = (j == 0 || j == G.ny) ? T(2) * w : w;
-            }
-            if (lev == TL.top) {
-                const int64_t a = pr.arena_base + TL.top_aoff[g];
-                for (int idx = threadIdx.x; idx < L.cells; idx += NT) {
-                    sm[G.v + idx] = V[a + idx];
-                    sm[G.b + idx] = B[a + idx];
-                }
+            const int64_t a = pr.arena_base + TL.top_aoff[g];
+            const int v0 = L.v0 + g * L.cells, b0 = L.b0 + g * L.cells;
+            for (int idx = threadIdx.x; idx < L.cells; idx += NT) {
+                sm[v0 + idx] = V[a + idx];
+                sm[b0 + idx] = B[a + idx];
             }
         }
     }
     for (int idx = threadIdx.x; idx < n0 * n0; idx += NT) Lc[idx] = chol[(int64_t)pr.sample * n0 * n0 + idx];
-    __syncthreads();
-    // inverse diagonals
-    for (int lev = 0; lev <= TL.top; ++lev) {
-        const KTailLevel L = TL.lvl[lev];
-        for (int sl = threadIdx.x; sl < L.cells * L.ng; sl += NT) {
-            int g, off;
-            split_slot(sl, L.cells, L.csh, g, off);
-            const TGrid G = tgrid(TL, L, lev, g);
-            int i, j;
-            cell_ij(off, G.nx, G.sh, i, j);
-            const T cW = sm[G.x + j * (G.nx + 1) + i], cE = sm[G.x + j * (G.nx + 1) + i + 1];
-            const T cS = sm[G.y + j * G.nx + i], cN = sm[G.y + (j + 1) * G.nx + i];
-            sm[G.d + off] = T(1) / (cW + cE + cS + cN);
-        }
-    }
     __syncthreads();
 
     if (count > 0) {
@@ -1095,7 +1117,7 @@ hipError_t launch_field(const FieldArgs& A, int nsamples, const int32_t* samples
 hipError_t launch_chol(int S, int c, const SampleBase* bases, const double* kx, const double* ky, double* chol,
                        hipStream_t st)
 {
-    hipLaunchKernelGGL(k_chol, dim3(S), dim3(64), sizeof(double) * c * c * c * c, st, S, c, bases, kx, ky, chol);
+    hipLaunchKernelGGL(k_chol, dim3(S), dim3(64), 2 * sizeof(double) * c * c * c * c, st, S, c, bases, kx, ky, chol);
     return LAUNCH_CHECK();
 }
 
@@ -1151,8 +1173,8 @@ hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int3
 template <typename T>
 hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int threads, size_t lds_bytes, int K,
                        const KProb* probs, const int32_t* active, int c, int mu, int nu1, int nu2, T omega,
-                       int count, T* V, T* B, const T* KX, const T* KY, const double* chol, const TailSolve& ad,
-                       hipStream_t st)
+                       int count, T* V, T* B, const T* KX, const T* KY, const T* pack, const double* chol,
+                       const TailSolve& ad, hipStream_t st)
 {
     const void* fn = threads == 256 ? (const void*)k_tail<T, 256> : (const void*)k_tail<T, 64>;
     if (lds_bytes > 65536) {
@@ -1161,10 +1183,18 @@ hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int th
     }
     if (threads == 256)
         hipLaunchKernelGGL((k_tail<T, 256>), dim3(K), dim3(256), lds_bytes, st, tables, cls, tidx, probs, active, c,
-                           mu, nu1, nu2, omega, count, V, B, KX, KY, chol, ad);
+                           mu, nu1, nu2, omega, count, V, B, KX, KY, pack, chol, ad);
     else
         hipLaunchKernelGGL((k_tail<T, 64>), dim3(K), dim3(64), lds_bytes, st, tables, cls, tidx, probs, active, c,
-                           mu, nu1, nu2, omega, count, V, B, KX, KY, chol, ad);
+                           mu, nu1, nu2, omega, count, V, B, KX, KY, pack, chol, ad);
+    return LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t launch_tail_pack(const KTail* table, int K, const KProb* probs, int c, const T* KX, const T* KY, T* pack,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL((k_tail_pack<T>), dim3(K), dim3(kBlock), 0, st, table, probs, c, KX, KY, pack);
     return LAUNCH_CHECK();
 }
 
@@ -1254,9 +1284,14 @@ template hipError_t launch_prolong<float>(const KLevel&, int, const KProb*, cons
                                           float*, const float*, const float*, hipStream_t);
 template hipError_t launch_tail<double>(const KTail*, const int32_t*, int, int, size_t, int, const KProb*,
                                         const int32_t*, int, int, int, int, double, int, double*, double*,
-                                        const double*, const double*, const double*, const TailSolve&, hipStream_t);
+                                        const double*, const double*, const double*, const double*,
+                                        const TailSolve&, hipStream_t);
 template hipError_t launch_tail<float>(const KTail*, const int32_t*, int, int, size_t, int, const KProb*,
                                        const int32_t*, int, int, int, int, float, int, float*, float*, const float*,
-                                       const float*, const double*, const TailSolve&, hipStream_t);
+                                       const float*, const float*, const double*, const TailSolve&, hipStream_t);
+template hipError_t launch_tail_pack<double>(const KTail*, int, const KProb*, int, const double*, const double*,
+                                             double*, hipStream_t);
+template hipError_t launch_tail_pack<float>(const KTail*, int, const KProb*, int, const float*, const float*, float*,
+                                            hipStream_t);
 
 }  // namespace msg

@@ -60,8 +60,12 @@ hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int3
 template <typename T>
 hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int threads, size_t lds_bytes, int K,
                        const KProb* probs, const int32_t* active, int c, int mu, int nu1, int nu2, T omega,
-                       int count, T* V, T* B, const T* KX, const T* KY, const double* chol, const TailSolve& ad,
-                       hipStream_t st);
+                       int count, T* V, T* B, const T* KX, const T* KY, const T* pack, const double* chol,
+                       const TailSolve& ad, hipStream_t st);
+// the conductance image of the tail of each of K problems (pack: K * nstat elements)
+template <typename T>
+hipError_t launch_tail_pack(const KTail* table, int K, const KProb* probs, int c, const T* KX, const T* KY, T* pack,
+                            hipStream_t st);
 hipError_t launch_fmg(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, double* V, double* B,
                       const double* U, const double* BP, const double* KX, const double* KY, hipStream_t st);
 hipError_t launch_resnorm(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, const double* V,
