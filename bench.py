@@ -5,15 +5,21 @@ every face of every grid, the full-MSG solve of every sample to a relative
 residual of 1e-10 on all 64 grids, and the multi-index differences.  Inputs
 (the standard normal KL coefficients) are resident in HBM before timing.
 
-Prints one JSON line.  Beside the headline value it reports:
+Prints one JSON line.  Beside the headline value it reports, under "extra":
   * the plain per-sample FP64 GPU MSG (the same library, one sample per
     call) on a few samples, for the batched-vs-plain ratio;
-  * the mixed-precision path on a slice of the batch, with its error against
-    the FP64 result of the same samples;
-  * the smoother's achieved bandwidth from HIP events around its launches in
-    the timed region (roofline), and the oracle timed on host cores.
+  * the 1024x64 strongly anisotropic workload in mixed precision (FP32
+    cycles, FP64 refinement to 1e-8) and in FP64 on the same samples, with
+    the mixed result's error against the FP64 one, and the plain per-sample
+    FP64 rate on that workload;
+  * the ragged multi-index batch {l1+l2 <= 8} in one call;
+  * the request loop (Poisson arrivals, HBM-budget admission, continuous
+    batching) with p50/p99 latency;
+and the smoother's achieved bandwidth from HIP events around its launches in
+the timed region (roofline), and the oracle timed on host cores.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -34,11 +40,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--samples", type=int, default=None, help="batch size (default: the preset's 4096)")
     ap.add_argument("--plain-samples", type=int, default=2)
-    ap.add_argument("--mixed-samples", type=int, default=512)
     ap.add_argument("--cpu-samples", type=int, default=None)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-mixed", action="store_true")
+    ap.add_argument("--skip-ragged", action="store_true")
+    ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--mixed-workload-samples", type=int, default=None, help="default: the preset's 1024")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-profile", action="store_true", help="no HIP events around launches")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_rbgs.json"))
     return ap.parse_args()
@@ -143,33 +152,16 @@ def main():
         extra["batched_over_plain"] = round(value / plain, 1)
         log(f"plain per-sample FP64: {plain:.3f} samples/s")
 
-    # mixed precision on a slice, error against the FP64 result of those samples
+    del bufs                       # the other legs allocate their own buffers
+    torch.cuda.empty_cache()
     if not args.skip_mixed:
-        n = min(args.mixed_samples, S)
-        wm = w.subset(n)
-        bm = msg.Batch(wm.c, wm.P, wm.Q)
-        om = msg.SolveOpts(tol=1e-8, max_cycles=w.max_cycles, precision=msg.MIXED)
-        bufm = msg.Buffers(bm, om)
-        msg.run(h, wm.field, bm, om, xi[:n], bufm)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        msg.run(h, wm.field, bm, om, xi[:n], bufm)
-        torch.cuda.synchronize()
-        tm = time.perf_counter() - t0
-        u64 = bufs.u[: bufm.u.numel()]
-        lay = bufm.layout
-        # worst per-grid relative difference to the FP64 solve over the slice (sampled grids)
-        err = 0.0
-        uc, um = u64.cpu().numpy(), bufm.u.cpu().numpy()
-        for s in range(0, n, max(1, n // 16)):
-            a = grids_of(uc[lay["cell"][s]:lay["cell"][s + 1]], wm.c, wm.P[s], wm.Q[s])
-            b = grids_of(um[lay["cell"][s]:lay["cell"][s + 1]], wm.c, wm.P[s], wm.Q[s])
-            for x, y in zip(a, b):
-                err = max(err, float(np.linalg.norm(x - y) / np.linalg.norm(x)))
-        extra["mixed"] = {"value": round(n / tm, 2), "unit": "samples/s", "samples": n, "tol": 1e-8,
-                          "max_rel_err_vs_fp64": err,
-                          "converged": int(np.sum(bufm.status.cpu().numpy() == 0))}
-        log(f"mixed: {n / tm:.1f} samples/s, max rel err vs FP64 {err:.2e}")
+        extra["mixed_1024x64"] = mixed_leg(h, msg, I, torch, args)
+
+    if not args.skip_ragged:
+        extra["ragged"] = ragged_leg(h, msg, I, torch)
+
+    if not args.skip_serve:
+        extra["serving"] = serve_leg(msg, I, args)
 
     cpu = None
     if not args.skip_cpu:
@@ -210,6 +202,99 @@ def grids_of(u, c, P, Q):
             n = (c << p) * (c << q)
             out.append(u[off:off + n])
             off += n
+    return out
+
+
+def timed_run(h, msg, torch, w, opts, xi, bufs=None):
+    batch = msg.Batch(w.c, w.P, w.Q)
+    bufs = bufs or msg.Buffers(batch, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    msg.run(h, w.field, batch, opts, xi, bufs)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, bufs
+
+
+def mixed_leg(h, msg, I, torch, args):
+    """1024x64 workload: batched mixed precision and batched FP64 on the same
+    samples (each run once warm), the mixed error against FP64 over the
+    samples both converged, and plain per-sample FP64 on a few samples."""
+    w = I.config(4)
+    if args.mixed_workload_samples:
+        w = w.subset(args.mixed_workload_samples)
+    S = w.n_samples
+    xi = torch.tensor(w.xi(), dtype=torch.float64, device="cuda:0")
+    om = msg.SolveOpts(tol=w.ir_tol, max_cycles=w.max_cycles, precision=msg.MIXED)
+    od = msg.SolveOpts(tol=w.ir_tol, max_cycles=w.max_cycles)
+    w1 = w.subset(min(8, S))
+    timed_run(h, msg, torch, w1, om, xi[:w1.n_samples])          # warm the code paths
+    tm, bm = timed_run(h, msg, torch, w, om, xi)
+    log(f"mixed {w.name}: {S / tm:.1f} samples/s")
+    td, bd = timed_run(h, msg, torch, w, od, xi)
+    log(f"fp64 {w.name}: {S / td:.1f} samples/s")
+    lay = bm.layout
+    sm, sd = bm.status.cpu().numpy(), bd.status.cpu().numpy()
+    um, ud = bm.u.cpu().numpy(), bd.u.cpu().numpy()
+    qm, qd = bm.q.cpu().numpy(), bd.q.cpu().numpy()
+    dm, dd = bm.dq.cpu().numpy(), bd.dq.cpu().numpy()
+    err_u = err_q = err_dq = 0.0
+    both = np.flatnonzero((sm == 0) & (sd == 0))
+    for s in both:
+        c0, c1 = lay["cell"][s], lay["cell"][s + 1]
+        for x, y in zip(grids_of(ud[c0:c1], w.c, w.P[s], w.Q[s]), grids_of(um[c0:c1], w.c, w.P[s], w.Q[s])):
+            err_u = max(err_u, float(np.linalg.norm(x - y) / np.linalg.norm(x)))
+        g0, g1 = lay["grid"][s], lay["grid"][s + 1]
+        err_q = max(err_q, float(np.max(np.abs(qd[g0:g1] - qm[g0:g1]) / np.abs(qd[g0:g1]))))
+        scale = float(np.max(np.abs(dd[g0:g1])))
+        err_dq = max(err_dq, float(np.max(np.abs(dd[g0:g1] - dm[g0:g1]))) / scale)
+    # plain per-sample FP64 at the same tolerance
+    n = min(args.plain_samples, S)
+    t0 = time.perf_counter()
+    for s in range(n):
+        one = dataclasses.replace(w, name=f"{w.name}[{s}]", P=w.P[s:s + 1], Q=w.Q[s:s + 1])
+        timed_run(h, msg, torch, one, od, xi[s:s + 1])
+    plain = n / (time.perf_counter() - t0)
+    return {"workload": w.name, "samples": S, "tol": w.ir_tol,
+            "mixed_value": round(S / tm, 2), "fp64_batched_value": round(S / td, 2),
+            "plain_fp64_per_sample_value": round(plain, 3), "plain_samples": n, "unit": "samples/s",
+            "mixed_over_plain_fp64": round((S / tm) / plain, 1), "mixed_over_batched_fp64": round(td / tm, 2),
+            "converged_mixed": int(np.sum(sm == 0)), "converged_fp64": int(np.sum(sd == 0)),
+            "compared_samples": int(len(both)),
+            "max_rel_err_vs_fp64": {"u_per_grid_l2": err_u, "Q": err_q, "dQ_over_max_dQ": err_dq}}
+
+
+def ragged_leg(h, msg, I, torch):
+    """The ragged multi-index batch {l1+l2 <= 8} (32416 samples) in one call."""
+    w = I.config(3)
+    opts = msg.SolveOpts(tol=w.tol, max_cycles=w.max_cycles)
+    xi = torch.tensor(w.xi(), dtype=torch.float64, device="cuda:0")
+    _, bufs = timed_run(h, msg, torch, w, opts, xi)          # warm
+    t, bufs = timed_run(h, msg, torch, w, opts, xi, bufs)
+    log(f"ragged {w.name}: {w.n_samples / t:.0f} samples/s")
+    return {"workload": w.name, "samples": w.n_samples, "value": round(w.n_samples / t, 1), "unit": "samples/s",
+            "seconds": round(t, 3), "converged": int(np.sum(bufs.status.cpu().numpy() == 0)),
+            "max_cycles_per_grid": int(bufs.cycles.cpu().numpy().max())}
+
+
+def serve_leg(msg, I, args):
+    """Request loop: the Poisson trace at its rate (bounded to the first
+    requests) and the same requests at a rate below capacity."""
+    from paper_1907_12334_amd.serve import Engine, replay, summarize
+    opts = msg.SolveOpts(tol=1e-8, max_cycles=200, precision=msg.MIXED)
+    out = {"field": "KL-10", "c": 4, "precision": "mixed, refined to 1e-8",
+           "admission": "80% of free HBM, 3 small-request workers + 1 large-request worker"}
+    for name, n, rate in (("offered_5000_per_s", args.serve_requests, 5000.0),
+                          ("offered_400_per_s", max(1, args.serve_requests // 2), 400.0)):
+        t, P, Q, ids = I.request_trace(n, rate)
+        eng = Engine(I.KL10, 4, opts, workers=3, big_workers=1)
+        try:
+            reqs = replay(eng, t, P, Q, ids, timeout=600)
+        finally:
+            eng.close()
+        s = summarize(reqs, rate)
+        s["max_batches_in_flight"] = eng.max_inflight
+        out[name] = s
+        log(f"serving {name}: {s}")
     return out
 
 
