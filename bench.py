@@ -49,8 +49,47 @@ def parse():
     ap.add_argument("--mixed-workload-samples", type=int, default=None, help="default: the preset's 1024")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-profile", action="store_true", help="no HIP events around launches")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_rbgs.json"))
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_k_rbgs_se-256x256-s4096.md"))
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run one device copy of this many bytes (calibrates the HBM byte counters)")
     return ap.parse_args()
+
+
+def kernel_source_digest():
+    """sha256 of the HIP kernel source: traffic counters taken on other code do not apply."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1907_12334_amd", "csrc", "msg_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(path):
+    """HBM bytes per smoother launch from a counter summary (lines 'key: value'),
+    or None when it is absent or was measured on another kernel source."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    if kv.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes):
+    """One elementwise device copy of nbytes (read nbytes, write nbytes)."""
+    import torch
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.add(src, 0.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "kernel": "elementwise add(src, 0) -> dst, float64"}), flush=True)
 
 
 def log(*a):
@@ -59,6 +98,9 @@ def log(*a):
 
 def main():
     args = parse()
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus_requested": args.gpus}))
@@ -114,12 +156,7 @@ def main():
     launches, kms, kbytes = prof["smooth"]
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
     kernel_share = {k: (v[1] / 1000.0) / elapsed for k, v in prof.items()}
-    traffic = None
-    if os.path.exists(args.traffic):
-        try:
-            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = read_traffic(args.traffic)
     roofline = {
         "kernel": "k_rbgs<double,2> (red-black Gauss-Seidel, 2 fused sweeps)",
         "bound": "hbm",

@@ -70,6 +70,8 @@ struct KLevel {
     int32_t ngrids;
     int32_t ntiles;        // blocks per problem
     int32_t nblocks;       // real blocks of the launch (ntiles * problems); set by the launcher
+    int32_t bs;            // threads per block (0: kBlock); a 1-D tile is bs consecutive cells
+    int32_t lds;           // smoother: LDS elements of the largest tile with its halo
     int32_t pad;
     KGrid g[kMaxLevelGrids];
 };

@@ -124,15 +124,20 @@ int g_handoff = 1024;        // hand a class's last cycling problems to one kern
 int g_solve_lds = 65536;     // LDS budget under which a class is solved entirely in one kernel
 bool g_debug_stages = false; // per-level timing on stderr
 
+// Smoother tile of a grid: up to 64 cells wide and 1024 cells in all, its
+// halo (H cells towards a neighbouring tile, one cell of wall where the tile
+// spans the grid) fitting kRbgsLds elements.
 void rbgs_tile(int nx, int ny, int H, int& tw, int& th)
 {
     tw = std::min(nx, 64);
+    const int Hx = tw < nx ? H : 1;
+    auto region = [&](int t) { return (tw + 2 * Hx) * (t + 2 * (t < ny ? H : 1)); };
     th = 1;
-    while (th * 2 <= ny && tw * th * 2 <= 1024 && (tw + 2 * H) * (th * 2 + 2 * H) <= kRbgsLds) th *= 2;
+    while (th * 2 <= ny && tw * th * 2 <= 1024 && region(th * 2) <= kRbgsLds) th *= 2;
     if (th < ny && th * 2 > ny) {
         // non-power-of-two heights: take the largest fitting height
         int t = ny;
-        while (t > th && (tw * t > 1024 || (tw + 2 * H) * (t + 2 * H) > kRbgsLds)) --t;
+        while (t > th && (tw * t > 1024 || region(t) > kRbgsLds)) --t;
         th = std::max(th, t);
     }
 }
@@ -170,11 +175,16 @@ struct StagePlan {
 
 int64_t grid_cells(int c, int a, int b) { return ((int64_t)c << a) * ((int64_t)c << b); }
 
+// A level's grids in 1-D tiles of bs consecutive cells (bs = 0: kBlock; -1:
+// 64 when every grid of the level is small, else kBlock).
 KLevel level_1d(int c, int pc, int qc, int lev, const std::vector<int64_t>& goff, int rel /*0 none, 1 children, 2 parents*/,
-                int maxq)
+                int maxq, int bs = 0)
 {
     KLevel K;
     std::memset(&K, 0, sizeof K);
+    if (bs < 0) bs = grid_cells(c, 0, lev) < 1024 ? 64 : kBlock;
+    if (bs == 0) bs = kBlock;
+    K.bs = bs;
     int tiles = 0;
     for (int a = 0; a <= pc; ++a) {
         const int b = lev - a;
@@ -197,7 +207,7 @@ KLevel level_1d(int c, int pc, int qc, int lev, const std::vector<int64_t>& goff
             if (a + 1 <= pc) G.aoff_x = goff[(a + 1) * (maxq + 1) + b];
             if (b + 1 <= qc) G.aoff_y = goff[a * (maxq + 1) + b + 1];
         }
-        tiles += (int)ceil_div(grid_cells(c, a, b), kBlock);
+        tiles += (int)ceil_div(grid_cells(c, a, b), bs);
     }
     K.ntiles = tiles;
     return K;
@@ -207,7 +217,7 @@ KLevel level_rbgs(int c, int pc, int qc, int lev, const std::vector<int64_t>& go
 {
     KLevel K;
     std::memset(&K, 0, sizeof K);
-    int tiles = 0;
+    int tiles = 0, area = 0;
     for (int a = 0; a <= pc; ++a) {
         const int b = lev - a;
         if (b < 0 || b > qc) continue;
@@ -222,8 +232,12 @@ KLevel level_rbgs(int c, int pc, int qc, int lev, const std::vector<int64_t>& go
         G.aoff = goff[a * (qc + 1) + b];
         G.aoff_x = G.aoff_y = -1;
         tiles += G.tiles_x * (int)ceil_div(G.ny, G.th);
+        const int Hx = G.tiles_x > 1 ? H : 1, Hy = G.th < G.ny ? H : 1;
+        K.lds = std::max(K.lds, (G.tw + 2 * Hx) * (G.th + 2 * Hy));
+        area = std::max(area, G.tw * G.th);
     }
     K.ntiles = tiles;
+    K.bs = area <= 256 ? 64 : kBlock;     // small tiles: more, smaller workgroups per CU
     return K;
 }
 
@@ -356,8 +370,8 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
                     G.aoff_x = G.p > 0 ? C.goff[(G.p - 1) * (qc + 1) + G.q] : -1;
                     G.aoff_y = G.q > 0 ? C.goff[G.p * (qc + 1) + G.q - 1] : -1;
                 }
-                C.pro[lev] = level_1d(c, pc, qc, lev, C.goff, 1, qc);
-                C.res[lev] = level_1d(c, pc, qc, lev - 1, C.goff, 2, qc);
+                C.pro[lev] = level_1d(c, pc, qc, lev, C.goff, 1, qc, -1);
+                C.res[lev] = level_1d(c, pc, qc, lev - 1, C.goff, 2, qc, -1);
             }
             C.part0 = SP.part_slots;
             SP.part_slots += (int64_t)C.top1d.ntiles * C.K;

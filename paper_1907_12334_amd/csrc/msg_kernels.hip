@@ -338,14 +338,15 @@ __device__ __forceinline__ T correction_at(const KGrid& G, const KProb& pr, int 
     return hx ? ex : ey;
 }
 
-template <typename T, int NS, bool CORR>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int NS, bool CORR, int NT>
+__global__ void __launch_bounds__(NT)
 k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c,
        const T* __restrict__ Vin, T* __restrict__ Vout, const T* __restrict__ B, const T* __restrict__ KX,
        const T* __restrict__ KY, const T* __restrict__ Vc, T omega)
 {
     constexpr int H = 2 * NS;
-    __shared__ T sv[kRbgsLds];
+    extern __shared__ __align__(16) unsigned char smem_rb[];
+    T* sv = reinterpret_cast<T*>(smem_rb);
     const Where w = locate(L);
     if (w.k < 0 || !active[w.k]) return;
     const KGrid& G = L.g[w.gi];
@@ -358,10 +359,13 @@ k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ ac
     const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
     const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
     const T ihx2 = T(nx) * T(nx), ihy2 = T(ny) * T(ny);
-    const int RW = tw + 2 * H, RH = th + 2 * H;
+    // a direction in which the tile spans the whole grid has no neighbouring
+    // tile: one cell of zeros (the wall) is all the halo it needs
+    const int Hx = G.tiles_x > 1 ? H : 1, Hy = th < ny ? H : 1;
+    const int RW = tw + 2 * Hx, RH = th + 2 * Hy;
 
-    for (int idx = threadIdx.x; idx < RW * RH; idx += blockDim.x) {
-        const int i = i0 - H + idx % RW, j = j0 - H + idx / RW;
+    for (int idx = threadIdx.x; idx < RW * RH; idx += NT) {
+        const int i = i0 - Hx + idx % RW, j = j0 - Hy + idx / RW;
         T x = T(0);
         if (i >= 0 && i < nx && j >= 0 && j < ny) {
             x = v[(int64_t)j * nx + i];
@@ -373,15 +377,16 @@ k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ ac
     for (int s = 0; s < NS; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
             const int e = H - 1 - 2 * s - colour;            // extent of this half-sweep beyond the tile
-            const int EW = tw + 2 * e, EH = th + 2 * e, slots = (EW + 1) >> 1;
-            const int ib = i0 - e;
-            for (int idx = threadIdx.x; idx < slots * EH; idx += blockDim.x) {
-                const int lj = idx / slots, j = j0 - e + lj;
-                const int li = 2 * (idx - lj * slots) + ((colour - ib - j) & 1);
-                const int i = ib + li;
-                if (li >= EW || i < 0 || i >= nx || j < 0 || j >= ny) continue;
+            const int xa = max(i0 - e, 0), xb = min(i0 + tw + e, nx);
+            const int ya = max(j0 - e, 0), yb = min(j0 + th + e, ny);
+            const int EW = xb - xa, EH = yb - ya, slots = (EW + 1) >> 1;
+            for (int idx = threadIdx.x; idx < slots * EH; idx += NT) {
+                const int lj = idx / slots, j = ya + lj;
+                const int li = 2 * (idx - lj * slots) + ((colour - xa - j) & 1);
+                if (li >= EW) continue;
+                const int i = xa + li;
                 const Stencil<T> st = stencil_at(kx, ky, nx, ny, i, j, ihx2, ihy2);
-                const int r = (j - j0 + H) * RW + (i - i0 + H);
+                const int r = (j - j0 + Hy) * RW + (i - i0 + Hx);
                 const T num = b[(int64_t)j * nx + i] + st.wW * sv[r - 1] + st.wE * sv[r + 1] + st.wS * sv[r - RW] +
                               st.wN * sv[r + RW];
                 sv[r] = num / (st.wW + st.wE + st.wS + st.wN);
@@ -389,9 +394,9 @@ k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ ac
             __syncthreads();
         }
     }
-    for (int idx = threadIdx.x; idx < tw * th; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < tw * th; idx += NT) {
         const int li = idx % tw, lj = idx / tw, i = i0 + li, j = j0 + lj;
-        if (i < nx && j < ny) vout[(int64_t)j * nx + i] = sv[(lj + H) * RW + li + H];
+        if (i < nx && j < ny) vout[(int64_t)j * nx + i] = sv[(lj + Hy) * RW + li + Hx];
     }
 }
 
@@ -400,7 +405,7 @@ k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ ac
 // x-restricted residual of (p+1,q) and the y-restricted residual of (p,q+1),
 // one-sided where only one exists; the coarse iterate is zeroed.  With
 // RHS = true the fine quantity is the right-hand side itself (F-cycle).
-// One thread per coarse cell; 256 consecutive cells of one grid per block.
+// One thread per coarse cell; a block takes consecutive cells of one grid.
 // ------------------------------------------------------------------------
 template <typename T, bool RHS>
 __global__ void __launch_bounds__(kBlock)
@@ -412,7 +417,7 @@ k_restrict(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict_
     if (w.k < 0 || (active && !active[w.k])) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
-    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
     const int nx = G.nx, ny = G.ny;
     if (cell >= (int64_t)nx * ny) return;
     const int I = (int)(cell % nx), J = (int)(cell / nx);
@@ -464,7 +469,7 @@ k_prolong(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__
     if (w.k < 0 || !active[w.k]) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
-    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
     const int nx = G.nx, ny = G.ny;
     if (cell >= (int64_t)nx * ny) return;
     const int i = (int)(cell % nx), j = (int)(cell / nx);
@@ -499,7 +504,7 @@ k_fmg(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ act
     if (w.k < 0 || !active[w.k]) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
-    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
     const int nx = G.nx, ny = G.ny;
     if (cell >= (int64_t)nx * ny) return;
     const int i = (int)(cell % nx), j = (int)(cell / nx);
@@ -538,7 +543,7 @@ k_resnorm(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__
     if (w.k < 0 || !active[w.k]) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
-    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
     const int nx = G.nx, ny = G.ny;
     double rr = 0.0, bb = 0.0;
     if (cell < (int64_t)nx * ny) {
@@ -620,7 +625,7 @@ k_ir_update(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict
     if (w.k < 0 || !active[w.k]) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
-    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
     if (cell >= (int64_t)G.nx * G.ny) return;
     V[pr.arena_base + G.aoff + cell] += (double)V32[pr.arena_base + G.aoff + cell];
 }
@@ -638,7 +643,7 @@ k_snapshot(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict_
     if (w.k < 0) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
-    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
     const bool dead = dead_level[pr.sample] <= level;
     double u = 0.0, zero = 0.0;
     if (cell < (int64_t)G.nx * G.ny) {
@@ -675,7 +680,7 @@ k_rhs_top(KLevel L, const KProb* __restrict__ probs, double* __restrict__ BP, co
     if (w.k < 0) return;
     const KGrid& G = L.g[w.gi];
     const KProb pr = probs[w.k];
-    const int64_t cell = (int64_t)w.t * kBlock + threadIdx.x;
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
     if (cell >= (int64_t)G.nx * G.ny) return;
     BP[pr.arena_base + G.aoff + cell] = rhs ? rhs[rhs_base[pr.sample] + cell] : 1.0;
 }
@@ -1123,11 +1128,31 @@ hipError_t launch_chol(int S, int c, const SampleBase* bases, const double* kx, 
 
 static dim3 level_grid(const KLevel& L, int K) { return dim3((unsigned)(((int64_t)L.ntiles * K + 7) / 8 * 8)); }
 
+static unsigned threads_of(const KLevel& L) { return L.bs > 0 ? (unsigned)L.bs : (unsigned)kBlock; }
+
 static KLevel with_blocks(const KLevel& L, int K)
 {
     KLevel c = L;
     c.nblocks = L.ntiles * K;
     return c;
+}
+
+template <typename T, int NT>
+static void rbgs_dispatch(int ns, bool corr, dim3 grid, size_t lds, hipStream_t st, const KLevel& Lb, const KProb* probs,
+                          const int32_t* active, int c, const T* Vin, T* Vout, const T* B, const T* KX, const T* KY,
+                          const T* Vc, T omega)
+{
+    if (corr) {
+        if (ns == 1)
+            hipLaunchKernelGGL((k_rbgs<T, 1, true, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+        else
+            hipLaunchKernelGGL((k_rbgs<T, 2, true, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+    } else {
+        if (ns == 1)
+            hipLaunchKernelGGL((k_rbgs<T, 1, false, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+        else
+            hipLaunchKernelGGL((k_rbgs<T, 2, false, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+    }
 }
 
 template <typename T>
@@ -1137,17 +1162,12 @@ hipError_t launch_rbgs(int ns, const KLevel& L, int K, const KProb* probs, const
 {
     const dim3 grid = level_grid(L, K);
     const KLevel Lb = with_blocks(L, K);
-    if (Vc) {
-        if (ns == 1)
-            hipLaunchKernelGGL((k_rbgs<T, 1, true>), grid, dim3(kBlock), 0, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
-        else
-            hipLaunchKernelGGL((k_rbgs<T, 2, true>), grid, dim3(kBlock), 0, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
-    } else {
-        if (ns == 1)
-            hipLaunchKernelGGL((k_rbgs<T, 1, false>), grid, dim3(kBlock), 0, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
-        else
-            hipLaunchKernelGGL((k_rbgs<T, 2, false>), grid, dim3(kBlock), 0, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
-    }
+    const size_t lds = sizeof(T) * (size_t)L.lds;
+    if (L.bs == 64)
+        rbgs_dispatch<T, 64>(ns, Vc != nullptr, grid, lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+    else
+        rbgs_dispatch<T, kBlock>(ns, Vc != nullptr, grid, lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc,
+                                 omega);
     return LAUNCH_CHECK();
 }
 
@@ -1156,9 +1176,9 @@ hipError_t launch_restrict(bool rhs, const KLevel& L, int K, const KProb* probs,
                            const T* Vf, T* Vc, T* B, const T* KX, const T* KY, hipStream_t st)
 {
     if (rhs)
-        hipLaunchKernelGGL((k_restrict<T, true>), level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, Vf, Vc, B, KX, KY);
+        hipLaunchKernelGGL((k_restrict<T, true>), level_grid(L, K), dim3(threads_of(L)), 0, st, with_blocks(L, K), probs, active, c, Vf, Vc, B, KX, KY);
     else
-        hipLaunchKernelGGL((k_restrict<T, false>), level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, Vf, Vc, B, KX, KY);
+        hipLaunchKernelGGL((k_restrict<T, false>), level_grid(L, K), dim3(threads_of(L)), 0, st, with_blocks(L, K), probs, active, c, Vf, Vc, B, KX, KY);
     return LAUNCH_CHECK();
 }
 
@@ -1166,7 +1186,7 @@ template <typename T>
 hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, T omega,
                           const T* Vc, T* Vf, const T* KX, const T* KY, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_prolong<T>), level_grid(L, K), dim3(kBlock), 0, st, with_blocks(L, K), probs, active, c, omega, Vc, Vf, KX, KY);
+    hipLaunchKernelGGL((k_prolong<T>), level_grid(L, K), dim3(threads_of(L)), 0, st, with_blocks(L, K), probs, active, c, omega, Vc, Vf, KX, KY);
     return LAUNCH_CHECK();
 }
 
