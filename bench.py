@@ -152,26 +152,35 @@ def main():
     ms = 1000.0 * elapsed / args.steps
     log(f"converged {converged}/{S}, max cycles per grid {cycles.max()}, {value:.1f} samples/s")
 
-    # roofline of the dominant kernel (the smoother), from the timed region
-    launches, kms, kbytes = prof["smooth"]
-    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
-    kernel_share = {k: (v[1] / 1000.0) / elapsed for k, v in prof.items()}
+    # roofline of the dominant HBM-bound kernel (the smoother), from the timed region
     traffic = read_traffic(args.traffic)
-    roofline = {
-        "kernel": "k_rbgs<double,2> (red-black Gauss-Seidel, 2 fused sweeps)",
-        "bound": "hbm",
-        "achieved": round(achieved, 1) if achieved else None,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-        "traffic": traffic,
-        "launches": launches,
-        "avg_launch_us": round(1000.0 * kms / launches, 3) if launches else None,
-        "algorithmic_bytes_per_launch": kbytes / launches if launches else None,
-    }
-
-    extra = {"kernel_time_share": {k: round(v, 4) for k, v in kernel_share.items()},
-             "samples_converged": converged, "max_cycles_per_grid": int(cycles.max())}
+    roofline = roofline_of(prof["smooth"], SMOOTH_KERNEL, traffic)
+    kernel_share = {k: round((v[1] / 1000.0) / elapsed, 4) for k, v in prof.items() if not k.endswith("_stage")}
+    extra = {"kernel_time_share": kernel_share, "samples_converged": converged,
+             "max_cycles_per_grid": int(cycles.max()),
+             "roofline_stage_level": {
+                 "note": "launches on each F-cycle stage's own level (its largest, HBM-resident grids)",
+                 "smooth": roofline_of(prof["smooth_stage"], SMOOTH_KERNEL),
+                 "restrict": roofline_of(prof["restrict_stage"], "k_restrict<double> (residual + restriction)")}}
+    if not args.no_profile:
+        # the same step with every launch on one stream: kernel times without
+        # another class's kernels sharing the device
+        h.set_profiling(True)
+        o0 = dataclasses.replace(opts, overlap=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        msg.run(h, w.field, batch, o0, xi, bufs)
+        torch.cuda.synchronize()
+        t_iso = time.perf_counter() - t0
+        p0 = h.profile()
+        h.set_profiling(False)
+        extra["roofline_one_stream"] = {
+            "note": "one extra step with overlap = 0 (no concurrent classes), same inputs",
+            "step_s": round(t_iso, 3), "samples_per_s": round(S / t_iso, 2),
+            "smooth": roofline_of(p0["smooth"], SMOOTH_KERNEL),
+            "smooth_stage_level": roofline_of(p0["smooth_stage"], SMOOTH_KERNEL),
+            "restrict_stage_level": roofline_of(p0["restrict_stage"], "k_restrict<double> (residual + restriction)")}
+        log(f"one-stream step: {S / t_iso:.1f} samples/s, smoother {extra['roofline_one_stream']['smooth']['achieved']} GB/s")
 
     # plain per-sample FP64 GPU MSG: one sample per call, same kernels
     if not args.skip_plain:
@@ -229,6 +238,27 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+SMOOTH_KERNEL = "k_rbgs<double,2> (red-black Gauss-Seidel, 2 fused sweeps)"
+
+
+def roofline_of(stats, kernel, traffic=None):
+    """HBM roofline of one kernel kind from (launches, ms, algorithmic bytes)."""
+    launches, kms, kbytes = stats
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
+    return {
+        "kernel": kernel,
+        "bound": "hbm",
+        "achieved": round(achieved, 1) if achieved else None,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+        "traffic": traffic,
+        "launches": launches,
+        "avg_launch_us": round(1000.0 * kms / launches, 3) if launches else None,
+        "algorithmic_bytes_per_launch": kbytes / launches if launches else None,
+    }
 
 
 def grids_of(u, c, P, Q):

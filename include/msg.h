@@ -102,10 +102,15 @@ typedef struct {
     int32_t handoff;            /* -1 = automatic; 0 = never; n: once at most n problems of a
                                    class still cycle and its rectangle fits on chip, their
                                    remaining cycles run inside one kernel */
+    int32_t overlap;            /* -1 = automatic (1); 0 = every launch on `stream`; 1 = the
+                                   cycles of the classes of a level alternate over two streams
+                                   forked from and joined back to `stream`; 2 = as 1, each large
+                                   class also split in two sub-batches.  Results do not depend
+                                   on it. */
 } msg_solve_opts;
 
 /* Fill opts with the defaults: W(2,2), 50 cycles, tol 1e-10, omega 1, FP64,
- * automatic tail depth and handoff. */
+ * automatic tail depth, handoff and overlap. */
 void msg_default_opts(msg_solve_opts *opts);
 
 /* Create a handle bound to HIP device `device`.  Returns MSG_OK or MSG_ERR_HIP. */
@@ -171,17 +176,23 @@ msg_status mimc_delta_q(const msg_batch_desc *batch, const double *d_q, double *
 
 /* Per-kernel timing (measurement support).  While enabled, msg_solve_batch
  * records a pair of HIP events around every launch of each kernel kind on
- * the caller's stream and accumulates, per kind, the launches, the summed
+ * the stream it runs on and accumulates, per kind, the launches, the summed
  * event time and the algorithmic bytes of those launches (the data the
- * kernel must touch at least once for the problems still cycling: see the
- * design notes).  Enabling or disabling clears the totals. */
+ * kernel must touch at least once for the problems still cycling).  With
+ * overlap, launches of different classes may share the device, and their
+ * event times include that sharing.  The two *_STAGE kinds are subsets of
+ * SMOOTH and RESTRICT: the launches on the F-cycle stage's own level, whose
+ * grids are the largest of the stage and stream from HBM.  Enabling or
+ * disabling clears the totals. */
 enum {
     MSG_KERNEL_SMOOTH = 0,        /* red-black Gauss-Seidel passes */
     MSG_KERNEL_RESTRICT = 1,      /* residual + restriction (eq. restriction) */
     MSG_KERNEL_PROLONG = 2,       /* weighted correction (eq. interpolation) */
     MSG_KERNEL_TAIL = 3,          /* on-chip cycles of the lowest levels */
     MSG_KERNEL_RESIDUAL_NORM = 4, /* finest-grid residual norms */
-    MSG_KERNEL_KINDS = 5
+    MSG_KERNEL_SMOOTH_STAGE = 5,  /* SMOOTH launches on the stage's own level */
+    MSG_KERNEL_RESTRICT_STAGE = 6,/* RESTRICT launches from the stage's own level */
+    MSG_KERNEL_KINDS = 7
 };
 typedef struct {
     int64_t launches;

@@ -13,7 +13,8 @@ constexpr int kMaxLevelGrids = kMaxIndex + 1;
 constexpr int kMaxCosTerms = 64;
 constexpr int kMaxModes = 64;
 constexpr int kBlock = 256;            // threads per block of the level kernels
-constexpr int kRbgsLds = 2048;         // elements of the smoother's LDS tile (with halo)
+constexpr int kRbgsLds = 2048;         // LDS elements of a smoother tile (iterate with halo)
+constexpr int kRbgsLdsMax = 8192;      // upper bound of a tuned tile (64 KB in FP64)
 
 // ---- offsets of grid (p,q) inside a sample with finest index (P,Qs) ------
 // cells of the grids before (p,q): sum over a < p, b <= Qs of c2^a c2^b,

@@ -81,6 +81,7 @@ msg_status check_opts(const msg_solve_opts* o)
     if (o->precision != MSG_FP64 && o->precision != MSG_MIXED) return fail(MSG_ERR_ARG, "unknown precision");
     if (o->tail_levels < -1 || o->tail_levels > 8) return fail(MSG_ERR_ARG, "tail_levels must be -1..8");
     if (o->handoff < -1) return fail(MSG_ERR_ARG, "handoff must be >= -1");
+    if (o->overlap < -1 || o->overlap > 2) return fail(MSG_ERR_ARG, "overlap must be -1..2");
     return MSG_OK;
 }
 
@@ -118,26 +119,37 @@ BatchLayout make_layout(const msg_batch_desc* b)
 }
 
 // ---------------------------------------------------------------- plans
+constexpr int kSideStreams = 2;   // W-cycles of sub-batches run on these, forked from the caller's stream
+constexpr int kMinSplit = 256;    // smallest sub-batch worth a stream of its own
 int g_fuse = 2;              // smoother sweeps fused per pass (1 or 2)
+int g_rbgs_tw = 64;          // smoother tile: widest, most cells, LDS elements
+int g_rbgs_cells = 1024;
+int g_rbgs_lds = kRbgsLds;
 int g_tail_lds = 40960;      // LDS budget of the W-cycle tail (sets its depth)
 int g_handoff = 1024;        // hand a class's last cycling problems to one kernel at or below this count
 int g_solve_lds = 65536;     // LDS budget under which a class is solved entirely in one kernel
 bool g_debug_stages = false; // per-level timing on stderr
 
-// Smoother tile of a grid: up to 64 cells wide and 1024 cells in all, its
-// halo (H cells towards a neighbouring tile, one cell of wall where the tile
-// spans the grid) fitting kRbgsLds elements.
+// LDS elements of a smoother tile tw x th with halo H: its iterate with H
+// cells of halo towards a neighbouring tile and one wall cell where the tile
+// spans the grid.
+int rbgs_lds(int nx, int ny, int H, int tw, int th)
+{
+    const int Hx = tw < nx ? H : 1, Hy = th < ny ? H : 1;
+    return (tw + 2 * Hx) * (th + 2 * Hy);
+}
+
+// Smoother tile of a grid: up to g_rbgs_tw cells wide and g_rbgs_cells cells
+// in all, within g_rbgs_lds elements of LDS.
 void rbgs_tile(int nx, int ny, int H, int& tw, int& th)
 {
-    tw = std::min(nx, 64);
-    const int Hx = tw < nx ? H : 1;
-    auto region = [&](int t) { return (tw + 2 * Hx) * (t + 2 * (t < ny ? H : 1)); };
+    tw = std::min(nx, g_rbgs_tw);
     th = 1;
-    while (th * 2 <= ny && tw * th * 2 <= 1024 && region(th * 2) <= kRbgsLds) th *= 2;
+    while (th * 2 <= ny && tw * th * 2 <= g_rbgs_cells && rbgs_lds(nx, ny, H, tw, th * 2) <= g_rbgs_lds) th *= 2;
     if (th < ny && th * 2 > ny) {
         // non-power-of-two heights: take the largest fitting height
         int t = ny;
-        while (t > th && (tw * t > 1024 || region(t) > kRbgsLds)) --t;
+        while (t > th && (tw * t > g_rbgs_cells || rbgs_lds(nx, ny, H, tw, t) > g_rbgs_lds)) --t;
         th = std::max(th, t);
     }
 }
@@ -232,8 +244,7 @@ KLevel level_rbgs(int c, int pc, int qc, int lev, const std::vector<int64_t>& go
         G.aoff = goff[a * (qc + 1) + b];
         G.aoff_x = G.aoff_y = -1;
         tiles += G.tiles_x * (int)ceil_div(G.ny, G.th);
-        const int Hx = G.tiles_x > 1 ? H : 1, Hy = G.th < G.ny ? H : 1;
-        K.lds = std::max(K.lds, (G.tw + 2 * Hx) * (G.th + 2 * Hy));
+        K.lds = std::max(K.lds, rbgs_lds(G.nx, G.ny, H, G.tw, G.th));
         area = std::max(area, G.tw * G.th);
     }
     K.ntiles = tiles;
@@ -417,7 +428,7 @@ Ws ws_layout(const BatchLayout& BL, const std::vector<StagePlan>& plans, bool mi
     w.active = take(sizeof(int32_t) * std::max<int64_t>(probs, 1));
     w.pcycles = take(sizeof(int32_t) * std::max<int64_t>(probs, 1));
     w.dead = take(sizeof(int32_t) * BL.S);
-    w.nactive = take(sizeof(int32_t) * (kMaxIndex + 1));
+    w.nactive = take(sizeof(int32_t) * (kMaxIndex + 1) * kSideStreams);
     w.sbase = take(sizeof(SampleBase) * BL.S);
     w.gbase = take(sizeof(int64_t) * BL.S);
     w.rbase = take(sizeof(int64_t) * BL.S);
@@ -466,6 +477,7 @@ struct Profiler {
         hipEvent_t a, b;
         int kind;
         double bytes;
+        int also;          // a second kind the launch counts towards (a subset kind), or -1
     };
     std::vector<hipEvent_t> pool;
     std::vector<Rec> pending;
@@ -488,9 +500,12 @@ struct Profiler {
         for (Rec& r : pending) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
-                tot[r.kind].launches += 1;
-                tot[r.kind].milliseconds += ms;
-                tot[r.kind].bytes += r.bytes;
+                for (int k : {r.kind, r.also}) {
+                    if (k < 0) continue;
+                    tot[k].launches += 1;
+                    tot[k].milliseconds += ms;
+                    tot[k].bytes += r.bytes;
+                }
             }
             pool.push_back(r.a);
             pool.push_back(r.b);
@@ -509,9 +524,31 @@ struct Profiler {
     }
 };
 
+
 struct msg_handle_s {
     int device;
     Profiler prof;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork = nullptr, join[kSideStreams] = {};
+    ~msg_handle_s()
+    {
+        for (int k = 0; k < kSideStreams; ++k) {
+            if (side[k]) (void)hipStreamDestroy(side[k]);
+            if (join[k]) (void)hipEventDestroy(join[k]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+    }
+    // default-priority streams and their fork/join events, created on first use
+    hipError_t side_streams()
+    {
+        if (fork) return hipSuccess;
+        hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        for (int k = 0; k < kSideStreams && e == hipSuccess; ++k) {
+            e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
+        }
+        return e;
+    }
 };
 
 // ======================================================================
@@ -531,6 +568,7 @@ void msg_default_opts(msg_solve_opts* o)
     o->precision = MSG_FP64;
     o->tail_levels = -1;
     o->handoff = -1;
+    o->overlap = -1;
 }
 
 const char* msg_last_error(void) { return g_err.c_str(); }
@@ -551,6 +589,9 @@ msg_status msg_create(msg_handle* h, int device)
         if (const char* t = std::getenv("MSG_SOLVE_LDS")) g_solve_lds = std::max(0, std::atoi(t));
         if (const char* t = std::getenv("MSG_DEBUG_STAGES")) g_debug_stages = std::atoi(t) != 0;
         if (const char* t = std::getenv("MSG_HANDOFF")) g_handoff = std::max(0, std::atoi(t));
+        if (const char* t = std::getenv("MSG_RBGS_TW")) g_rbgs_tw = std::max(4, std::min(256, std::atoi(t)));
+        if (const char* t = std::getenv("MSG_RBGS_CELLS")) g_rbgs_cells = std::max(64, std::min(4096, std::atoi(t)));
+        if (const char* t = std::getenv("MSG_RBGS_LDS")) g_rbgs_lds = std::max(1024, std::min(kRbgsLdsMax, std::atoi(t)));
     });
     *h = new msg_handle_s{device};
     return MSG_OK;
@@ -731,7 +772,7 @@ struct Ctx {
 
 // algorithmic bytes: data a kernel must touch at least once per active problem
 template <typename T>
-double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolong, 3 correction children*/,
+double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolong, 3 correction children, 4 copy*/,
                    int64_t K)
 {
     double per = 0.0;
@@ -749,20 +790,22 @@ double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolo
             per += 2 * cells + faces;                         // fine v read and written, faces read
             if (G.aoff_x >= 0) per += cells / 2;
             if (G.aoff_y >= 0) per += cells / 2;
-        } else {
+        } else if (kind_rel == 3) {
             if (G.aoff_x >= 0) per += cells / 2;              // coarse iterates of the children
             if (G.aoff_y >= 0) per += cells / 2;
+        } else {
+            per += 2 * cells;                                 // iterate read and written
         }
     }
     return per * sizeof(T) * (double)K;
 }
 
 template <typename F>
-msg_status timed(const Ctx& X, int kind, double bytes, F&& f)
+msg_status timed(const Ctx& X, int kind, double bytes, F&& f, int also = -1)
 {
     Profiler* P = X.prof;
     if (!P || !P->on) return f();
-    Profiler::Rec r{P->get(), P->get(), kind, bytes};
+    Profiler::Rec r{P->get(), P->get(), kind, bytes, also};
     if (!r.a || !r.b) return fail(MSG_ERR_HIP, "event creation failed");
     HIPCHK(hipEventRecord(r.a, X.s));
     msg_status st = f();
@@ -783,18 +826,33 @@ struct Iter {
 
 // Algorithm MSG mu-cycle on level lev of class C, recursion on the host down
 // to the tail level, whose cycles run inside one workgroup per problem.
-template <typename T>
-msg_status mu_cycle(const Ctx& X, const ClassPlan& C, int lev, Iter<T>& it, T* B, const T* KX, const T* KY)
+// problems [k0, k0 + kn) of a class
+struct Span {
+    int k0, kn;
+};
+
+// a class's sub-batches: kSideStreams equal parts when overlap = 2 and it is large enough
+int nparts(const ClassPlan& C, int overlap) { return overlap == 2 && C.K >= 2 * kMinSplit ? kSideStreams : 1; }
+Span part_span(const ClassPlan& C, int overlap, int part)
 {
-    const KProb* pr = X.probs + C.first;
-    const int32_t* act = X.active + C.first;
+    const int n = nparts(C, overlap);
+    const int a = (int)((int64_t)C.K * part / n), b = (int)((int64_t)C.K * (part + 1) / n);
+    return Span{a, b - a};
+}
+
+template <typename T>
+msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, Iter<T>& it, T* B, const T* KX,
+                    const T* KY)
+{
+    const KProb* pr = X.probs + C.first + sp.k0;
+    const int32_t* act = X.active + C.first + sp.k0;
     msg_status st;
     auto tail = [&](int count) {
         T* V = it.now(C.tail_top);
-        const T* pack = C.tpack >= 0 ? (const T*)X.tpack + C.tpack : nullptr;
+        const T* pack = C.tpack >= 0 ? (const T*)X.tpack + C.tpack + (int64_t)sp.k0 * C.tail.nstat : nullptr;
         const double bytes = tail_bytes(C.tail, sizeof(T)) * (double)X.kact;
         return timed(X, MSG_KERNEL_TAIL, bytes, [&] {
-            return chunked(C.top1d, C.K, [&](int k0, int kn) {
+            return chunked(C.top1d, sp.kn, [&](int k0, int kn) {
                 return launch_tail<T>(X.tails, nullptr, 2 * C.ci, 64, C.tail_lds, kn, pr + k0, act + k0, X.c, X.o->mu,
                                       X.o->nu1, X.o->nu2, (T)X.o->omega, count, V, B, KX, KY,
                                       pack ? pack + (int64_t)k0 * C.tail.nstat : nullptr, X.chol, TailSolve{}, X.s);
@@ -803,25 +861,38 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, int lev, Iter<T>& it, T* B
     };
     if (lev <= C.tail_top) return tail(1);
     // sweeps red-black sweeps on level lev, two fused per pass; with `corr`
-    // the first pass also applies the coarse-grid correction (eq. interpolation)
+    // the first pass also applies the coarse-grid correction (eq. interpolation).
+    // ns = 0 is a copy pass (no sweep).
+    int flips = 0;
+    auto pass = [&](int ns, bool corr) -> msg_status {
+        const KLevel& L = corr ? C.rbc[lev] : C.rb[lev];
+        const T* vin = it.now(lev);
+        T* vout = it.v[1 - it.cur[lev]];
+        const T* vc = corr ? it.now(lev - 1) : nullptr;
+        // smoother bytes (a copy: read and write the iterate), plus the coarse
+        // iterates the correction reads
+        const double bytes = ns == 0 ? level_bytes<T>(L, 4, X.kact)
+                                     : level_bytes<T>(L, 0, X.kact) + (corr ? level_bytes<T>(L, 3, X.kact) : 0.0);
+        msg_status r = timed(
+            X, MSG_KERNEL_SMOOTH, bytes,
+            [&] {
+                return chunked(L, sp.kn, [&](int k0, int kn) {
+                    return launch_rbgs<T>(ns, L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, vc,
+                                          (T)X.o->omega, X.s);
+                });
+            },
+            lev == C.L ? MSG_KERNEL_SMOOTH_STAGE : -1);
+        if (r != MSG_OK) return r;
+        it.cur[lev] ^= 1;
+        ++flips;
+        return MSG_OK;
+    };
     auto smooth = [&](int sweeps, bool corr) -> msg_status {
         while (sweeps > 0) {
             // tiles are planned for the configured fusion; one sweep fits the same tile
             const int ns = (sweeps >= 2 && g_fuse == 2) ? 2 : 1;
-            const KLevel& L = corr ? C.rbc[lev] : C.rb[lev];
-            const T* vin = it.now(lev);
-            T* vout = it.v[1 - it.cur[lev]];
-            const T* vc = corr ? it.now(lev - 1) : nullptr;
-            // smoother bytes, plus the coarse iterates the correction reads
-            const double bytes = level_bytes<T>(L, 0, X.kact) + (corr ? level_bytes<T>(L, 3, X.kact) : 0.0);
-            msg_status r = timed(X, MSG_KERNEL_SMOOTH, bytes, [&] {
-                return chunked(L, C.K, [&](int k0, int kn) {
-                    return launch_rbgs<T>(ns, L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, vc, (T)X.o->omega,
-                                          X.s);
-                });
-            });
+            msg_status r = pass(ns, corr);
             if (r != MSG_OK) return r;
-            it.cur[lev] ^= 1;
             sweeps -= ns;
             corr = false;
         }
@@ -832,11 +903,14 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, int lev, Iter<T>& it, T* B
         const KLevel& L = C.res[lev];
         const T* vf = it.now(lev);
         T* vc = it.v[0];
-        st = timed(X, MSG_KERNEL_RESTRICT, level_bytes<T>(L, 1, X.kact), [&] {
-            return chunked(L, C.K, [&](int k0, int kn) {
-                return launch_restrict<T>(false, L, kn, pr + k0, act + k0, X.c, vf, vc, B, KX, KY, X.s);
-            });
-        });
+        st = timed(
+            X, MSG_KERNEL_RESTRICT, level_bytes<T>(L, 1, X.kact),
+            [&] {
+                return chunked(L, sp.kn, [&](int k0, int kn) {
+                    return launch_restrict<T>(false, L, kn, pr + k0, act + k0, X.c, vf, vc, B, KX, KY, X.s);
+                });
+            },
+            lev == C.L ? MSG_KERNEL_RESTRICT_STAGE : -1);
         if (st != MSG_OK) return st;
         it.cur[lev - 1] = 0;
     }
@@ -844,17 +918,26 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, int lev, Iter<T>& it, T* B
         if ((st = tail(X.o->mu)) != MSG_OK) return st;
     } else {
         for (int m = 0; m < X.o->mu; ++m)
-            if ((st = mu_cycle<T>(X, C, lev - 1, it, B, KX, KY)) != MSG_OK) return st;
+            if ((st = mu_cycle<T>(X, C, sp, lev - 1, it, B, KX, KY)) != MSG_OK) return st;
     }
-    if (X.o->nu2 > 0) return smooth(X.o->nu2, true);      // correction fused into the first pass
-    const KLevel& L = C.pro[lev];
-    const T* vc = it.now(lev - 1);
-    T* vf = it.now(lev);
-    return timed(X, MSG_KERNEL_PROLONG, level_bytes<T>(L, 2, X.kact), [&] {
-        return chunked(L, C.K, [&](int k0, int kn) {
-            return launch_prolong<T>(L, kn, pr + k0, act + k0, X.c, (T)X.o->omega, vc, vf, KX, KY, X.s);
+    if (X.o->nu2 > 0) {
+        if ((st = smooth(X.o->nu2, true)) != MSG_OK) return st;      // correction fused into the first pass
+    } else {
+        const KLevel& L = C.pro[lev];
+        const T* vc = it.now(lev - 1);
+        T* vf = it.now(lev);
+        st = timed(X, MSG_KERNEL_PROLONG, level_bytes<T>(L, 2, X.kact), [&] {
+            return chunked(L, sp.kn, [&](int k0, int kn) {
+                return launch_prolong<T>(L, kn, pr + k0, act + k0, X.c, (T)X.o->omega, vc, vf, KX, KY, X.s);
+            });
         });
-    });
+        if (st != MSG_OK) return st;
+    }
+    // The stage's own level keeps its iterate across cycles, and problems that
+    // have stopped are skipped by every pass: an odd number of buffer swaps
+    // per cycle would leave theirs behind, so a copy pass evens it out.
+    if (lev == C.L && (flips & 1)) return pass(0, false);
+    return MSG_OK;
 }
 
 }  // namespace
@@ -886,6 +969,8 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
                 return fail(MSG_ERR_UNSUPPORTED, "class (%d,%d) does not fit LDS; lower tail_levels", C.pc, C.qc);
         }
     HIPCHK(hipSetDevice(h->device));
+    const int ov = opts->overlap < 0 ? 1 : opts->overlap;
+    if (ov > 0) HIPCHK(h->side_streams());
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)d_ws;
     const int c = BL.c, S = BL.S;
@@ -1071,7 +1156,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
             }
         }
         // adaptive number of cycles per problem (Section 2): check, then cycle
-        std::vector<int32_t> host_active(ncls, 0);
+        std::vector<int32_t> host_active(ncls, 0), part_active((size_t)ncls * kSideStreams, 0);
         std::vector<char> handed(ncls, 0);
         int iters = 0;
         for (int it = 0; it <= opts->max_cycles + 1; ++it) {
@@ -1108,7 +1193,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
                     HIPCHK(hipStreamSynchronize(s));
                 }
             }
-            HIPCHK(hipMemsetAsync(nact, 0, sizeof(int32_t) * ncls, s));
+            HIPCHK(hipMemsetAsync(nact, 0, sizeof(int32_t) * ncls * kSideStreams, s));
             iters = it;
             for (int ci = 0; ci < ncls; ++ci) {
                 const ClassPlan& C = SP.classes[ci];
@@ -1126,33 +1211,70 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
                     });
                 });
                 if (st != MSG_OK) return st;
-                hipError_t e = launch_converge(C.K, C.top1d.ntiles, X.probs + C.first, X.active + C.first,
-                                               pcycles + C.first, dead, d_status, part, opts->tol, opts->max_cycles,
-                                               SP.L, nact + ci, s);
-                if (e != hipSuccess) return fail(MSG_ERR_HIP, "converge: %s", hipGetErrorString(e));
+                for (int pi = 0; pi < nparts(C, ov); ++pi) {
+                    const Span sp = part_span(C, ov, pi);
+                    const int a = C.first + sp.k0;
+                    hipError_t e = launch_converge(sp.kn, C.top1d.ntiles, X.probs + a, X.active + a, pcycles + a, dead,
+                                                   d_status, part, opts->tol, opts->max_cycles, SP.L,
+                                                   nact + ci * kSideStreams + pi, s);
+                    if (e != hipSuccess) return fail(MSG_ERR_HIP, "converge: %s", hipGetErrorString(e));
+                }
             }
-            HIPCHK(hipMemcpyAsync(host_active.data(), nact, sizeof(int32_t) * ncls, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(part_active.data(), nact, sizeof(int32_t) * ncls * kSideStreams,
+                                  hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
+            for (int ci = 0; ci < ncls; ++ci) {
+                host_active[ci] = 0;
+                for (int pi = 0; pi < kSideStreams; ++pi) host_active[ci] += part_active[ci * kSideStreams + pi];
+            }
             if (h->prof.on) h->prof.resolve();
             int64_t any = 0;
             for (int32_t a : host_active) any += a;
             if (any == 0) break;
+            // one W-cycle per class still cycling.  With overlap the classes
+            // (and, with overlap = 2, halves of large classes) alternate over
+            // two streams forked from the caller's, so that one's on-chip,
+            // latency-bound tail runs beside another's bandwidth-bound
+            // sweeps.  They touch disjoint problems; the halves of a class
+            // follow the same buffer sequence.
+            const bool fork = ov > 0;
+            if (fork) {
+                HIPCHK(hipEventRecord(h->fork, s));
+                for (int k = 0; k < kSideStreams; ++k) HIPCHK(hipStreamWaitEvent(h->side[k], h->fork, 0));
+            }
+            int rr = 0;
             for (int ci = 0; ci < ncls; ++ci) {
                 const ClassPlan& C = SP.classes[ci];
-                X.kact = host_active[ci];
-                if (X.kact == 0) continue;                 // every problem of this class has stopped
-                if (mixed) {
-                    st = mu_cycle<float>(X, C, SP.L, i32[ci], a32b, d_kx32, d_ky32);
+                if (host_active[ci] == 0) continue;        // every problem of this class has stopped
+                Iter<double> n64 = i64[ci];
+                Iter<float> n32 = i32[ci];
+                for (int pi = 0; pi < nparts(C, ov); ++pi) {
+                    Ctx Y = X;
+                    Y.kact = part_active[ci * kSideStreams + pi];
+                    if (Y.kact == 0) continue;             // this sub-batch has stopped
+                    const Span span = part_span(C, ov, pi);
+                    Y.s = fork ? h->side[rr++ % kSideStreams] : s;
+                    if (mixed) {
+                        n32 = i32[ci];
+                        st = mu_cycle<float>(Y, C, span, SP.L, n32, a32b, d_kx32, d_ky32);
+                        if (st != MSG_OK) return st;
+                        const float* e32 = n32.now(SP.L);
+                        st = chunked(C.top1d, span.kn, [&](int k0, int kn) {
+                            const int a = C.first + span.k0 + k0;
+                            return launch_ir_update(C.top1d, kn, X.probs + a, X.active + a, it64.v[0], e32, Y.s);
+                        });
+                    } else {
+                        n64 = i64[ci];
+                        st = mu_cycle<double>(Y, C, span, SP.L, n64, a64b, d_kx, d_ky);
+                    }
                     if (st != MSG_OK) return st;
-                    const float* e32 = i32[ci].now(SP.L);
-                    st = chunked(C.top1d, C.K, [&](int k0, int kn) {
-                        return launch_ir_update(C.top1d, kn, X.probs + C.first + k0, X.active + C.first + k0,
-                                                it64.v[0], e32, s);
-                    });
-                } else {
-                    st = mu_cycle<double>(X, C, SP.L, i64[ci], a64b, d_kx, d_ky);
                 }
-                if (st != MSG_OK) return st;
+                i64[ci] = n64;
+                i32[ci] = n32;
+            }
+            for (int k = 0; fork && k < kSideStreams; ++k) {
+                HIPCHK(hipEventRecord(h->join[k], h->side[k]));
+                HIPCHK(hipStreamWaitEvent(s, h->join[k], 0));
             }
         }
         // returned solutions of this level and their means

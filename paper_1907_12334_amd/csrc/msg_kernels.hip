@@ -319,6 +319,8 @@ __device__ __forceinline__ Where locate(const KLevel& L)
 // would race.
 // ------------------------------------------------------------------------
 //
+// NS = 0 copies the tile (a pass that keeps the buffer parity of a level).
+//
 // CORR: the pass starts from v + omega * (coarse-grid correction of eq.
 // interpolation), computed while the tile and its halo are loaded, so the
 // correction needs no pass of its own (same arithmetic as k_prolong).
@@ -1142,7 +1144,9 @@ static void rbgs_dispatch(int ns, bool corr, dim3 grid, size_t lds, hipStream_t 
                           const int32_t* active, int c, const T* Vin, T* Vout, const T* B, const T* KX, const T* KY,
                           const T* Vc, T omega)
 {
-    if (corr) {
+    if (ns == 0) {
+        hipLaunchKernelGGL((k_rbgs<T, 0, false, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+    } else if (corr) {
         if (ns == 1)
             hipLaunchKernelGGL((k_rbgs<T, 1, true, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
         else

@@ -24,8 +24,9 @@ FP64, MIXED = 0, 1
 EXPORTS = ("msg_default_opts", "msg_create", "msg_destroy", "msg_last_error", "msg_layout",
            "msg_workspace_size", "msg_sample_field", "msg_solve_batch", "mimc_delta_q",
            "msg_set_profiling", "msg_get_profile")
-KERNEL_SMOOTH, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_TAIL, KERNEL_RESIDUAL_NORM = range(5)
-KERNEL_NAMES = ("smooth", "restrict", "prolong", "tail", "residual_norm")
+(KERNEL_SMOOTH, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_TAIL, KERNEL_RESIDUAL_NORM, KERNEL_SMOOTH_STAGE,
+ KERNEL_RESTRICT_STAGE) = range(7)
+KERNEL_NAMES = ("smooth", "restrict", "prolong", "tail", "residual_norm", "smooth_stage", "restrict_stage")
 
 
 class MsgError(RuntimeError):
@@ -54,7 +55,8 @@ class KernelStatsC(ctypes.Structure):
 class SolveOptsC(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
                 ("max_cycles", ctypes.c_int32), ("tol", ctypes.c_double), ("omega", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("tail_levels", ctypes.c_int32), ("handoff", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("tail_levels", ctypes.c_int32), ("handoff", ctypes.c_int32),
+                ("overlap", ctypes.c_int32)]
 
 
 _lib = None
@@ -146,16 +148,18 @@ class SolveOpts:
     precision: int = FP64
     tail_levels: int = -1
     handoff: int = -1
+    overlap: int = -1
 
     def c_struct(self):
         return SolveOptsC(self.mu, self.nu1, self.nu2, self.max_cycles, self.tol, self.omega, self.precision,
-                          self.tail_levels, self.handoff)
+                          self.tail_levels, self.handoff, self.overlap)
 
 
 def default_opts() -> SolveOpts:
     o = SolveOptsC()
     lib().msg_default_opts(ctypes.byref(o))
-    return SolveOpts(o.mu, o.nu1, o.nu2, o.max_cycles, o.tol, o.omega, o.precision, o.tail_levels, o.handoff)
+    return SolveOpts(o.mu, o.nu1, o.nu2, o.max_cycles, o.tol, o.omega, o.precision, o.tail_levels, o.handoff,
+                     o.overlap)
 
 
 class FieldSpec:

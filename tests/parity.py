@@ -34,10 +34,10 @@ def per_sample(out, s):
     }
 
 
-def oracle_solve(c, P, Q, spec, xi, tol=1e-10, max_cycles=50, forced=None, rhs=None, omega=1.0):
+def oracle_solve(c, P, Q, spec, xi, tol=1e-10, max_cycles=50, forced=None, rhs=None, omega=1.0, mu=2, nu1=2, nu2=2):
     kx, ky = O.hierarchy_field(c, P, Q, spec.as_dict(), xi)
-    r = O.fmsg_solve(c, P, Q, kx, ky, O.opts(tol=tol, max_cycles=max_cycles, omega=omega), rhs_top=rhs,
-                     forced_cycles=forced)
+    o = O.opts(mu=mu, nu1=nu1, nu2=nu2, tol=tol, max_cycles=max_cycles, omega=omega)
+    r = O.fmsg_solve(c, P, Q, kx, ky, o, rhs_top=rhs, forced_cycles=forced)
     r["kx"], r["ky"] = kx, ky
     r["dq"] = O.delta_q(P, Q, r["q"])
     return r
@@ -54,16 +54,16 @@ def grid_errors(c, P, Q, u_gpu, u_ora):
     return worst
 
 
-def compare_sample(c, P, Q, spec, xi, g, tol=1e-10, max_cycles=50, rhs=None, omega=1.0):
+def compare_sample(c, P, Q, spec, xi, g, tol=1e-10, max_cycles=50, rhs=None, omega=1.0, mu=2, nu1=2, nu2=2):
     """Oracle on the same inputs; where a per-grid cycle count differs (a tie
     at the tolerance), the oracle is rerun at the GPU's counts so iterates are
     compared at equal counts.  Returns (u_err, q_err, dq_err, oracle result);
     the oracle's status is always that of its own adaptive run."""
-    ora = oracle_solve(c, P, Q, spec, xi, tol=tol, max_cycles=max_cycles, rhs=rhs, omega=omega)
+    kw = dict(tol=tol, max_cycles=max_cycles, rhs=rhs, omega=omega, mu=mu, nu1=nu1, nu2=nu2)
+    ora = oracle_solve(c, P, Q, spec, xi, **kw)
     if not np.array_equal(ora["cycles"], g["cycles"]):
         status = ora["status"]
-        ora = oracle_solve(c, P, Q, spec, xi, tol=tol, max_cycles=max_cycles, forced=g["cycles"], rhs=rhs,
-                           omega=omega)
+        ora = oracle_solve(c, P, Q, spec, xi, forced=g["cycles"], **kw)
         ora["status"] = status
     eu = grid_errors(c, P, Q, g["u"], ora["u"])
     eq = np.max(np.abs(g["q"] - ora["q"]) / np.maximum(np.abs(ora["q"]), 1e-300))

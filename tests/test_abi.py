@@ -82,6 +82,10 @@ def test_workspace_size_and_options():
         msg.workspace_size(b, msg.SolveOpts(mu=0))
     with pytest.raises(msg.MsgError):
         msg.workspace_size(b, msg.SolveOpts(tail_levels=9))
+    assert (o.tail_levels, o.handoff, o.overlap) == (-1, -1, -1)
+    for bad in (-2, 3):
+        with pytest.raises(msg.MsgError):
+            msg.workspace_size(b, msg.SolveOpts(overlap=bad))
 
 
 def test_entry_points_reject_null_handle_without_device_work():

@@ -38,7 +38,8 @@ def _check_batch(handle, c, P, Q, spec, opts, seed=I.BASE_SEED, tol=FP64_TOL, id
     for s in ids:
         g = PR.per_sample(out, s)
         eu, eq, edq, ora = PR.compare_sample(c, int(P[s]), int(Q[s]), spec, xi[s], g, tol=opts.tol,
-                                             max_cycles=opts.max_cycles, omega=opts.omega)
+                                             max_cycles=opts.max_cycles, omega=opts.omega, mu=opts.mu,
+                                             nu1=opts.nu1, nu2=opts.nu2)
         assert g["status"] == ora["status"], (s, g["status"], ora["status"])
         assert eu <= tol and eq <= tol and edq <= tol, (s, eu, eq, edq)
         worst = max(worst, eu)
@@ -100,6 +101,34 @@ def test_converged_with_and_without_handoff(handle, handoff):
     single problem of a class is left, and with the default threshold."""
     c, P, Q, spec = 2, 5, 4, I.separable(0.3, 0.03, 1.0, m=20)
     _check_batch(handle, c, [P] * 6, [Q] * 6, spec, msg.SolveOpts(max_cycles=1000, handoff=handoff))
+
+
+@pytest.mark.parametrize("mu,nu1,nu2", [(2, 3, 2), (2, 1, 0), (1, 2, 2), (2, 1, 1)])
+def test_cycle_kinds_and_sweep_counts(handle, mu, nu1, nu2):
+    """V- and W-cycles, odd and even smoothing counts (odd totals take the
+    stage level through an odd number of buffer swaps per cycle), with
+    problems of one class stopping at different cycles; host loop only."""
+    c, P, Q, spec = 2, 5, 4, I.separable(0.3, 0.03, 1.0, m=20)
+    opts = msg.SolveOpts(mu=mu, nu1=nu1, nu2=nu2, max_cycles=400, handoff=0)
+    out, _ = _check_batch(handle, c, [P] * 6, [Q] * 6, spec, opts)
+    cyc = out["cycles"].reshape(6, -1)
+    assert len({tuple(r) for r in cyc}) > 1        # the samples stopped at different counts
+
+
+def test_overlap_modes_give_identical_results(handle):
+    """Every launch on the caller's stream, classes over two streams, and
+    classes plus halves of large classes: bitwise the same answers."""
+    c, spec = 2, I.separable(0.3, 0.03, 1.0, m=20)
+    P, Q = [5] * 520 + [4] * 8, [4] * 520 + [5] * 8          # one class large enough to split
+    xi = I.draw_xi(spec.n_terms, range(len(P)))
+    outs = [PR.gpu_solve(c, P, Q, spec, xi, msg.SolveOpts(max_cycles=400, overlap=ov), handle=handle)
+            for ov in (0, 1, 2)]
+    for o in outs[1:]:
+        for k in ("u", "q", "dq", "cycles", "status"):
+            assert np.array_equal(o[k], outs[0][k]), k
+    g = PR.per_sample(outs[2], 0)
+    eu, eq, edq, ora = PR.compare_sample(c, P[0], Q[0], spec, xi[0], g, max_cycles=400)
+    assert g["status"] == ora["status"] and max(eu, eq, edq) <= FP64_TOL
 
 
 def test_ragged_batch_and_batch_invariance(handle):
