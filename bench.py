@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-ragged", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--skip-one-stream", action="store_true", help="no extra one-stream profiled step")
     ap.add_argument("--mixed-workload-samples", type=int, default=None, help="default: the preset's 1024")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-profile", action="store_true", help="no HIP events around launches")
@@ -162,7 +163,7 @@ def main():
                  "note": "launches on each F-cycle stage's own level (its largest, HBM-resident grids)",
                  "smooth": roofline_of(prof["smooth_stage"], SMOOTH_KERNEL),
                  "restrict": roofline_of(prof["restrict_stage"], "k_restrict<double> (residual + restriction)")}}
-    if not args.no_profile:
+    if not args.no_profile and not args.skip_one_stream:
         # the same step with every launch on one stream: kernel times without
         # another class's kernels sharing the device
         h.set_profiling(True)
