@@ -125,7 +125,7 @@ int g_fuse = 2;              // smoother sweeps fused per pass (1 or 2)
 int g_rbgs_tw = 64;          // smoother tile: widest, most cells, LDS elements
 int g_rbgs_cells = 1024;
 int g_rbgs_lds = kRbgsLds;
-int g_tail_lds = 40960;      // LDS budget of the W-cycle tail (sets its depth)
+int g_tail_lds = 20480;      // LDS budget of the W-cycle tail (sets its depth)
 int g_handoff = 1024;        // hand a class's last cycling problems to one kernel at or below this count
 int g_solve_lds = 65536;     // LDS budget under which a class is solved entirely in one kernel
 bool g_debug_stages = false; // per-level timing on stderr
