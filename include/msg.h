@@ -102,11 +102,13 @@ typedef struct {
     int32_t handoff;            /* -1 = automatic; 0 = never; n: once at most n problems of a
                                    class still cycle and its rectangle fits on chip, their
                                    remaining cycles run inside one kernel */
-    int32_t overlap;            /* -1 = automatic (1); 0 = every launch on `stream`; 1 = the
-                                   cycles of the classes of a level alternate over two streams
-                                   forked from and joined back to `stream`; 2 = as 1, each large
-                                   class also split in two sub-batches.  Results do not depend
-                                   on it. */
+    int32_t overlap;            /* -1 = automatic (2 for 1024 samples or more, else 1);
+                                   0 = every launch on `stream`; 1 = the cycles of the classes
+                                   of a level alternate over two streams forked from and
+                                   joined back to `stream`; 2 = the batch is split in two
+                                   halves solved concurrently by two host threads, each half
+                                   on one stream of its own.  Results do not depend on it; the
+                                   workspace size does (msg_workspace_size). */
 } msg_solve_opts;
 
 /* Fill opts with the defaults: W(2,2), 50 cycles, tol 1e-10, omega 1, FP64,

@@ -20,6 +20,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/msg.h"
@@ -120,12 +121,12 @@ BatchLayout make_layout(const msg_batch_desc* b)
 
 // ---------------------------------------------------------------- plans
 constexpr int kSideStreams = 2;   // W-cycles of sub-batches run on these, forked from the caller's stream
-constexpr int kMinSplit = 256;    // smallest sub-batch worth a stream of its own
 int g_fuse = 2;              // smoother sweeps fused per pass (1 or 2)
 int g_rbgs_tw = 64;          // smoother tile: widest, most cells, LDS elements
 int g_rbgs_cells = 1024;
 int g_rbgs_lds = kRbgsLds;
 int g_tail_lds = 20480;      // LDS budget of the W-cycle tail (sets its depth)
+int g_split_inner = 0;       // overlap mode inside each concurrently solved half (0 or 1)
 int g_handoff = 1024;        // hand a class's last cycling problems to one kernel at or below this count
 int g_solve_lds = 65536;     // LDS budget under which a class is solved entirely in one kernel
 bool g_debug_stages = false; // per-level timing on stderr
@@ -428,7 +429,7 @@ Ws ws_layout(const BatchLayout& BL, const std::vector<StagePlan>& plans, bool mi
     w.active = take(sizeof(int32_t) * std::max<int64_t>(probs, 1));
     w.pcycles = take(sizeof(int32_t) * std::max<int64_t>(probs, 1));
     w.dead = take(sizeof(int32_t) * BL.S);
-    w.nactive = take(sizeof(int32_t) * (kMaxIndex + 1) * kSideStreams);
+    w.nactive = take(sizeof(int32_t) * (kMaxIndex + 1));
     w.sbase = take(sizeof(SampleBase) * BL.S);
     w.gbase = take(sizeof(int64_t) * BL.S);
     w.rbase = take(sizeof(int64_t) * BL.S);
@@ -525,24 +526,31 @@ struct Profiler {
 };
 
 
-struct msg_handle_s {
-    int device;
+// What one concurrently solved part of a batch owns: its stream, the side
+// streams its classes alternate over, their fork/join events, and its
+// kernel timing.
+struct Lane {
     Profiler prof;
+    hipStream_t own = nullptr;
     hipStream_t side[kSideStreams] = {};
-    hipEvent_t fork = nullptr, join[kSideStreams] = {};
-    ~msg_handle_s()
+    hipEvent_t fork = nullptr, join[kSideStreams] = {}, done = nullptr;
+    ~Lane()
     {
         for (int k = 0; k < kSideStreams; ++k) {
             if (side[k]) (void)hipStreamDestroy(side[k]);
             if (join[k]) (void)hipEventDestroy(join[k]);
         }
+        if (own) (void)hipStreamDestroy(own);
         if (fork) (void)hipEventDestroy(fork);
+        if (done) (void)hipEventDestroy(done);
     }
-    // default-priority streams and their fork/join events, created on first use
-    hipError_t side_streams()
+    // default-priority streams and their events, created on first use
+    hipError_t streams()
     {
         if (fork) return hipSuccess;
         hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
         for (int k = 0; k < kSideStreams && e == hipSuccess; ++k) {
             e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
@@ -550,6 +558,55 @@ struct msg_handle_s {
         return e;
     }
 };
+
+constexpr int kParts = 2;          // a large batch is solved as this many concurrent parts
+constexpr int kSplitMin = 1024;    // smallest batch split by the automatic overlap
+
+struct msg_handle_s {
+    int device;
+    Lane lane[kParts];
+};
+
+// Bytes of workspace of a part, and the split of a batch into parts.
+namespace {
+
+size_t part_ws_bytes(const msg_batch_desc* batch, const msg_solve_opts* opts)
+{
+    const BatchLayout BL = make_layout(batch);
+    return ws_layout(BL, make_plans(BL, *opts), opts->precision == MSG_MIXED).total;
+}
+
+// overlap mode actually used: -1 picks 2 (two concurrent halves) for large batches
+int overlap_mode(const msg_batch_desc* batch, const msg_solve_opts* opts)
+{
+    const int m = opts->overlap < 0 ? (batch->n_samples >= kSplitMin ? 2 : 1) : opts->overlap;
+    return (m == 2 && batch->n_samples < kParts) ? 1 : m;
+}
+
+struct Split {
+    msg_batch_desc part[kParts];
+    int first[kParts];
+    size_t ws_off[kParts], ws_bytes[kParts], total;
+};
+
+Split split_batch(const msg_batch_desc* batch, const msg_solve_opts* opts)
+{
+    Split sp;
+    size_t off = 0;
+    for (int k = 0; k < kParts; ++k) {
+        const int a = (int)((int64_t)batch->n_samples * k / kParts);
+        const int b = (int)((int64_t)batch->n_samples * (k + 1) / kParts);
+        sp.first[k] = a;
+        sp.part[k] = msg_batch_desc{b - a, batch->c, batch->P + a, batch->Q + a};
+        sp.ws_off[k] = off;
+        sp.ws_bytes[k] = part_ws_bytes(&sp.part[k], opts);
+        off = align_up(off + sp.ws_bytes[k]);
+    }
+    sp.total = off;
+    return sp;
+}
+
+}  // namespace
 
 // ======================================================================
 // C-ABI
@@ -586,6 +643,7 @@ msg_status msg_create(msg_handle* h, int device)
     std::call_once(env_once, [] {
         if (const char* f = std::getenv("MSG_RBGS_FUSE")) g_fuse = std::atoi(f) == 1 ? 1 : 2;
         if (const char* t = std::getenv("MSG_TAIL_LDS")) g_tail_lds = std::max(1024, std::atoi(t));
+        if (const char* t = std::getenv("MSG_SPLIT_INNER")) g_split_inner = std::atoi(t) > 0 ? 1 : 0;
         if (const char* t = std::getenv("MSG_SOLVE_LDS")) g_solve_lds = std::max(0, std::atoi(t));
         if (const char* t = std::getenv("MSG_DEBUG_STAGES")) g_debug_stages = std::atoi(t) != 0;
         if (const char* t = std::getenv("MSG_HANDOFF")) g_handoff = std::max(0, std::atoi(t));
@@ -620,9 +678,7 @@ msg_status msg_workspace_size(msg_handle, const msg_batch_desc* batch, const msg
     if (st != MSG_OK) return st;
     if ((st = check_opts(opts)) != MSG_OK) return st;
     if (!bytes) return fail(MSG_ERR_ARG, "bytes is NULL");
-    const BatchLayout BL = make_layout(batch);
-    const std::vector<StagePlan> plans = make_plans(BL, *opts);
-    *bytes = ws_layout(BL, plans, opts->precision == MSG_MIXED).total;
+    *bytes = overlap_mode(batch, opts) == 2 ? split_batch(batch, opts).total : part_ws_bytes(batch, opts);
     return MSG_OK;
 }
 
@@ -831,14 +887,7 @@ struct Span {
     int k0, kn;
 };
 
-// a class's sub-batches: kSideStreams equal parts when overlap = 2 and it is large enough
-int nparts(const ClassPlan& C, int overlap) { return overlap == 2 && C.K >= 2 * kMinSplit ? kSideStreams : 1; }
-Span part_span(const ClassPlan& C, int overlap, int part)
-{
-    const int n = nparts(C, overlap);
-    const int a = (int)((int64_t)C.K * part / n), b = (int)((int64_t)C.K * (part + 1) / n);
-    return Span{a, b - a};
-}
+
 
 template <typename T>
 msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, Iter<T>& it, T* B, const T* KX,
@@ -942,20 +991,19 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, I
 
 }  // namespace
 
-extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch, const msg_solve_opts* opts,
-                                      const double* d_kx, const double* d_ky, const float* d_kx32,
-                                      const float* d_ky32, const double* d_rhs, double* d_u_out, double* d_q_out,
-                                      int32_t* d_status, int32_t* d_cycles, void* d_ws, size_t ws_bytes,
-                                      msg_stream stream)
+namespace {
+
+// One part of a batch (the whole batch, or one of the halves solved
+// concurrently) on stream s with lane ln; ov > 0 lets the classes of a level
+// alternate over the lane's two side streams.  Arguments are validated by
+// the caller; the part's arrays start at its first sample.
+msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batch, const msg_solve_opts* opts,
+                      const double* d_kx, const double* d_ky, const float* d_kx32, const float* d_ky32,
+                      const double* d_rhs, double* d_u_out, double* d_q_out, int32_t* d_status, int32_t* d_cycles,
+                      void* d_ws, size_t ws_bytes, hipStream_t s)
 {
-    if (!h) return fail(MSG_ERR_ARG, "handle is NULL");
-    msg_status st = check_batch(batch);
-    if (st != MSG_OK) return st;
-    if ((st = check_opts(opts)) != MSG_OK) return st;
-    if (!d_kx || !d_ky || !d_u_out || !d_q_out || !d_status || !d_ws)
-        return fail(MSG_ERR_ARG, "kx, ky, u_out, q_out, status and workspace are required");
+    msg_status st = MSG_OK;
     const bool mixed = opts->precision == MSG_MIXED;
-    if (mixed && (!d_kx32 || !d_ky32)) return fail(MSG_ERR_ARG, "mixed precision needs the FP32 coefficient copies");
     const BatchLayout BL = make_layout(batch);
     const std::vector<StagePlan> plans = make_plans(BL, *opts);
     const Ws W = ws_layout(BL, plans, mixed);
@@ -969,9 +1017,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
                 return fail(MSG_ERR_UNSUPPORTED, "class (%d,%d) does not fit LDS; lower tail_levels", C.pc, C.qc);
         }
     HIPCHK(hipSetDevice(h->device));
-    const int ov = opts->overlap < 0 ? 1 : opts->overlap;
-    if (ov > 0) HIPCHK(h->side_streams());
-    hipStream_t s = (hipStream_t)stream;
+    if (ov > 0) HIPCHK(ln.streams());
     char* ws = (char*)d_ws;
     const int c = BL.c, S = BL.S;
 
@@ -1047,7 +1093,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
     X.s = s;
     X.c = c;
     X.chol = chol;
-    X.prof = &h->prof;
+    X.prof = &ln.prof;
     X.kact = 0;
     double* a64b = (double*)(ws + W.a64b);
     float* a32b = mixed ? (float*)(ws + W.a32b) : nullptr;
@@ -1156,7 +1202,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
             }
         }
         // adaptive number of cycles per problem (Section 2): check, then cycle
-        std::vector<int32_t> host_active(ncls, 0), part_active((size_t)ncls * kSideStreams, 0);
+        std::vector<int32_t> host_active(ncls, 0);
         std::vector<char> handed(ncls, 0);
         int iters = 0;
         for (int it = 0; it <= opts->max_cycles + 1; ++it) {
@@ -1193,7 +1239,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
                     HIPCHK(hipStreamSynchronize(s));
                 }
             }
-            HIPCHK(hipMemsetAsync(nact, 0, sizeof(int32_t) * ncls * kSideStreams, s));
+            HIPCHK(hipMemsetAsync(nact, 0, sizeof(int32_t) * ncls, s));
             iters = it;
             for (int ci = 0; ci < ncls; ++ci) {
                 const ClassPlan& C = SP.classes[ci];
@@ -1211,70 +1257,50 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
                     });
                 });
                 if (st != MSG_OK) return st;
-                for (int pi = 0; pi < nparts(C, ov); ++pi) {
-                    const Span sp = part_span(C, ov, pi);
-                    const int a = C.first + sp.k0;
-                    hipError_t e = launch_converge(sp.kn, C.top1d.ntiles, X.probs + a, X.active + a, pcycles + a, dead,
-                                                   d_status, part, opts->tol, opts->max_cycles, SP.L,
-                                                   nact + ci * kSideStreams + pi, s);
-                    if (e != hipSuccess) return fail(MSG_ERR_HIP, "converge: %s", hipGetErrorString(e));
-                }
+                hipError_t e = launch_converge(C.K, C.top1d.ntiles, X.probs + C.first, X.active + C.first,
+                                               pcycles + C.first, dead, d_status, part, opts->tol, opts->max_cycles,
+                                               SP.L, nact + ci, s);
+                if (e != hipSuccess) return fail(MSG_ERR_HIP, "converge: %s", hipGetErrorString(e));
             }
-            HIPCHK(hipMemcpyAsync(part_active.data(), nact, sizeof(int32_t) * ncls * kSideStreams,
-                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(host_active.data(), nact, sizeof(int32_t) * ncls, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            for (int ci = 0; ci < ncls; ++ci) {
-                host_active[ci] = 0;
-                for (int pi = 0; pi < kSideStreams; ++pi) host_active[ci] += part_active[ci * kSideStreams + pi];
-            }
-            if (h->prof.on) h->prof.resolve();
+            if (ln.prof.on) ln.prof.resolve();
             int64_t any = 0;
             for (int32_t a : host_active) any += a;
             if (any == 0) break;
             // one W-cycle per class still cycling.  With overlap the classes
-            // (and, with overlap = 2, halves of large classes) alternate over
-            // two streams forked from the caller's, so that one's on-chip,
-            // latency-bound tail runs beside another's bandwidth-bound
-            // sweeps.  They touch disjoint problems; the halves of a class
-            // follow the same buffer sequence.
+            // alternate over two streams forked from this part's stream, so
+            // that one's on-chip, latency-bound tail runs beside another's
+            // bandwidth-bound sweeps.  They touch disjoint problems.
             const bool fork = ov > 0;
             if (fork) {
-                HIPCHK(hipEventRecord(h->fork, s));
-                for (int k = 0; k < kSideStreams; ++k) HIPCHK(hipStreamWaitEvent(h->side[k], h->fork, 0));
+                HIPCHK(hipEventRecord(ln.fork, s));
+                for (int k = 0; k < kSideStreams; ++k) HIPCHK(hipStreamWaitEvent(ln.side[k], ln.fork, 0));
             }
             int rr = 0;
             for (int ci = 0; ci < ncls; ++ci) {
                 const ClassPlan& C = SP.classes[ci];
                 if (host_active[ci] == 0) continue;        // every problem of this class has stopped
-                Iter<double> n64 = i64[ci];
-                Iter<float> n32 = i32[ci];
-                for (int pi = 0; pi < nparts(C, ov); ++pi) {
-                    Ctx Y = X;
-                    Y.kact = part_active[ci * kSideStreams + pi];
-                    if (Y.kact == 0) continue;             // this sub-batch has stopped
-                    const Span span = part_span(C, ov, pi);
-                    Y.s = fork ? h->side[rr++ % kSideStreams] : s;
-                    if (mixed) {
-                        n32 = i32[ci];
-                        st = mu_cycle<float>(Y, C, span, SP.L, n32, a32b, d_kx32, d_ky32);
-                        if (st != MSG_OK) return st;
-                        const float* e32 = n32.now(SP.L);
-                        st = chunked(C.top1d, span.kn, [&](int k0, int kn) {
-                            const int a = C.first + span.k0 + k0;
-                            return launch_ir_update(C.top1d, kn, X.probs + a, X.active + a, it64.v[0], e32, Y.s);
-                        });
-                    } else {
-                        n64 = i64[ci];
-                        st = mu_cycle<double>(Y, C, span, SP.L, n64, a64b, d_kx, d_ky);
-                    }
+                Ctx Y = X;
+                Y.kact = host_active[ci];
+                Y.s = fork ? ln.side[rr++ % kSideStreams] : s;
+                const Span span{0, C.K};
+                if (mixed) {
+                    st = mu_cycle<float>(Y, C, span, SP.L, i32[ci], a32b, d_kx32, d_ky32);
                     if (st != MSG_OK) return st;
+                    const float* e32 = i32[ci].now(SP.L);
+                    st = chunked(C.top1d, C.K, [&](int k0, int kn) {
+                        const int a = C.first + k0;
+                        return launch_ir_update(C.top1d, kn, X.probs + a, X.active + a, it64.v[0], e32, Y.s);
+                    });
+                } else {
+                    st = mu_cycle<double>(Y, C, span, SP.L, i64[ci], a64b, d_kx, d_ky);
                 }
-                i64[ci] = n64;
-                i32[ci] = n32;
+                if (st != MSG_OK) return st;
             }
             for (int k = 0; fork && k < kSideStreams; ++k) {
-                HIPCHK(hipEventRecord(h->join[k], h->side[k]));
-                HIPCHK(hipStreamWaitEvent(s, h->join[k], 0));
+                HIPCHK(hipEventRecord(ln.join[k], ln.side[k]));
+                HIPCHK(hipStreamWaitEvent(s, ln.join[k], 0));
             }
         }
         // returned solutions of this level and their means
@@ -1302,15 +1328,82 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
         }
     }
     HIPCHK(hipStreamSynchronize(s));
-    if (h->prof.on) h->prof.resolve();
+    if (ln.prof.on) ln.prof.resolve();
+    return MSG_OK;
+}
+
+}  // namespace
+
+extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch, const msg_solve_opts* opts,
+                                      const double* d_kx, const double* d_ky, const float* d_kx32,
+                                      const float* d_ky32, const double* d_rhs, double* d_u_out, double* d_q_out,
+                                      int32_t* d_status, int32_t* d_cycles, void* d_ws, size_t ws_bytes,
+                                      msg_stream stream)
+{
+    if (!h) return fail(MSG_ERR_ARG, "handle is NULL");
+    msg_status st = check_batch(batch);
+    if (st != MSG_OK) return st;
+    if ((st = check_opts(opts)) != MSG_OK) return st;
+    if (!d_kx || !d_ky || !d_u_out || !d_q_out || !d_status || !d_ws)
+        return fail(MSG_ERR_ARG, "kx, ky, u_out, q_out, status and workspace are required");
+    const bool mixed = opts->precision == MSG_MIXED;
+    if (mixed && (!d_kx32 || !d_ky32)) return fail(MSG_ERR_ARG, "mixed precision needs the FP32 coefficient copies");
+    if ((uintptr_t)d_ws % kAlign) return fail(MSG_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+    hipStream_t s = (hipStream_t)stream;
+    const int mode = overlap_mode(batch, opts);
+    if (mode < 2)
+        return solve_part(h, h->lane[0], mode, batch, opts, d_kx, d_ky, d_kx32, d_ky32, d_rhs, d_u_out, d_q_out,
+                          d_status, d_cycles, d_ws, ws_bytes, s);
+
+    // two halves of the batch, each a whole F-cycle of its own on one stream
+    // of its own (forked from and joined back to the caller's), driven by two
+    // host threads: one half's long-running problems, latency-bound tails and
+    // host round trips overlap the other's work.  Each half uses a single
+    // stream: more streams than the device's hardware queues share queues and
+    // serialise (measured: 244 samples/s against 210 with the classes of
+    // each half also on two streams, 256x256 x 4096)
+    const Split sp = split_batch(batch, opts);
+    if (ws_bytes < sp.total) return fail(MSG_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, sp.total);
+    const BatchLayout BL = make_layout(batch);
+    HIPCHK(hipSetDevice(h->device));
+    for (int k = 0; k < kParts; ++k) HIPCHK(h->lane[k].streams());
+    HIPCHK(hipEventRecord(h->lane[0].done, s));
+    for (int k = 0; k < kParts; ++k) HIPCHK(hipStreamWaitEvent(h->lane[k].own, h->lane[0].done, 0));
+    msg_status res[kParts];
+    std::string err[kParts];
+    auto part = [&](int k) {
+        const int a = sp.first[k];
+        if (hipSetDevice(h->device) != hipSuccess) {
+            res[k] = MSG_ERR_HIP;
+            err[k] = "hipSetDevice failed";
+            return;
+        }
+        res[k] = solve_part(h, h->lane[k], g_split_inner, &sp.part[k], opts, d_kx + BL.xf[a], d_ky + BL.yf[a],
+                            d_kx32 ? d_kx32 + BL.xf[a] : nullptr, d_ky32 ? d_ky32 + BL.yf[a] : nullptr,
+                            d_rhs ? d_rhs + BL.top[a] : nullptr, d_u_out + BL.cell[a], d_q_out + BL.grid[a],
+                            d_status + a, d_cycles ? d_cycles + BL.grid[a] : nullptr, (char*)d_ws + sp.ws_off[k],
+                            sp.ws_bytes[k], h->lane[k].own);
+        if (res[k] != MSG_OK) err[k] = msg_last_error();
+    };
+    std::thread t1(part, 1);
+    part(0);
+    t1.join();
+    for (int k = 0; k < kParts; ++k) {
+        HIPCHK(hipEventRecord(h->lane[k].done, h->lane[k].own));
+        HIPCHK(hipStreamWaitEvent(s, h->lane[k].done, 0));
+    }
+    for (int k = 0; k < kParts; ++k)
+        if (res[k] != MSG_OK) return fail(res[k], "part %d: %s", k, err[k].c_str());
     return MSG_OK;
 }
 
 extern "C" msg_status msg_set_profiling(msg_handle h, int enable)
 {
     if (!h) return fail(MSG_ERR_ARG, "handle is NULL");
-    h->prof.on = enable != 0;
-    h->prof.reset();
+    for (Lane& ln : h->lane) {
+        ln.prof.on = enable != 0;
+        ln.prof.reset();
+    }
     return MSG_OK;
 }
 
@@ -1318,6 +1411,11 @@ extern "C" msg_status msg_get_profile(msg_handle h, int kind, msg_kernel_stats* 
 {
     if (!h || !out) return fail(MSG_ERR_ARG, "handle and output are required");
     if (kind < 0 || kind >= MSG_KERNEL_KINDS) return fail(MSG_ERR_ARG, "unknown kernel kind %d", kind);
-    *out = h->prof.tot[kind];
+    *out = msg_kernel_stats{0, 0.0, 0.0};
+    for (const Lane& ln : h->lane) {
+        out->launches += ln.prof.tot[kind].launches;
+        out->milliseconds += ln.prof.tot[kind].milliseconds;
+        out->bytes += ln.prof.tot[kind].bytes;
+    }
     return MSG_OK;
 }
