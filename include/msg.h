@@ -102,7 +102,7 @@ typedef struct {
     int32_t handoff;            /* -1 = automatic; 0 = never; n: once at most n problems of a
                                    class still cycle and its rectangle fits on chip, their
                                    remaining cycles run inside one kernel */
-    int32_t overlap;            /* -1 = automatic (2 for 1024 samples or more, else 1);
+    int32_t overlap;            /* -1 = automatic (2 for 1024 samples or more, else 0);
                                    0 = every launch on `stream`; 1 = the cycles of the classes
                                    of a level alternate over two streams forked from and
                                    joined back to `stream`; 2 = the batch is split in two

@@ -311,15 +311,20 @@ double tail_bytes(const KTail& TL, size_t elem)
     return per * elem;
 }
 
+// deepest tail whose LDS image fits the budget: the phases of the tail are
+// latency-bound, so several problems per CU must be resident to hide it
+// (measured at 256x256 x 4096: 20 KB, levels 0..4 and eight problems per CU,
+// beat 8, 28, 40 and 45 KB)
 template <typename T>
 int choose_tail(int c, int pc, int qc, int L, int req, const std::vector<int64_t>& goff)
 {
     KTail TL;
     if (req >= 0) return std::min(req, L);
+    const size_t budget = (size_t)g_tail_lds;
     int best = 0;
     for (int m = 0; m <= std::min(L, kMaxTailLevels - 1); ++m) {
         const size_t bytes = tail_layout<T>(c, pc, qc, m, goff, TL);
-        if (bytes == 0 || bytes > (size_t)g_tail_lds) break;
+        if (bytes == 0 || bytes > budget) break;
         best = m;
     }
     return best;
@@ -576,10 +581,14 @@ size_t part_ws_bytes(const msg_batch_desc* batch, const msg_solve_opts* opts)
     return ws_layout(BL, make_plans(BL, *opts), opts->precision == MSG_MIXED).total;
 }
 
-// overlap mode actually used: -1 picks 2 (two concurrent halves) for large batches
+// overlap mode actually used: -1 picks 2 (two concurrent halves) for large
+// batches and 0 otherwise.  Extra streams pay only while the device has
+// hardware queues to spare: with several callers solving concurrently (the
+// request loop), class streams made every batch wait on the others (median
+// latency 730 ms against 2.8 ms without them, 1000 requests at 400/s).
 int overlap_mode(const msg_batch_desc* batch, const msg_solve_opts* opts)
 {
-    const int m = opts->overlap < 0 ? (batch->n_samples >= kSplitMin ? 2 : 1) : opts->overlap;
+    const int m = opts->overlap < 0 ? (batch->n_samples >= kSplitMin ? 2 : 0) : opts->overlap;
     return (m == 2 && batch->n_samples < kParts) ? 1 : m;
 }
 

@@ -172,6 +172,9 @@ class Engine:
                  max_batch_work: float = 6e9, big_work: float = 1e6, seed: int = I.BASE_SEED + 5):
         import torch
         self.torch = torch
+        # the workers are the concurrency: each batch stays on its worker's
+        # stream (more streams than hardware queues serialise the batches)
+        opts = dataclasses.replace(opts, overlap=0)
         self.field, self.c, self.opts, self.device, self.seed = field, c, opts, device, seed
         self.dev = torch.device(f"cuda:{device}")
         if budget_bytes is None:
