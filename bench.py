@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--skip-ragged", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--skip-one-stream", action="store_true", help="no extra one-stream profiled step")
+    ap.add_argument("--no-tune", action="store_true", help="library default plan instead of the autotuner's")
+    ap.add_argument("--tune-cycles", type=int, default=1, help="cycles per stage in each autotuner trial")
     ap.add_argument("--mixed-workload-samples", type=int, default=None, help="default: the preset's 1024")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-profile", action="store_true", help="no HIP events around launches")
@@ -120,6 +122,12 @@ def main():
     log(f"workload {w.name}: S={S}, c={w.c}, (P,Q)=({w.P[0]},{w.Q[0]}), tol={w.tol}")
     xi_h = w.xi()
     xi = torch.tensor(xi_h, dtype=torch.float64, device="cuda:0")
+    tune = None
+    if not args.no_tune:
+        from paper_1907_12334_amd import autotune as AT
+        opts, tune = AT.autotune(h, w, opts, samples=S, cycles=args.tune_cycles, reps=1, log=log)
+        torch.cuda.empty_cache()
+        log(f"autotuned plan: {tune['params']}")
     bufs = msg.Buffers(batch, opts)
     log(f"device buffers {sum(t.numel() * t.element_size() for t in [bufs.kx, bufs.ky, bufs.u, bufs.ws]) / 1e9:.1f} GB")
 
@@ -157,7 +165,7 @@ def main():
     traffic = read_traffic(args.traffic)
     roofline = roofline_of(prof["smooth"], SMOOTH_KERNEL, traffic)
     kernel_share = {k: round((v[1] / 1000.0) / elapsed, 4) for k, v in prof.items() if not k.endswith("_stage")}
-    extra = {"kernel_time_share": kernel_share, "samples_converged": converged,
+    extra = {"kernel_time_share": kernel_share, "samples_converged": converged, "autotune": tune,
              "max_cycles_per_grid": int(cycles.max()),
              "roofline_stage_level": {
                  "note": "launches on each F-cycle stage's own level (its largest, HBM-resident grids)",

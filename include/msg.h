@@ -109,6 +109,14 @@ typedef struct {
                                    halves solved concurrently by two host threads, each half
                                    on one stream of its own.  Results do not depend on it; the
                                    workspace size does (msg_workspace_size). */
+    /* Plan tuning (0 = the library's defaults; see paper_1907_12334_amd/autotune.py).
+     * None changes results beyond rounding; all change the workspace size. */
+    int32_t tail_budget;        /* LDS bytes per problem of the on-chip cycle tail (sets its
+                                   depth): 0 or 1024..65536; default 20480 */
+    int32_t tile_width;         /* smoother tile width cap: 0 or a power of two 4..256; default 64 */
+    int32_t tile_cells;         /* smoother tile cell cap: 0 or 64..4096; default 1024 */
+    int32_t tile_lds;           /* smoother tile LDS elements with halo: 0 or 256..8192;
+                                   default 2048 */
 } msg_solve_opts;
 
 /* Fill opts with the defaults: W(2,2), 50 cycles, tol 1e-10, omega 1, FP64,

@@ -83,6 +83,14 @@ msg_status check_opts(const msg_solve_opts* o)
     if (o->tail_levels < -1 || o->tail_levels > 8) return fail(MSG_ERR_ARG, "tail_levels must be -1..8");
     if (o->handoff < -1) return fail(MSG_ERR_ARG, "handoff must be >= -1");
     if (o->overlap < -1 || o->overlap > 2) return fail(MSG_ERR_ARG, "overlap must be -1..2");
+    if (o->tail_budget != 0 && (o->tail_budget < 1024 || o->tail_budget > 65536))
+        return fail(MSG_ERR_ARG, "tail_budget must be 0 or 1024..65536 bytes");
+    if (o->tile_width != 0 && (o->tile_width < 4 || o->tile_width > 256 || (o->tile_width & (o->tile_width - 1))))
+        return fail(MSG_ERR_ARG, "tile_width must be 0 or a power of two in 4..256");
+    if (o->tile_cells != 0 && (o->tile_cells < 64 || o->tile_cells > 4096))
+        return fail(MSG_ERR_ARG, "tile_cells must be 0 or 64..4096");
+    if (o->tile_lds != 0 && (o->tile_lds < 256 || o->tile_lds > kRbgsLdsMax))
+        return fail(MSG_ERR_ARG, "tile_lds must be 0 or 256..%d elements", kRbgsLdsMax);
     return MSG_OK;
 }
 
@@ -140,18 +148,38 @@ int rbgs_lds(int nx, int ny, int H, int tw, int th)
     return (tw + 2 * Hx) * (th + 2 * Hy);
 }
 
-// Smoother tile of a grid: up to g_rbgs_tw cells wide and g_rbgs_cells cells
-// in all, within g_rbgs_lds elements of LDS.
-void rbgs_tile(int nx, int ny, int H, int& tw, int& th)
+// Plan parameters a caller may tune (msg_solve_opts; 0 there = the defaults)
+struct Tuning {
+    int tail_budget;   // LDS bytes per problem of the cycle tail
+    int tile_w;        // smoother tile: widest
+    int tile_cells;    //   most cells
+    int tile_lds;      //   LDS elements with halo
+};
+
+Tuning tuning_of(const msg_solve_opts& o)
 {
-    tw = std::min(nx, g_rbgs_tw);
+    return Tuning{o.tail_budget > 0 ? o.tail_budget : g_tail_lds, o.tile_width > 0 ? o.tile_width : g_rbgs_tw,
+                  o.tile_cells > 0 ? o.tile_cells : g_rbgs_cells, o.tile_lds > 0 ? o.tile_lds : g_rbgs_lds};
+}
+
+// Smoother tile of a grid: up to tile_w cells wide and tile_cells cells in
+// all, within tile_lds elements of LDS.
+void rbgs_tile(int nx, int ny, int H, const Tuning& tu, int& tw, int& th)
+{
+    tw = std::min(nx, tu.tile_w);
     th = 1;
-    while (th * 2 <= ny && tw * th * 2 <= g_rbgs_cells && rbgs_lds(nx, ny, H, tw, th * 2) <= g_rbgs_lds) th *= 2;
+    while (th * 2 <= ny && tw * th * 2 <= tu.tile_cells && rbgs_lds(nx, ny, H, tw, th * 2) <= tu.tile_lds) th *= 2;
     if (th < ny && th * 2 > ny) {
         // non-power-of-two heights: take the largest fitting height
         int t = ny;
-        while (t > th && (tw * t > g_rbgs_cells || rbgs_lds(nx, ny, H, tw, t) > g_rbgs_lds)) --t;
+        while (t > th && (tw * t > tu.tile_cells || rbgs_lds(nx, ny, H, tw, t) > tu.tile_lds)) --t;
         th = std::max(th, t);
+    }
+    // a tile too narrow for its halo still works; one that cannot hold a
+    // single row with halo falls back to the smallest
+    if (rbgs_lds(nx, ny, H, tw, th) > kRbgsLdsMax) {
+        tw = std::min(nx, 16);
+        th = 1;
     }
 }
 
@@ -226,7 +254,7 @@ KLevel level_1d(int c, int pc, int qc, int lev, const std::vector<int64_t>& goff
     return K;
 }
 
-KLevel level_rbgs(int c, int pc, int qc, int lev, const std::vector<int64_t>& goff, int H)
+KLevel level_rbgs(int c, int pc, int qc, int lev, const std::vector<int64_t>& goff, int H, const Tuning& tu)
 {
     KLevel K;
     std::memset(&K, 0, sizeof K);
@@ -239,7 +267,7 @@ KLevel level_rbgs(int c, int pc, int qc, int lev, const std::vector<int64_t>& go
         G.ny = c << b;
         G.p = a;
         G.q = b;
-        rbgs_tile(G.nx, G.ny, H, G.tw, G.th);
+        rbgs_tile(G.nx, G.ny, H, tu, G.tw, G.th);
         G.tiles_x = (int)ceil_div(G.nx, G.tw);
         G.tile0 = tiles;
         G.aoff = goff[a * (qc + 1) + b];
@@ -316,11 +344,10 @@ double tail_bytes(const KTail& TL, size_t elem)
 // (measured at 256x256 x 4096: 20 KB, levels 0..4 and eight problems per CU,
 // beat 8, 28, 40 and 45 KB)
 template <typename T>
-int choose_tail(int c, int pc, int qc, int L, int req, const std::vector<int64_t>& goff)
+int choose_tail(int c, int pc, int qc, int L, int req, size_t budget, const std::vector<int64_t>& goff)
 {
     KTail TL;
     if (req >= 0) return std::min(req, L);
-    const size_t budget = (size_t)g_tail_lds;
     int best = 0;
     for (int m = 0; m <= std::min(L, kMaxTailLevels - 1); ++m) {
         const size_t bytes = tail_layout<T>(c, pc, qc, m, goff, TL);
@@ -332,6 +359,7 @@ int choose_tail(int c, int pc, int qc, int L, int req, const std::vector<int64_t
 
 std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o)
 {
+    const Tuning tu = tuning_of(o);
     std::vector<StagePlan> plans(BL.maxL + 1);
     const int c = BL.c;
     const int H = 2 * g_fuse;
@@ -370,8 +398,8 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
             else C.solve_in_tail = b64 > 0 && b64 <= (size_t)g_solve_lds;
             if (L == 0) C.solve_in_tail = b64 > 0;
             const int mcap = std::max(0, L - 1);
-            C.tail_top = o.precision == MSG_MIXED ? choose_tail<float>(c, pc, qc, mcap, o.tail_levels, C.goff)
-                                                   : choose_tail<double>(c, pc, qc, mcap, o.tail_levels, C.goff);
+            C.tail_top = o.precision == MSG_MIXED ? choose_tail<float>(c, pc, qc, mcap, o.tail_levels, tu.tail_budget, C.goff)
+                                                   : choose_tail<double>(c, pc, qc, mcap, o.tail_levels, tu.tail_budget, C.goff);
             C.tail_lds = o.precision == MSG_MIXED ? tail_layout<float>(c, pc, qc, C.tail_top, C.goff, C.tail)
                                                    : tail_layout<double>(c, pc, qc, C.tail_top, C.goff, C.tail);
             C.top1d = level_1d(c, pc, qc, L, C.goff, 1, qc);
@@ -380,7 +408,7 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
             C.pro.resize(L + 1);
             C.res.resize(L + 1);
             for (int lev = 1; lev <= L; ++lev) {
-                C.rb[lev] = level_rbgs(c, pc, qc, lev, C.goff, H);
+                C.rb[lev] = level_rbgs(c, pc, qc, lev, C.goff, H, tu);
                 C.rbc[lev] = C.rb[lev];
                 for (int g = 0; g < C.rbc[lev].ngrids; ++g) {
                     KGrid& G = C.rbc[lev].g[g];
@@ -635,6 +663,10 @@ void msg_default_opts(msg_solve_opts* o)
     o->tail_levels = -1;
     o->handoff = -1;
     o->overlap = -1;
+    o->tail_budget = 0;
+    o->tile_width = 0;
+    o->tile_cells = 0;
+    o->tile_lds = 0;
 }
 
 const char* msg_last_error(void) { return g_err.c_str(); }

@@ -83,9 +83,17 @@ def test_workspace_size_and_options():
     with pytest.raises(msg.MsgError):
         msg.workspace_size(b, msg.SolveOpts(tail_levels=9))
     assert (o.tail_levels, o.handoff, o.overlap) == (-1, -1, -1)
+    assert (o.tail_budget, o.tile_width, o.tile_cells, o.tile_lds) == (0, 0, 0, 0)
     for bad in (-2, 3):
         with pytest.raises(msg.MsgError):
             msg.workspace_size(b, msg.SolveOpts(overlap=bad))
+    for bad in (dict(tail_budget=512), dict(tail_budget=70000), dict(tile_width=48), dict(tile_width=512),
+                dict(tile_cells=32), dict(tile_lds=9000)):
+        with pytest.raises(msg.MsgError):
+            msg.workspace_size(b, msg.SolveOpts(**bad))
+    # a deeper tail needs a larger per-stage conductance image
+    big = msg.Batch(2, [7] * 4, [7] * 4)
+    assert msg.workspace_size(big, msg.SolveOpts(tail_budget=40960)) > msg.workspace_size(big, msg.SolveOpts())
 
 
 def test_entry_points_reject_null_handle_without_device_work():

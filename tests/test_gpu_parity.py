@@ -131,6 +131,30 @@ def test_overlap_modes_give_identical_results(handle):
     assert g["status"] == ora["status"] and max(eu, eq, edq) <= FP64_TOL
 
 
+def test_autotuned_plan_gives_the_same_answers(handle, tmp_path):
+    """The autotuner's choice and every candidate plan solve the same problem:
+    same cycle counts, iterates equal to rounding; the choice is cached."""
+    from paper_1907_12334_amd import autotune as AT
+    import dataclasses
+    w = dataclasses.replace(I.config(2).subset(24), P=[5] * 24, Q=[4] * 24)
+    base = msg.SolveOpts(tol=1e-10, max_cycles=400)
+    cache = str(tmp_path / "tune.json")
+    tuned, rep = AT.autotune(handle, w, base, samples=24, cycles=2, reps=1, cache=cache)
+    assert len(rep["trials"]) == len(AT.TILES) + len(AT.TAIL_BUDGETS) - 1 and not rep["cached"]
+    again, rep2 = AT.autotune(handle, w, base, samples=24, cycles=2, reps=1, cache=cache)
+    assert rep2["cached"] and again == tuned
+    xi = w.xi()
+    ref = PR.gpu_solve(w.c, w.P, w.Q, w.field, xi, base, handle=handle)
+    for params in [tuned] + [dataclasses.replace(base, tile_width=t[0], tile_cells=t[1], tile_lds=t[2])
+                             for t in AT.TILES[1:]] + [dataclasses.replace(base, tail_budget=b)
+                                                        for b in AT.TAIL_BUDGETS[1:]]:
+        out = PR.gpu_solve(w.c, w.P, w.Q, w.field, xi, params, handle=handle)
+        assert np.array_equal(out["cycles"], ref["cycles"]) and np.array_equal(out["status"], ref["status"])
+        for s in range(0, 24, 5):
+            a, b = PR.per_sample(out, s), PR.per_sample(ref, s)
+            assert PR.grid_errors(w.c, w.P[s], w.Q[s], a["u"], b["u"]) <= 1e-12
+
+
 def test_ragged_batch_and_batch_invariance(handle):
     rng = np.random.default_rng(5)
     P = rng.integers(0, 5, size=12)
