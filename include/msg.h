@@ -117,6 +117,9 @@ typedef struct {
     int32_t tile_cells;         /* smoother tile cell cap: 0 or 64..4096; default 1024 */
     int32_t tile_lds;           /* smoother tile LDS elements with halo: 0 or 256..8192;
                                    default 2048 */
+    int32_t graphs;             /* 1 = capture each class's W-cycle as a HIP graph on its first
+                                   cycle of a stage and replay it for the others (not while
+                                   kernel timing is on); 0 = launch every kernel (default) */
 } msg_solve_opts;
 
 /* Fill opts with the defaults: W(2,2), 50 cycles, tol 1e-10, omega 1, FP64,

@@ -91,6 +91,7 @@ msg_status check_opts(const msg_solve_opts* o)
         return fail(MSG_ERR_ARG, "tile_cells must be 0 or 64..4096");
     if (o->tile_lds != 0 && (o->tile_lds < 256 || o->tile_lds > kRbgsLdsMax))
         return fail(MSG_ERR_ARG, "tile_lds must be 0 or 256..%d elements", kRbgsLdsMax);
+    if (o->graphs < 0 || o->graphs > 1) return fail(MSG_ERR_ARG, "graphs must be 0 or 1");
     return MSG_OK;
 }
 
@@ -667,6 +668,7 @@ void msg_default_opts(msg_solve_opts* o)
     o->tile_width = 0;
     o->tile_cells = 0;
     o->tile_lds = 0;
+    o->graphs = 0;
 }
 
 const char* msg_last_error(void) { return g_err.c_str(); }
@@ -921,6 +923,38 @@ struct Iter {
     T* now(int l) const { return v[cur[l]]; }
 };
 
+// the state a W-cycle on level L depends on: the buffers and which holds
+// level L (every coarser level's is set by the restriction before use)
+template <typename T>
+bool same_start(const Iter<T>& a, const Iter<T>& b, int L)
+{
+    return a.v[0] == b.v[0] && a.v[1] == b.v[1] && a.cur[L] == b.cur[L];
+}
+
+// A class's captured W-cycle and the buffer states before and after it.
+struct ClassGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Iter<double> before64{}, after64{};
+    Iter<float> before32{}, after32{};
+    ClassGraph() = default;
+    ClassGraph(const ClassGraph&) = delete;
+    ClassGraph& operator=(const ClassGraph&) = delete;
+    ClassGraph(ClassGraph&& o) noexcept { *this = std::move(o); }
+    ClassGraph& operator=(ClassGraph&& o) noexcept
+    {
+        std::swap(graph, o.graph);
+        std::swap(exec, o.exec);
+        before64 = o.before64; after64 = o.after64; before32 = o.before32; after32 = o.after32;
+        return *this;
+    }
+    ~ClassGraph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
 // Algorithm MSG mu-cycle on level lev of class C, recursion on the host down
 // to the tail level, whose cycles run inside one workgroup per problem.
 // problems [k0, k0 + kn) of a class
@@ -1058,7 +1092,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                 return fail(MSG_ERR_UNSUPPORTED, "class (%d,%d) does not fit LDS; lower tail_levels", C.pc, C.qc);
         }
     HIPCHK(hipSetDevice(h->device));
-    if (ov > 0) HIPCHK(ln.streams());
+    if (ov > 0 || opts->graphs > 0) HIPCHK(ln.streams());
     char* ws = (char*)d_ws;
     const int c = BL.c, S = BL.S;
 
@@ -1242,6 +1276,10 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                 if (st != MSG_OK) return st;
             }
         }
+        // captured W-cycles of this stage's classes (not while timing kernels:
+        // the per-launch events would be captured too)
+        const bool use_graphs = opts->graphs > 0 && !ln.prof.on;
+        std::vector<ClassGraph> graphs(ncls);
         // adaptive number of cycles per problem (Section 2): check, then cycle
         std::vector<int32_t> host_active(ncls, 0);
         std::vector<char> handed(ncls, 0);
@@ -1313,7 +1351,11 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
             // alternate over two streams forked from this part's stream, so
             // that one's on-chip, latency-bound tail runs beside another's
             // bandwidth-bound sweeps.  They touch disjoint problems.
-            const bool fork = ov > 0;
+            // Graphs are captured on library streams only (the caller's may
+            // be the null stream, which cannot be captured): without overlap
+            // the classes then run on the lane's own stream, forked from and
+            // joined back to the part's stream.
+            const bool fork = ov > 0 || use_graphs;
             if (fork) {
                 HIPCHK(hipEventRecord(ln.fork, s));
                 for (int k = 0; k < kSideStreams; ++k) HIPCHK(hipStreamWaitEvent(ln.side[k], ln.fork, 0));
@@ -1324,20 +1366,51 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                 if (host_active[ci] == 0) continue;        // every problem of this class has stopped
                 Ctx Y = X;
                 Y.kact = host_active[ci];
-                Y.s = fork ? ln.side[rr++ % kSideStreams] : s;
+                Y.s = ov > 0 ? ln.side[rr++ % kSideStreams] : (use_graphs ? ln.side[0] : s);
                 const Span span{0, C.K};
-                if (mixed) {
-                    st = mu_cycle<float>(Y, C, span, SP.L, i32[ci], a32b, d_kx32, d_ky32);
-                    if (st != MSG_OK) return st;
+                // one W-cycle of the class (and its refinement update)
+                auto cycle = [&]() -> msg_status {
+                    if (!mixed) return mu_cycle<double>(Y, C, span, SP.L, i64[ci], a64b, d_kx, d_ky);
+                    msg_status r = mu_cycle<float>(Y, C, span, SP.L, i32[ci], a32b, d_kx32, d_ky32);
+                    if (r != MSG_OK) return r;
                     const float* e32 = i32[ci].now(SP.L);
-                    st = chunked(C.top1d, C.K, [&](int k0, int kn) {
+                    return chunked(C.top1d, C.K, [&](int k0, int kn) {
                         const int a = C.first + k0;
                         return launch_ir_update(C.top1d, kn, X.probs + a, X.active + a, it64.v[0], e32, Y.s);
                     });
-                } else {
-                    st = mu_cycle<double>(Y, C, span, SP.L, i64[ci], a64b, d_kx, d_ky);
+                };
+                if (!use_graphs) {
+                    if ((st = cycle()) != MSG_OK) return st;
+                    continue;
                 }
-                if (st != MSG_OK) return st;
+                // The launch sequence of a class's W-cycle is the same every
+                // cycle of the stage (stopped problems are masked on the
+                // device), so it is captured once and replayed.
+                ClassGraph& G = graphs[ci];
+                if (!G.exec) {
+                    G.before64 = i64[ci];
+                    G.before32 = i32[ci];
+                    HIPCHK(hipStreamBeginCapture(Y.s, hipStreamCaptureModeThreadLocal));
+                    const msg_status r = cycle();
+                    hipGraph_t g = nullptr;
+                    const hipError_t e = hipStreamEndCapture(Y.s, &g);
+                    if (r != MSG_OK) {
+                        if (g) (void)hipGraphDestroy(g);
+                        return r;
+                    }
+                    if (e != hipSuccess) return fail(MSG_ERR_HIP, "W-cycle capture: %s", hipGetErrorString(e));
+                    G.graph = g;
+                    HIPCHK(hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0));
+                    G.after64 = i64[ci];
+                    G.after32 = i32[ci];
+                } else {
+                    // replays assume the buffer state the capture started from
+                    if (!same_start(i64[ci], G.before64, SP.L) || !same_start(i32[ci], G.before32, SP.L))
+                        return fail(MSG_ERR_HIP, "W-cycle graph replay from a different buffer state");
+                    i64[ci] = G.after64;
+                    i32[ci] = G.after32;
+                }
+                HIPCHK(hipGraphLaunch(G.exec, Y.s));
             }
             for (int k = 0; fork && k < kSideStreams; ++k) {
                 HIPCHK(hipEventRecord(ln.join[k], ln.side[k]));

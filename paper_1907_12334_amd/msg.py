@@ -57,7 +57,7 @@ class SolveOptsC(ctypes.Structure):
                 ("max_cycles", ctypes.c_int32), ("tol", ctypes.c_double), ("omega", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("tail_levels", ctypes.c_int32), ("handoff", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("tail_budget", ctypes.c_int32), ("tile_width", ctypes.c_int32),
-                ("tile_cells", ctypes.c_int32), ("tile_lds", ctypes.c_int32)]
+                ("tile_cells", ctypes.c_int32), ("tile_lds", ctypes.c_int32), ("graphs", ctypes.c_int32)]
 
 
 _lib = None
@@ -154,18 +154,19 @@ class SolveOpts:
     tile_width: int = 0
     tile_cells: int = 0
     tile_lds: int = 0
+    graphs: int = 0
 
     def c_struct(self):
         return SolveOptsC(self.mu, self.nu1, self.nu2, self.max_cycles, self.tol, self.omega, self.precision,
                           self.tail_levels, self.handoff, self.overlap, self.tail_budget, self.tile_width,
-                          self.tile_cells, self.tile_lds)
+                          self.tile_cells, self.tile_lds, self.graphs)
 
 
 def default_opts() -> SolveOpts:
     o = SolveOptsC()
     lib().msg_default_opts(ctypes.byref(o))
     return SolveOpts(o.mu, o.nu1, o.nu2, o.max_cycles, o.tol, o.omega, o.precision, o.tail_levels, o.handoff,
-                     o.overlap, o.tail_budget, o.tile_width, o.tile_cells, o.tile_lds)
+                     o.overlap, o.tail_budget, o.tile_width, o.tile_cells, o.tile_lds, o.graphs)
 
 
 class FieldSpec:

@@ -7,6 +7,8 @@ change a count by one; the iterates are then compared at equal counts).
 Mixed precision: the same quantities within 1e-8 of the FP64 oracle run to
 1e-10.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -153,6 +155,23 @@ def test_autotuned_plan_gives_the_same_answers(handle, tmp_path):
         for s in range(0, 24, 5):
             a, b = PR.per_sample(out, s), PR.per_sample(ref, s)
             assert PR.grid_errors(w.c, w.P[s], w.Q[s], a["u"], b["u"]) <= 1e-12
+
+
+@pytest.mark.parametrize("precision,overlap", [(msg.FP64, 0), (msg.FP64, 2), (msg.MIXED, 0)])
+def test_graph_replay_matches_launches(handle, precision, overlap):
+    """Each class's W-cycle captured once per stage and replayed every later
+    cycle (with the convergence checks and host synchronisation between
+    replays): the same bits as launching every kernel, over many replays."""
+    c, spec = 2, I.separable(0.3, 0.03, 1.0, m=20)
+    P, Q = [5] * 6 + [4] * 4 + [3] * 2, [4] * 6 + [5] * 4 + [3] * 2
+    xi = I.draw_xi(spec.n_terms, range(len(P)))
+    tol = 1e-10 if precision == msg.FP64 else 1e-8
+    base = msg.SolveOpts(tol=tol, max_cycles=400, precision=precision, overlap=overlap, handoff=0, tail_levels=2)
+    ref = PR.gpu_solve(c, P, Q, spec, xi, base, handle=handle)
+    out = PR.gpu_solve(c, P, Q, spec, xi, dataclasses.replace(base, graphs=1), handle=handle)
+    assert ref["cycles"].max() >= 10                    # many replays per stage
+    for k in ("u", "q", "dq", "cycles", "status"):
+        assert np.array_equal(out[k], ref[k]), k
 
 
 def test_ragged_batch_and_batch_invariance(handle):
