@@ -37,6 +37,8 @@ def lib():
         L.oracle_msg_cycles.argtypes = [ctypes.c_int] * 3 + [_D, _D, _D, ctypes.POINTER(OracleOpts),
                                                               ctypes.c_int, _D, _D]
         L.oracle_delta_q.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D]
+        L.oracle_qoi_grid.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_int]
+        L.oracle_qoi_grid.restype = ctypes.c_double
         for name in ("oracle_apply",):
             getattr(L, name).argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
         L.oracle_residual.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, _D, _D]
@@ -228,6 +230,29 @@ def msg_cycles(c, P, Q, kx_all, ky_all, ncycles, o=None, rhs_top=None):
     lib().oracle_msg_cycles(c, P, Q, _d(kx_all), _d(ky_all), _d(rhs) if rhs is not None else None,
                             ctypes.byref(o), ncycles, _d(u), _d(ratios))
     return u, ratios
+
+
+QOI_MEAN, QOI_POINT, QOI_SUBDOMAIN, QOI_FLUX = range(4)
+
+
+def qoi_grid(u, kx, kind):
+    """One grid's quantity of interest: u (ny, nx) cells, kx (ny, nx+1) faces."""
+    u = f64(u)
+    ny, nx = u.shape
+    kx = f64(kx) if kx is not None else np.zeros((ny, nx + 1))
+    return lib().oracle_qoi_grid(nx, ny, _d(kx), _d(u), kind)
+
+
+def qoi(c, P, Q, u_all, kx_all, kind):
+    """Per-grid quantities of interest of one sample (packed order)."""
+    u_all, kx_all = f64(u_all), f64(kx_all)
+    out, cu, cx = [], 0, 0
+    for p, q, nx, ny in grid_shapes(c, P, Q):
+        out.append(qoi_grid(u_all[cu:cu + nx * ny].reshape(ny, nx),
+                            kx_all[cx:cx + (nx + 1) * ny].reshape(ny, nx + 1), kind))
+        cu += nx * ny
+        cx += (nx + 1) * ny
+    return np.array(out)
 
 
 def delta_q(P, Q, q):

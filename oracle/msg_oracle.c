@@ -670,6 +670,64 @@ void oracle_delta_q(int P, int Q, const double *q, double *dq)
         }
 }
 
+/* Quantities of interest of Section 5 on one grid, from its cell values u
+ * (row-major, x fastest) and, for the flux, its x-face coefficients kx
+ * ((nx+1) per row).  Readings for the cell-centred grid:
+ *   kind 0: mean of u over the cells (the workload's QoI, midpoint rule);
+ *   kind 1: u at (1/2, 1/2), the bilinear interpolant of the cell-centre
+ *           values (the point is a cell centre or lies between centres);
+ *   kind 2: the average over D_sub = [1/4,1/2]^2 of the piecewise-constant
+ *           finite-volume solution: each cell weighted by its overlap with
+ *           D_sub (exact for that reconstruction at any alignment);
+ *   kind 3: the flux -int_0^1 k du/dx dy through the wall x = 1: per row,
+ *           the wall face's flux 2 k u / h_x (one-sided difference over the
+ *           half cell to u = 0) times the face length h_y. */
+double oracle_qoi_grid(int nx, int ny, const double *kx, const double *u, int kind)
+{
+    if (kind == 0) {
+        double s = 0.0;
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) s += u[j * nx + i];
+        return s / ((double)nx * ny);
+    }
+    if (kind == 1) {
+        /* fractional cell index of x = 1/2: centres sit at (i + 1/2)/n */
+        const double tx = 0.5 * nx - 0.5, ty = 0.5 * ny - 0.5;
+        const int i0 = (int)floor(tx), j0 = (int)floor(ty);
+        const double wx = tx - i0, wy = ty - j0;
+        double val = 0.0;
+        for (int dj = 0; dj <= 1; ++dj)
+            for (int di = 0; di <= 1; ++di) {
+                const double w = (di ? wx : 1.0 - wx) * (dj ? wy : 1.0 - wy);
+                if (w == 0.0) continue;
+                val += w * u[(j0 + dj) * nx + (i0 + di)];
+            }
+        return val;
+    }
+    if (kind == 2) {
+        const double lo = 0.25, hi = 0.5;
+        double s = 0.0;
+        for (int j = 0; j < ny; ++j) {
+            const double oy = fmin((j + 1.0) / ny, hi) - fmax((double)j / ny, lo);
+            if (oy <= 0.0) continue;
+            for (int i = 0; i < nx; ++i) {
+                const double ox = fmin((i + 1.0) / nx, hi) - fmax((double)i / nx, lo);
+                if (ox <= 0.0) continue;
+                s += u[j * nx + i] * ox * oy;
+            }
+        }
+        return s / ((hi - lo) * (hi - lo));
+    }
+    /* kind 3 */
+    const double hx = 1.0 / nx, hy = 1.0 / ny;
+    double s = 0.0;
+    for (int j = 0; j < ny; ++j) {
+        const double k = kx[j * (nx + 1) + nx];
+        s += 2.0 * k * (u[j * nx + nx - 1] - 0.0) / hx * hy;
+    }
+    return s;
+}
+
 /* ---- single-grid steps, exported so tests can pin each one ------------- */
 
 static ogrid make_view(int nx, int ny, const double *kx, const double *ky)

@@ -529,3 +529,76 @@ def test_kl10_variance_separates_directions(oracle):
     assert abs(wx - 1.3729) < 1e-3 and abs(wy - 1.2270) < 1e-3
     tol = 3.5 * math.sqrt(2.0 / nd)
     assert abs(zx.var() / wx - 1) <= tol and abs(zy.var() / wy - 1) <= tol
+
+
+# ---------------------------------------------------------------- paper QoIs (Section 5)
+@pytest.mark.parametrize("nx,ny", [(2, 2), (4, 8), (3, 6), (12, 5)])
+def test_point_value_reproduces_bilinear_fields(oracle, nx, ny):
+    """Q1 = u(1/2,1/2) from cell centres: exact for any bilinear field, whether
+    the point is a cell centre (odd sizes) or lies between four centres."""
+    X, Y = cell_centres(nx, ny)
+    u = 1.0 + 2.0 * X + 3.0 * Y + 4.0 * X * Y
+    assert abs(oracle.qoi_grid(u, None, oracle.QOI_POINT) - 4.5) <= 1e-13
+
+
+@pytest.mark.parametrize("nx,ny", [(8, 8), (2, 2), (4, 16), (6, 10), (3, 3)])
+def test_subdomain_average_of_piecewise_constant_field(oracle, nx, ny):
+    """Q2: average over [1/4,1/2]^2 of the cell-wise constant solution.  A
+    constant averages to itself; u = x averages to the overlap-weighted mean
+    of the covered cell centres, checked against the exact integral of the
+    piecewise-constant function computed on a fine lattice of sub-cells."""
+    assert abs(oracle.qoi_grid(np.full((ny, nx), 2.5), None, oracle.QOI_SUBDOMAIN) - 2.5) <= 1e-14
+    X, Y = cell_centres(nx, ny)
+    rng = np.random.default_rng(nx * 31 + ny)
+    u = rng.standard_normal((ny, nx))
+    f = 16 * math.lcm(nx, ny, 4)                      # sub-cells per unit length: every face is a lattice line
+    xs = (np.arange(f) + 0.5) / f
+    inside = (xs >= 0.25) & (xs <= 0.5)
+    ii = np.minimum((xs * nx).astype(int), nx - 1)
+    jj = np.minimum((xs * ny).astype(int), ny - 1)
+    brute = u[np.ix_(jj[inside], ii[inside])].mean()
+    assert abs(oracle.qoi_grid(u, None, oracle.QOI_SUBDOMAIN) - brute) <= 1e-12
+    if nx % 4 == 0 and ny % 4 == 0:                   # faces on 1/4 and 1/2: mean of covered centres
+        assert abs(oracle.qoi_grid(X, None, oracle.QOI_SUBDOMAIN) - 0.375) <= 1e-14
+
+
+@pytest.mark.parametrize("n", [4, 8, 16])
+def test_flux_of_symmetric_problem_is_a_quarter_of_the_source(oracle, n):
+    """Q3 through x = 1: with k = 1 and h = 1 on an n x n grid, the discrete
+    solution has the square's symmetry, so the four walls carry equal flux;
+    the scheme is conservative, so together they carry int h = 1."""
+    kx, ky = const_faces(n, n)
+    A = dense(oracle, n, n, kx, ky)
+    u = np.linalg.solve(A, np.ones(n * n)).reshape(n, n)
+    q3 = oracle.qoi_grid(u, kx.reshape(n, n + 1), oracle.QOI_FLUX)
+    assert abs(q3 - 0.25) <= 1e-12
+    # the wall flux scales with the wall coefficient and is blind to the others
+    kx2 = kx.reshape(n, n + 1).copy()
+    kx2[:, n] *= 3.0
+    kx2[:, 0] *= 7.0
+    assert abs(oracle.qoi_grid(u, kx2, oracle.QOI_FLUX) - 0.75) <= 1e-12
+
+
+def test_flux_balances_the_source_with_a_variable_field(oracle):
+    """Conservation with a KL-10 field: the flux through x = 1, plus the same
+    functional on the solution mirrored in x, y and the transpose (the other
+    three walls), sums to int h = 1."""
+    n = 8
+    kx, ky = kl10_faces(oracle, n, n)
+    A = dense(oracle, n, n, kx, ky)
+    u = np.linalg.solve(A, np.ones(n * n)).reshape(n, n)
+    KX, KY = kx.reshape(n, n + 1), ky.reshape(n + 1, n)
+    east = oracle.qoi_grid(u, KX, oracle.QOI_FLUX)
+    west = oracle.qoi_grid(u[:, ::-1].copy(), KX[:, ::-1].copy(), oracle.QOI_FLUX)
+    north = oracle.qoi_grid(u.T.copy(), KY.T.copy(), oracle.QOI_FLUX)
+    south = oracle.qoi_grid(u.T[:, ::-1].copy(), KY.T[:, ::-1].copy(), oracle.QOI_FLUX)
+    assert abs(east + west + north + south - 1.0) <= 1e-12
+    assert min(east, west, north, south) > 0.0
+
+
+def test_mean_quantity_matches_the_solver_q(oracle):
+    """kind 0 is the Q the solver returns per grid."""
+    c, P, Q = 4, 2, 1
+    kx, ky = oracle.hierarchy_field(c, P, Q, I.KL10.as_dict(), I.draw_xi(10, [5])[0])
+    r = oracle.fmsg_solve(c, P, Q, kx, ky, oracle.opts())
+    assert np.allclose(oracle.qoi(c, P, Q, r["u"], kx, oracle.QOI_MEAN), r["q"], rtol=1e-14, atol=0)
