@@ -180,6 +180,22 @@ msg_status msg_solve_batch(msg_handle h, const msg_batch_desc *batch, const msg_
                            int32_t *d_status, int32_t *d_cycles,
                            void *d_ws, size_t ws_bytes, msg_stream stream);
 
+/* Quantities of interest per grid (Section 5 defines three for the unit
+ * square; the readings below adapt them to the cell-centred grid):
+ *   MSG_QOI_MEAN       mean of u over the cells (what msg_solve_batch returns in d_q_out);
+ *   MSG_QOI_POINT      u(1/2,1/2): bilinear interpolation of the cell-centre values;
+ *   MSG_QOI_SUBDOMAIN  average over D_sub = [1/4,1/2]^2 of the cell-wise constant solution,
+ *                      each cell weighted by its area inside D_sub;
+ *   MSG_QOI_FLUX       flux -int_0^1 k du/dx dy through the wall x = 1: per row, the wall
+ *                      face's 2 k u / h_x (the one-sided difference of the discretisation)
+ *                      times h_y.
+ * d_u: device FP64 cells (msg_solve_batch layout); d_kx: device FP64 x-faces, required for
+ * MSG_QOI_FLUX (else may be NULL); d_q: device FP64 [grids] output.  Enqueued on `stream`;
+ * returns after it completes. */
+enum { MSG_QOI_MEAN = 0, MSG_QOI_POINT = 1, MSG_QOI_SUBDOMAIN = 2, MSG_QOI_FLUX = 3 };
+msg_status msg_quantity(const msg_batch_desc *batch, int kind, const double *d_kx, const double *d_u,
+                        double *d_q, msg_stream stream);
+
 /* Multi-index differences (Section 3): for every sample and grid l = (p,q),
  * Delta Q_l = (Delta_1 x Delta_2) Q_l with Delta_i Q_l = Q_l - Q_{l - e_i}
  * when l_i > 0, else Q_l.  d_q, d_dq: device FP64 [grids] in the per-grid

@@ -821,6 +821,46 @@ msg_status msg_sample_field(msg_handle h, const msg_field_spec* spec, const msg_
     return MSG_OK;
 }
 
+static_assert(MSG_QOI_MEAN == QOI_MEAN && MSG_QOI_POINT == QOI_POINT && MSG_QOI_SUBDOMAIN == QOI_SUBDOMAIN &&
+                  MSG_QOI_FLUX == QOI_FLUX,
+              "quantity kinds of the C-ABI and the kernels agree");
+
+msg_status msg_quantity(const msg_batch_desc* batch, int kind, const double* d_kx, const double* d_u, double* d_q,
+                        msg_stream stream)
+{
+    msg_status st = check_batch(batch);
+    if (st != MSG_OK) return st;
+    if (kind < MSG_QOI_MEAN || kind > MSG_QOI_FLUX) return fail(MSG_ERR_ARG, "unknown quantity kind %d", kind);
+    if (!d_u || !d_q) return fail(MSG_ERR_ARG, "u and q are required");
+    if (kind == MSG_QOI_FLUX && !d_kx) return fail(MSG_ERR_ARG, "the flux needs kx");
+    hipStream_t s = (hipStream_t)stream;
+    const BatchLayout BL = make_layout(batch);
+    std::vector<int32_t> pq(2 * BL.S);
+    int maxg = 1;
+    for (int k = 0; k < BL.S; ++k) {
+        pq[2 * k] = BL.P[k];
+        pq[2 * k + 1] = BL.Q[k];
+        maxg = std::max(maxg, (BL.P[k] + 1) * (BL.Q[k] + 1));
+    }
+    void* dmem = nullptr;
+    const size_t a = align_up(sizeof(int32_t) * 2 * BL.S), b = align_up(sizeof(int64_t) * BL.S);
+    HIPCHK(hipMallocAsync(&dmem, a + 3 * b, s));
+    char* m = (char*)dmem;
+    HIPCHK(hipMemcpyAsync(m, pq.data(), sizeof(int32_t) * 2 * BL.S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(m + a, BL.cell.data(), sizeof(int64_t) * BL.S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(m + a + b, BL.xf.data(), sizeof(int64_t) * BL.S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(m + a + 2 * b, BL.grid.data(), sizeof(int64_t) * BL.S, hipMemcpyHostToDevice, s));
+    for (int s0 = 0; s0 < BL.S; s0 += 65535) {
+        const int n = std::min(65535, BL.S - s0);
+        hipError_t e = launch_qoi(n, maxg, kind, BL.c, (int32_t*)m + 2 * s0, (int64_t*)(m + a) + s0,
+                                  (int64_t*)(m + a + b) + s0, (int64_t*)(m + a + 2 * b) + s0, d_kx, d_u, d_q, s);
+        if (e != hipSuccess) return fail(MSG_ERR_HIP, "quantity launch: %s", hipGetErrorString(e));
+    }
+    HIPCHK(hipFreeAsync(dmem, s));
+    HIPCHK(hipStreamSynchronize(s));   // the host staging vectors die with this call
+    return MSG_OK;
+}
+
 msg_status mimc_delta_q(const msg_batch_desc* batch, const double* d_q, double* d_dq, msg_stream stream)
 {
     msg_status st = check_batch(batch);

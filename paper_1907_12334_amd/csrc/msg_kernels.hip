@@ -1103,6 +1103,67 @@ k_delta_q(int S, const int32_t* __restrict__ PQ, const int64_t* __restrict__ gba
 }
 
 // ------------------------------------------------------------------------
+// Quantities of interest of Section 5 per grid, one workgroup per (grid,
+// sample): the mean of u; u at (1/2,1/2) by bilinear interpolation of the
+// cell centres; the average over [1/4,1/2]^2 of the cell-wise constant
+// solution (cells weighted by their overlap); the flux through x = 1, per
+// row the wall face's 2 k u / h_x times h_y.  Sums run in a fixed order.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum1(double v)
+{
+    __shared__ double part[kBlock / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+    return t;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_qoi(int S, int kind, int c, const int32_t* __restrict__ PQ, const int64_t* __restrict__ cbase,
+      const int64_t* __restrict__ xbase, const int64_t* __restrict__ gbase, const double* __restrict__ KX,
+      const double* __restrict__ U, double* __restrict__ out)
+{
+    const int s = blockIdx.y, g = blockIdx.x;
+    if (s >= S) return;
+    const int P = PQ[2 * s], Qs = PQ[2 * s + 1];
+    if (g >= (P + 1) * (Qs + 1)) return;                  // uniform per workgroup
+    const int p = g / (Qs + 1), q = g % (Qs + 1);
+    const int nx = c << p, ny = c << q;
+    const double* u = U + cbase[s] + cell_off(c, Qs, p, q);
+    double acc = 0.0;
+    if (kind == QOI_MEAN) {
+        for (int k = threadIdx.x; k < nx * ny; k += kBlock) acc += u[k];
+        acc = block_sum1(acc) / ((double)nx * ny);
+    } else if (kind == QOI_POINT) {
+        const double tx = 0.5 * nx - 0.5, ty = 0.5 * ny - 0.5;
+        const int i0 = (int)floor(tx), j0 = (int)floor(ty);
+        const double wx = tx - i0, wy = ty - j0;
+        const int i1 = wx > 0.0 ? i0 + 1 : i0, j1 = wy > 0.0 ? j0 + 1 : j0;
+        acc = (1.0 - wx) * (1.0 - wy) * u[j0 * nx + i0] + wx * (1.0 - wy) * u[j0 * nx + i1] +
+              (1.0 - wx) * wy * u[j1 * nx + i0] + wx * wy * u[j1 * nx + i1];
+    } else if (kind == QOI_SUBDOMAIN) {
+        // cells overlapping [1/4,1/2] in each direction
+        const int ia = (nx / 4), ib = (nx + 1) / 2, ja = (ny / 4), jb = (ny + 1) / 2;
+        const int w = ib - ia, h = jb - ja;
+        for (int k = threadIdx.x; k < w * h; k += kBlock) {
+            const int i = ia + k % w, j = ja + k / w;
+            const double ox = fmin((i + 1.0) / nx, 0.5) - fmax((double)i / nx, 0.25);
+            const double oy = fmin((j + 1.0) / ny, 0.5) - fmax((double)j / ny, 0.25);
+            if (ox > 0.0 && oy > 0.0) acc += u[j * nx + i] * ox * oy;
+        }
+        acc = block_sum1(acc) / 0.0625;
+    } else {
+        const double* kx = KX + xbase[s] + xface_off(c, Qs, p, q);
+        for (int j = threadIdx.x; j < ny; j += kBlock)
+            acc += 2.0 * kx[j * (nx + 1) + nx] * u[j * nx + nx - 1] * (double)nx / (double)ny;
+        acc = block_sum1(acc);
+    }
+    if (threadIdx.x == 0) out[gbase[s] + g] = acc;
+}
+
+// ------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------
 #define LAUNCH_CHECK() (hipGetLastError())
@@ -1288,6 +1349,15 @@ hipError_t launch_delta_q(int S, int max_grids, const int32_t* PQ, const int64_t
                           hipStream_t st)
 {
     hipLaunchKernelGGL(k_delta_q, dim3((max_grids + kBlock - 1) / kBlock, S), dim3(kBlock), 0, st, S, PQ, gbase, q, dq);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_qoi(int S, int max_grids, int kind, int c, const int32_t* PQ, const int64_t* cbase,
+                      const int64_t* xbase, const int64_t* gbase, const double* KX, const double* U, double* out,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_qoi, dim3(max_grids, S), dim3(kBlock), 0, st, S, kind, c, PQ, cbase, xbase, gbase, KX, U,
+                       out);
     return LAUNCH_CHECK();
 }
 

@@ -83,6 +83,12 @@ hipError_t launch_qreduce(int K, int ntiles, int64_t cells, const KProb* probs, 
                           hipStream_t st);
 hipError_t launch_rhs_top(const KLevel& L, int K, const KProb* probs, double* BP, const double* rhs,
                           const int64_t* rhs_base, hipStream_t st);
+// quantities of interest (the same values as the C-ABI's MSG_QOI_*)
+enum QoiKind { QOI_MEAN = 0, QOI_POINT = 1, QOI_SUBDOMAIN = 2, QOI_FLUX = 3 };
+// quantity of interest `kind` of every grid of S samples
+hipError_t launch_qoi(int S, int max_grids, int kind, int c, const int32_t* PQ, const int64_t* cbase,
+                      const int64_t* xbase, const int64_t* gbase, const double* KX, const double* U, double* out,
+                      hipStream_t st);
 hipError_t launch_delta_q(int S, int max_grids, const int32_t* PQ, const int64_t* gbase, const double* q, double* dq,
                           hipStream_t st);
 hipError_t launch_activate(int K, const KProb* probs, const int32_t* dead_level, int level, int32_t* active,

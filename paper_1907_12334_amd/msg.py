@@ -22,8 +22,9 @@ FIELD_COS_TABLE, FIELD_SEPARABLE_SE = 0, 1
 FP64, MIXED = 0, 1
 
 EXPORTS = ("msg_default_opts", "msg_create", "msg_destroy", "msg_last_error", "msg_layout",
-           "msg_workspace_size", "msg_sample_field", "msg_solve_batch", "mimc_delta_q",
+           "msg_workspace_size", "msg_sample_field", "msg_solve_batch", "msg_quantity", "mimc_delta_q",
            "msg_set_profiling", "msg_get_profile")
+QOI_MEAN, QOI_POINT, QOI_SUBDOMAIN, QOI_FLUX = range(4)
 (KERNEL_SMOOTH, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_TAIL, KERNEL_RESIDUAL_NORM, KERNEL_SMOOTH_STAGE,
  KERNEL_RESTRICT_STAGE) = range(7)
 KERNEL_NAMES = ("smooth", "restrict", "prolong", "tail", "residual_norm", "smooth_stage", "restrict_stage")
@@ -84,10 +85,11 @@ def lib():
         L.msg_solve_batch.argtypes = [vp, ctypes.POINTER(BatchDescC), ctypes.POINTER(SolveOptsC),
                                       vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.mimc_delta_q.argtypes = [ctypes.POINTER(BatchDescC), vp, vp, vp]
+        L.msg_quantity.argtypes = [ctypes.POINTER(BatchDescC), ctypes.c_int, vp, vp, vp, vp]
         L.msg_set_profiling.argtypes = [vp, ctypes.c_int]
         L.msg_get_profile.argtypes = [vp, ctypes.c_int, ctypes.POINTER(KernelStatsC)]
         for n in ("msg_create", "msg_layout", "msg_workspace_size", "msg_sample_field", "msg_solve_batch",
-                  "mimc_delta_q", "msg_set_profiling", "msg_get_profile"):
+                  "msg_quantity", "mimc_delta_q", "msg_set_profiling", "msg_get_profile"):
             getattr(L, n).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -239,6 +241,12 @@ class Handle:
                                      _ptr(cycles), _ptr(ws), ws.numel() * ws.element_size() if ws is not None else 0,
                                      _stream(stream)),
                "msg_solve_batch")
+
+
+def quantity(batch: Batch, kind: int, kx, u, q, stream=None):
+    """Per-grid quantity of interest `kind` (QOI_*) of solutions u into q."""
+    _check(lib().msg_quantity(ctypes.byref(batch.c_struct), int(kind), _ptr(kx), _ptr(u), _ptr(q), _stream(stream)),
+           "msg_quantity")
 
 
 def delta_q(batch: Batch, q, dq, stream=None):

@@ -265,3 +265,43 @@ def test_full_size_config2_sampled(handle):
         g = PR.per_sample(out, s)
         eu, eq, edq, _ = PR.compare_sample(w.c, 7, 7, w.field, xi[s], g, max_cycles=w.max_cycles)
         assert eu <= FP64_TOL and eq <= FP64_TOL and edq <= FP64_TOL, (s, eu, eq, edq)
+
+
+@pytest.mark.parametrize("kind", [msg.QOI_MEAN, msg.QOI_POINT, msg.QOI_SUBDOMAIN, msg.QOI_FLUX])
+def test_quantities_of_interest_match_oracle(handle, kind):
+    """Section 5's quantities on every grid: from the GPU's own solutions they
+    equal the oracle's functional to rounding; end to end (oracle solution)
+    within the FP64 bar; their differences follow as for Q."""
+    import torch
+    c, P, Q = 3, [2, 1, 3, 0], [1, 2, 0, 2]                     # odd sizes: the point is a cell centre on some grids
+    spec = I.KL10
+    xi = I.draw_xi(spec.n_terms, range(len(P)))
+    out = PR.gpu_solve(c, P, Q, spec, xi, msg.SolveOpts(), handle=handle)
+    b = msg.Batch(c, P, Q)
+    dev = lambda a, dt=torch.float64: torch.tensor(a, dtype=dt, device="cuda:0")
+    q = torch.empty(int(out["layout"]["grid"][-1]), dtype=torch.float64, device="cuda:0")
+    msg.quantity(b, kind, dev(out["kx"]), dev(out["u"]), q)
+    qg = q.cpu().numpy()
+    lay = out["layout"]
+    for s in range(len(P)):
+        g = PR.per_sample(out, s)
+        mine = qg[lay["grid"][s]:lay["grid"][s + 1]]
+        same_u = O.qoi(c, P[s], Q[s], g["u"], g["kx"], kind)
+        assert np.allclose(mine, same_u, rtol=1e-13, atol=1e-15), (s, mine, same_u)
+        ora = PR.oracle_solve(c, P[s], Q[s], spec, xi[s])
+        ref = O.qoi(c, P[s], Q[s], ora["u"], ora["kx"], kind)
+        assert np.max(np.abs(mine - ref) / np.abs(ref)) <= FP64_TOL
+        if kind == msg.QOI_MEAN:
+            assert np.allclose(mine, g["q"], rtol=1e-14, atol=0)
+    assert np.all(qg > 0)                                          # h = 1 > 0: u > 0 and outward flux
+
+
+def test_quantity_argument_errors(handle):
+    b = msg.Batch(4, [1], [1])
+    with pytest.raises(msg.MsgError):
+        msg.quantity(b, 7, None, None, None)
+    import torch
+    u = torch.zeros(int(b.layout()["cell"][-1]), dtype=torch.float64, device="cuda:0")
+    q = torch.zeros(int(b.layout()["grid"][-1]), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(msg.MsgError):
+        msg.quantity(b, msg.QOI_FLUX, None, u, q)                  # the flux needs kx
