@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-ragged", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--skip-mimc", action="store_true")
     ap.add_argument("--skip-one-stream", action="store_true", help="no extra one-stream profiled step")
     ap.add_argument("--no-tune", action="store_true", help="library default plan instead of the autotuner's")
     ap.add_argument("--tune-cycles", type=int, default=1, help="cycles per stage in each autotuner trial")
@@ -218,6 +219,9 @@ def main():
     if not args.skip_serve:
         extra["serving"] = serve_leg(msg, I, args)
 
+    if not args.skip_mimc:
+        extra["msg_mimc"] = mimc_leg(h, msg, I)
+
     cpu = None
     if not args.skip_cpu:
         cpu = cpu_baseline(w, args.cpu_samples)
@@ -350,6 +354,22 @@ def ragged_leg(h, msg, I, torch):
     return {"workload": w.name, "samples": w.n_samples, "value": round(w.n_samples / t, 1), "unit": "samples/s",
             "seconds": round(t, 3), "converged": int(np.sum(bufs.status.cpu().numpy() == 0)),
             "max_cycles_per_grid": int(bufs.cycles.cpu().numpy().max())}
+
+
+def mimc_leg(h, msg, I):
+    """Algorithm MSG-MIMC to a fixed RMSE for the point value and the boundary
+    flux (KL-10, c = 4, mixed precision to 1e-8), batches of 512 samples."""
+    from paper_1907_12334_amd import mimc as M
+    out = {"field": "KL-10", "c": 4, "precision": "mixed, refined to 1e-8", "batch": 512}
+    for name, kind, tol in (("Q1_point", msg.QOI_POINT, 3e-4), ("Q3_flux", msg.QOI_FLUX, 3e-3)):
+        r = M.MSGMIMC(h, I.KL10, c=4, kind=kind).run(tol=tol, batch=512)
+        top = sorted(r.index_counts.items(), key=lambda kv: -kv[1])[:6]
+        out[name] = {"tol": tol, "E": r.E, "rmse": r.rmse, "samples": r.N, "batches": r.batches,
+                     "seconds": round(r.seconds, 3), "samples_per_s": round(r.N / r.seconds, 1),
+                     "learned_rates": [round(x, 3) for x in r.rates],
+                     "most_drawn_indices": [[list(k), v] for k, v in top]}
+        log(f"MSG-MIMC {name}: E={r.E:.6f} rmse={r.rmse:.2e} N={r.N} in {r.seconds:.1f} s")
+    return out
 
 
 def serve_leg(msg, I, args):

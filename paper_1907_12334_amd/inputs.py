@@ -119,6 +119,12 @@ def config(k: int) -> Workload:
     raise ValueError(f"no workload preset {k}")
 
 
+def mimc_uniforms(n: int, batch: int = 0, seed: int = BASE_SEED + 6, d: int = 2) -> np.ndarray:
+    """U(0,1] draws, one row per Monte Carlo sample of batch `batch` of the
+    multi-index estimator, from which each side draws its random index L."""
+    return 1.0 - np.random.default_rng([int(seed), int(batch)]).random((n, d))
+
+
 def request_trace(n: int, rate: float, seed: int = BASE_SEED + 5, lmax: int = 9):
     """Poisson arrivals (exponential gaps at `rate`/s) of requests whose finest
     index per direction is l in 1..lmax with probability proportional to

@@ -1,0 +1,122 @@
+"""Multi-index Monte Carlo with sample reuse: the reference estimator pinned
+to closed forms (unbiasedness by exact enumeration, the sampler's tail law,
+Theorem 1 by direct cost accounting), the product's host arithmetic against
+it, and on the GPU the batched estimator against the reference estimator fed
+with oracle solutions of the same samples."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mimc_oracle as MO
+from paper_1907_12334_amd import inputs as I
+from paper_1907_12334_amd import mimc as M
+
+
+def test_unbiased_by_exact_enumeration():
+    """E[Y] over the geometric index equals the telescoped sum of the
+    differences, here a closed form (no truncation of the index set)."""
+    r = (0.9, 1.3)
+    dq = {(a, b): 0.3 * 2.0 ** (-2 * a) * 3.0 ** (-b) for a in range(80) for b in range(80)}
+    total = 0.3 / ((1 - 1 / 4) * (1 - 1 / 3))
+    ey = 0.0
+    for L1, L2 in itertools.product(range(45), range(45)):
+        prob = ((1 - math.exp(-r[0])) * math.exp(-r[0] * L1)) * ((1 - math.exp(-r[1])) * math.exp(-r[1] * L2))
+        ey += prob * MO.sample_y(dq, (L1, L2), r)
+    assert abs(ey - total) <= 1e-10 * total
+
+
+def test_geometric_sampler_tail_law():
+    """P(L >= l) = exp(-r l): exact at the inverse-transform boundaries, and
+    empirically on many draws."""
+    r = 1.7
+    for l in range(6):
+        u = math.exp(-r * l)
+        assert MO.draw_index((r,), (u,))[0] == l
+        assert MO.draw_index((r,), (u * (1 + 1e-12),))[0] == l - 1 if l > 0 else True
+    u = I.mimc_uniforms(200000, 0)[:, 0]
+    L = np.array([MO.draw_index((r,), (x,))[0] for x in u[:20000]])
+    for l in range(4):
+        p = math.exp(-r * l)
+        assert abs(np.mean(L >= l) - p) <= 4 * math.sqrt(p * (1 - p) / len(L)) + 1e-12
+
+
+@pytest.mark.parametrize("beta,gamma", [((4.73, 4.47), (1.27, 1.21)), ((2.21, 2.57), (1.21, 1.34)),
+                                        ((1.36, 1.51), (1.49, 1.26)), ((4.0, 4.0), (1.0, 1.0))])
+def test_theorem1_by_direct_cost_accounting(beta, gamma):
+    """Theorem 1 against the sums it summarises: sample sizes N_tau ~
+    prod 2^(-(gamma+beta) tau / 2), the reuse-reduced sizes of its proof and
+    costs prod 2^(gamma tau), summed over a large box; and in two
+    directions the factorised form (1 - a1)(1 - a2)."""
+    K = 120
+    a = [2.0 ** (-(g + b) / 2.0) for b, g in zip(beta, gamma)]
+    num = den = 0.0
+    for t1 in range(K):
+        for t2 in range(K):
+            N = lambda x, y: 2.0 ** (-(gamma[0] + beta[0]) * x / 2) * 2.0 ** (-(gamma[1] + beta[1]) * y / 2)
+            C = 2.0 ** (gamma[0] * t1) * 2.0 ** (gamma[1] * t2)
+            Nr = N(t1, t2) - (N(t1 + 1, t2) + N(t1, t2 + 1) - N(t1 + 1, t2 + 1))
+            num += Nr * C
+            den += N(t1, t2) * C
+    ratio = MO.cost_ratio(beta, gamma)
+    assert abs(ratio - num / den) <= 1e-12
+    assert abs(ratio - (1 - a[0]) * (1 - a[1])) <= 1e-14
+
+
+def test_estimate_matches_sample_statistics():
+    ys = list(np.random.default_rng(3).standard_normal(50))
+    e, v = MO.estimate(ys)
+    assert abs(e - np.mean(ys)) <= 1e-15 and abs(v - np.var(ys, ddof=1) / len(ys)) <= 1e-15
+
+
+def test_product_host_arithmetic_matches_reference():
+    """The driver's vectorised draws, weights and statistics equal the
+    reference's loops on the same uniforms."""
+    r = M.initial_rates()
+    u = I.mimc_uniforms(500, 3)
+    L = M.draw_indices(u, r, lmax=30)
+    ref = np.array([MO.draw_index(tuple(r), tuple(x)) for x in u])
+    assert np.array_equal(L, ref)
+    rng = np.random.default_rng(9)
+    for P, Q in [(0, 0), (3, 2), (1, 5)]:
+        d = rng.standard_normal((P + 1) * (Q + 1))
+        table = {(a, b): d[a * (Q + 1) + b] for a in range(P + 1) for b in range(Q + 1)}
+        assert abs(np.dot(d, M.reuse_weights(P, Q, r)) - MO.sample_y(table, (P, Q), tuple(r))) <= 1e-12 * (
+            1 + abs(MO.sample_y(table, (P, Q), tuple(r))))
+    assert abs(M.initial_rates()[0] - math.log(2) * 5 / 2) <= 1e-15
+
+
+@pytest.mark.gpu
+def test_batched_estimator_matches_reference_on_oracle_solutions():
+    """Two batches of 24 samples, fixed rates, indices capped at 3: the GPU
+    estimator's E and V equal the reference estimator's on oracle solutions
+    of the same samples (same uniforms, same xi) to the FP64 bar."""
+    import torch
+    from oracle import binding as O
+    from paper_1907_12334_amd import msg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = msg.Handle(0)
+    est = M.MSGMIMC(h, I.KL10, c=4, kind=msg.QOI_POINT, opts=msg.SolveOpts(tol=1e-10), lmax=3,
+                    r0=np.array([0.6, 0.8]), learn=False)
+    est.add_batch(24)
+    est.add_batch(24)
+    e, v = est.estimate()
+    ys, sid = [], 0
+    for b in range(2):
+        u = I.mimc_uniforms(24, b, est.seed)
+        for x in u:
+            L = MO.draw_index((0.6, 0.8), tuple(x))
+            L = (min(L[0], 3), min(L[1], 3))
+            xi = I.draw_xi(I.KL10.n_terms, [sid], est.seed)[0]
+            sid += 1
+            kx, ky = O.hierarchy_field(4, L[0], L[1], I.KL10.as_dict(), xi)
+            r = O.fmsg_solve(4, L[0], L[1], kx, ky, O.opts(tol=1e-10))
+            q = O.qoi(4, L[0], L[1], r["u"], kx, O.QOI_POINT)
+            dq = O.delta_q(L[0], L[1], q)
+            table = {(a, c): dq[a * (L[1] + 1) + c] for a in range(L[0] + 1) for c in range(L[1] + 1)}
+            ys.append(MO.sample_y(table, L, (0.6, 0.8)))
+    e0, v0 = MO.estimate(ys)
+    assert abs(e - e0) <= 1e-9 * abs(e0) and abs(v - v0) <= 1e-7 * v0
+    assert len(est.counts) > 3                        # the draws spread over several rectangles
