@@ -37,6 +37,9 @@ def lib():
         L.oracle_msg_cycles.argtypes = [ctypes.c_int] * 3 + [_D, _D, _D, ctypes.POINTER(OracleOpts),
                                                               ctypes.c_int, _D, _D]
         L.oracle_delta_q.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D]
+        L.oracle_mg_cycles.argtypes = [ctypes.c_int] * 3 + [_D, _D, _D, ctypes.POINTER(OracleOpts),
+                                                             ctypes.c_int, _D, _D]
+        L.oracle_mg_cycles.restype = None
         L.oracle_qoi_grid.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_int]
         L.oracle_qoi_grid.restype = ctypes.c_double
         for name in ("oracle_apply",):
@@ -217,6 +220,20 @@ def fmsg_solve(c, P, Q, kx_all, ky_all, o=None, rhs_top=None, forced_cycles=None
     if want_hist:
         res["hist"] = hist.reshape(ng, o.max_cycles + 1)
     return res
+
+
+def mg_cycles(c, P, Q, kx_all, ky_all, ncycles, o=None, rhs_top=None):
+    """Standard-coarsening multigrid cycles from zero on the finest grid.
+    Returns (u_top, ratios)."""
+    o = o or opts()
+    nx, ny = c << P, c << Q
+    kx_all, ky_all = f64(kx_all), f64(ky_all)
+    u = np.empty(nx * ny)
+    ratios = np.empty(ncycles + 1)
+    rhs = f64(rhs_top) if rhs_top is not None else None
+    lib().oracle_mg_cycles(c, P, Q, _d(kx_all), _d(ky_all), _d(rhs) if rhs is not None else None,
+                           ctypes.byref(o), ncycles, _d(u), _d(ratios))
+    return u, ratios
 
 
 def msg_cycles(c, P, Q, kx_all, ky_all, ncycles, o=None, rhs_top=None):

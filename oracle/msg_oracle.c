@@ -299,9 +299,9 @@ static void interp_combine(ohier *H, int p, int q, int cubic, double *out)
 /* ------------------------------------------------------------------------ */
 /* Coarsest grid: dense Cholesky of A^(0,0), assembled column by column.      */
 /* ------------------------------------------------------------------------ */
-static int coarse_factor(ohier *H)
+/* dense Cholesky factor L (n*n, n = nx*ny) of one grid's matrix */
+static int dense_factor(const ogrid *g, double *L)
 {
-    ogrid *g = grid_at(H, 0, 0);
     int n = g->nx * g->ny;
     double *e = calloc((size_t)n, sizeof(double)), *col = malloc((size_t)n * sizeof(double));
     double *A = malloc((size_t)n * n * sizeof(double));
@@ -311,7 +311,6 @@ static int coarse_factor(ohier *H)
         apply_grid(g, e, col);
         for (int m = 0; m < n; ++m) A[(size_t)m * n + k] = col[m];
     }
-    double *L = H->chol;
     memset(L, 0, (size_t)n * n * sizeof(double));
     int ok = 1;
     for (int j = 0; j < n; ++j) {
@@ -329,12 +328,10 @@ static int coarse_factor(ohier *H)
     return ok;
 }
 
-/* v^(0,0) = (A^(0,0))^{-1} b^(0,0): forward then backward substitution */
-static void coarse_solve(ohier *H)
+/* v = A^{-1} b on one grid from its factor: forward then backward substitution */
+static void dense_solve(ogrid *g, const double *L)
 {
-    ogrid *g = grid_at(H, 0, 0);
     int n = g->nx * g->ny;
-    const double *L = H->chol;
     double *y = malloc((size_t)n * sizeof(double));
     for (int i = 0; i < n; ++i) {
         double s = g->b[i];
@@ -348,6 +345,11 @@ static void coarse_solve(ohier *H)
     }
     free(y);
 }
+
+static int coarse_factor(ohier *H) { return dense_factor(grid_at(H, 0, 0), H->chol); }
+
+/* v^(0,0) = (A^(0,0))^{-1} b^(0,0) */
+static void coarse_solve(ohier *H) { dense_solve(grid_at(H, 0, 0), H->chol); }
 
 /* ------------------------------------------------------------------------ */
 /* Algorithm MSG mu-cycle (recursive definition)                             */
@@ -653,6 +655,62 @@ void oracle_msg_cycles(int c, int P, int Q, const double *kx_all, const double *
         if (k < ncycles) mu_cycle(&H, P + Q, o);
     }
     memcpy(u_top, g->v, n * sizeof(double));
+    hier_free(&H);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Standard-coarsening multigrid, the comparison of Section 2 (its Fig. of    */
+/* convergence factors): grid (p,q) coarsens to (p-1,q-1) until one index is */
+/* zero, where the grid is solved directly.  Restriction and prolongation are */
+/* the products of the one-directional cell-centred operators (the 2D average */
+/* of four cells, and bilinear interpolation), the operator is rediscretised */
+/* on every grid, the smoother is the same red-black Gauss-Seidel.            */
+/* ------------------------------------------------------------------------ */
+static void mg_cycle(ohier *H, int k, int m, const double *Lc, const oracle_opts *o)
+{
+    ogrid *g = grid_at(H, H->P - k, H->Q - k);
+    if (k == m) { dense_solve(g, Lc); return; }
+    ogrid *gc = grid_at(H, H->P - k - 1, H->Q - k - 1);
+    size_t n = (size_t)g->nx * g->ny;
+    for (int s = 0; s < o->nu1; ++s) rbgs_sweep(g, g->b, g->v);
+    residual_grid(g, g->b, g->v, g->r);
+    double *half = malloc((size_t)gc->nx * g->ny * sizeof(double));
+    restrict_x(gc->nx, g->ny, g->r, half);               /* (nx, ny) -> (nx/2, ny) */
+    restrict_y(gc->nx, gc->ny, half, gc->b);             /* -> (nx/2, ny/2) */
+    memset(gc->v, 0, (size_t)gc->nx * gc->ny * sizeof(double));
+    for (int t = 0; t < o->mu; ++t) mg_cycle(H, k + 1, m, Lc, o);
+    double *corr = malloc(n * sizeof(double));
+    prolong_y(gc->nx, gc->ny, gc->v, half, 0);           /* (nx/2, ny/2) -> (nx/2, ny) */
+    prolong_x(gc->nx, g->ny, half, corr, 0);             /* -> (nx, ny) */
+    for (size_t t = 0; t < n; ++t) g->v[t] += o->omega * corr[t];
+    for (int s = 0; s < o->nu2; ++s) rbgs_sweep(g, g->b, g->v);
+    free(half); free(corr);
+}
+
+/* ncycles standard-multigrid mu-cycles from zero on the finest grid (P,Q);
+ * ratios[k] = ||b - A v_k|| / ||b|| for k = 0..ncycles. */
+void oracle_mg_cycles(int c, int P, int Q, const double *kx_all, const double *ky_all,
+                      const double *rhs_top, const oracle_opts *o, int ncycles,
+                      double *u_top, double *ratios)
+{
+    ohier H;
+    hier_init(&H, c, P, Q, kx_all, ky_all);
+    set_top_rhs(&H, rhs_top);
+    const int m = P < Q ? P : Q;
+    ogrid *gm = grid_at(&H, P - m, Q - m);
+    size_t nm = (size_t)gm->nx * gm->ny;
+    double *Lc = malloc(nm * nm * sizeof(double));
+    dense_factor(gm, Lc);
+    ogrid *g = grid_at(&H, P, Q);
+    size_t n = (size_t)g->nx * g->ny;
+    double bn = norm2(g->b, n);
+    for (int k = 0; k <= ncycles; ++k) {
+        residual_grid(g, g->b, g->v, g->r);
+        ratios[k] = norm2(g->r, n) / bn;
+        if (k < ncycles) mg_cycle(&H, 0, m, Lc, o);
+    }
+    memcpy(u_top, g->v, n * sizeof(double));
+    free(Lc);
     hier_free(&H);
 }
 

@@ -602,3 +602,51 @@ def test_mean_quantity_matches_the_solver_q(oracle):
     kx, ky = oracle.hierarchy_field(c, P, Q, I.KL10.as_dict(), I.draw_xi(10, [5])[0])
     r = oracle.fmsg_solve(c, P, Q, kx, ky, oracle.opts())
     assert np.allclose(oracle.qoi(c, P, Q, r["u"], kx, oracle.QOI_MEAN), r["q"], rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------------------- standard multigrid (comparison)
+def aniso_faces(O, c, P, Q, ex, ey):
+    kx, ky = [], []
+    for p, q, nx, ny in O.grid_shapes(c, P, Q):
+        kx.append(np.full((nx + 1) * ny, ex))
+        ky.append(np.full(nx * (ny + 1), ey))
+    return np.concatenate(kx), np.concatenate(ky)
+
+
+def test_mg_on_the_coarsest_grid_is_a_direct_solve(oracle):
+    kx, ky = aniso_faces(oracle, 4, 0, 0, 1.0, 1.0)
+    _, r = oracle.mg_cycles(4, 0, 0, kx, ky, 1)
+    assert r[0] == 1.0 and r[1] <= 1e-14
+
+
+@pytest.mark.parametrize("P,Q", [(3, 3), (4, 2)])
+def test_mg_converges_to_the_dense_solution(oracle, P, Q):
+    """Square and rectangular (coarsest 16x4) hierarchies with a KL-10 field:
+    the cycles converge to numpy's dense solve of the finest system."""
+    c = 2
+    kx, ky = oracle.hierarchy_field(c, P, Q, I.KL10.as_dict(), I.draw_xi(10, [11])[0])
+    nx, ny = c << P, c << Q
+    fx = sum((a + 1) * b for _, _, a, b in oracle.grid_shapes(c, P, Q)[:-1])
+    fy = sum(a * (b + 1) for _, _, a, b in oracle.grid_shapes(c, P, Q)[:-1])
+    A = dense(oracle, nx, ny, kx[fx:], ky[fy:])
+    exact = np.linalg.solve(A, np.ones(nx * ny))
+    u, r = oracle.mg_cycles(c, P, Q, kx, ky, 40)
+    assert r[-1] <= 1e-11
+    assert np.linalg.norm(u - exact) <= 1e-9 * np.linalg.norm(exact)
+
+
+def test_mg_isotropic_factor_and_anisotropic_breakdown(oracle):
+    """Point-smoothed standard multigrid converges fast for an isotropic
+    coefficient and stalls as the coefficient becomes anisotropic, while MSG
+    keeps its factor (the robustness Section 2 claims for MSG)."""
+    c, P, Q = 2, 5, 5
+    o = oracle.opts(nu1=2, nu2=2)
+
+    def factor(fn, ex, ey):
+        kx, ky = aniso_faces(oracle, c, P, Q, ex, ey)
+        _, r = fn(c, P, Q, kx, ky, 12, o)
+        return (r[-1] / r[2]) ** (1 / 10)
+
+    assert factor(oracle.mg_cycles, 1.0, 1.0) <= 0.2
+    assert factor(oracle.mg_cycles, 1.0, 1e-3) >= 0.8
+    assert factor(oracle.msg_cycles, 1.0, 1e-3) <= 0.2
