@@ -203,6 +203,39 @@ msg_status msg_quantity(const msg_batch_desc *batch, int kind, const double *d_k
 msg_status mimc_delta_q(const msg_batch_desc *batch, const double *d_q, double *d_dq,
                         msg_stream stream);
 
+/* Plain cycles from zero, the convergence-factor comparison of Section 2.
+ * Every sample runs `ncycles` cycles on its finest grid (P,Q), started from
+ * v = 0 with right-hand side h = 1 (d_rhs NULL) or d_rhs, and reports the
+ * residual ratio ||h - A v_k|| / ||h|| (Euclidean norms over the cells)
+ * before each cycle k = 0..ncycles.
+ *   MSG_CYCLES_MSG  the mu-cycle of Algorithm MSG on the semi-coarsened
+ *                   family (grids of every level below (P,Q));
+ *   MSG_CYCLES_MG   standard multigrid: grid (p,q) coarsens to (p-1,q-1),
+ *                   restriction is the average of the four fine cells of a
+ *                   coarse cell, prolongation the bilinear interpolation of
+ *                   the cell-centred iterate (odd reflection at the walls),
+ *                   the operator is rediscretised on each grid from that
+ *                   grid's face conductances, the coarsest grid (0,0) is
+ *                   solved exactly, the smoother is the same red-black
+ *                   Gauss-Seidel; requires P == Q.
+ * Both use mu, nu1, nu2 and omega of `opts` (tol, max_cycles and the
+ * adaptive rule are not used; every cycle runs); precision must be
+ * MSG_FP64.  The batch must be uniform (one (P,Q) for every sample).
+ * d_kx, d_ky: device FP64 faces (msg_sample_field layout).  d_rhs: NULL or
+ * device FP64 [n_samples][finest cells], sample-major.  d_u_top: device FP64
+ * [n_samples][finest cells], the iterate after the last cycle.  d_ratios:
+ * device FP64 [n_samples][ncycles + 1].  Workspace from
+ * msg_cycles_workspace_size (whose handle may be NULL; 256-byte aligned).  Errors: MSG_ERR_ARG (bad
+ * pointer, kind, ncycles outside 0..10000), MSG_ERR_UNSUPPORTED (ragged
+ * batch, P != Q for MG, precision other than FP64, a tail that does not fit
+ * LDS), MSG_ERR_WORKSPACE.  Enqueued on `stream`; returns after it completes. */
+enum { MSG_CYCLES_MSG = 0, MSG_CYCLES_MG = 1 };
+msg_status msg_cycles_workspace_size(msg_handle h, const msg_batch_desc *batch, const msg_solve_opts *opts,
+                                     int kind, size_t *bytes);
+msg_status msg_cycles(msg_handle h, const msg_batch_desc *batch, const msg_solve_opts *opts, int kind,
+                      int ncycles, const double *d_kx, const double *d_ky, const double *d_rhs,
+                      double *d_u_top, double *d_ratios, void *d_ws, size_t ws_bytes, msg_stream stream);
+
 /* Per-kernel timing (measurement support).  While enabled, msg_solve_batch
  * records a pair of HIP events around every launch of each kernel kind on
  * the stream it runs on and accumulates, per kind, the launches, the summed

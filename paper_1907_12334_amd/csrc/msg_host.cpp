@@ -358,67 +358,83 @@ int choose_tail(int c, int pc, int qc, int L, int req, size_t budget, const std:
     return best;
 }
 
+// The plan of class (pc,qc) on stage L = pc + qc for the problems of
+// `samples`: arena layout of its grids, tail, smoother tiles and transfer
+// launches per level.  Stage tables (first problem, arena, partial sums, tail
+// images) are set by the caller.  With `host_cycles` the class never runs
+// its whole solve in one kernel.
+ClassPlan plan_class(int c, int pc, int qc, std::vector<int> samples, const msg_solve_opts& o, const Tuning& tu,
+                     bool host_cycles)
+{
+    const int L = pc + qc;
+    const int H = 2 * g_fuse;
+    ClassPlan C;
+    C.pc = pc;
+    C.qc = qc;
+    C.L = L;
+    C.samples = std::move(samples);
+    C.K = (int)C.samples.size();
+    C.goff.assign((size_t)(pc + 1) * (qc + 1), 0);
+    int64_t off = 0;
+    for (int a = 0; a <= pc; ++a)
+        for (int b = 0; b <= qc; ++b) {
+            C.goff[a * (qc + 1) + b] = off;
+            off += grid_cells(c, a, b);
+        }
+    C.stride = off;
+    // classes whose whole rectangle fits in LDS run their adaptive
+    // cycles inside one FP64 kernel; the others cycle on the host
+    // down to a tail of levels 0..tail_top < L
+    const size_t b64 = L < kMaxTailLevels ? tail_layout<double>(c, pc, qc, L, C.goff, C.tail64) : 0;
+    C.tail64_lds = b64;
+    if (o.tail_levels >= 0) C.solve_in_tail = L <= o.tail_levels && b64 > 0;
+    else C.solve_in_tail = b64 > 0 && b64 <= (size_t)g_solve_lds;
+    if (L == 0) C.solve_in_tail = b64 > 0;
+    if (host_cycles) C.solve_in_tail = false;
+    const int mcap = std::max(0, L - 1);
+    C.tail_top = o.precision == MSG_MIXED ? choose_tail<float>(c, pc, qc, mcap, o.tail_levels, tu.tail_budget, C.goff)
+                                           : choose_tail<double>(c, pc, qc, mcap, o.tail_levels, tu.tail_budget, C.goff);
+    C.tail_lds = o.precision == MSG_MIXED ? tail_layout<float>(c, pc, qc, C.tail_top, C.goff, C.tail)
+                                           : tail_layout<double>(c, pc, qc, C.tail_top, C.goff, C.tail);
+    C.top1d = level_1d(c, pc, qc, L, C.goff, 1, qc);
+    C.rb.resize(L + 1);
+    C.rbc.resize(L + 1);
+    C.pro.resize(L + 1);
+    C.res.resize(L + 1);
+    for (int lev = 1; lev <= L; ++lev) {
+        C.rb[lev] = level_rbgs(c, pc, qc, lev, C.goff, H, tu);
+        C.rbc[lev] = C.rb[lev];
+        for (int g = 0; g < C.rbc[lev].ngrids; ++g) {
+            KGrid& G = C.rbc[lev].g[g];
+            G.aoff_x = G.p > 0 ? C.goff[(G.p - 1) * (qc + 1) + G.q] : -1;
+            G.aoff_y = G.q > 0 ? C.goff[G.p * (qc + 1) + G.q - 1] : -1;
+        }
+        C.pro[lev] = level_1d(c, pc, qc, lev, C.goff, 1, qc, -1);
+        C.res[lev] = level_1d(c, pc, qc, lev - 1, C.goff, 2, qc, -1);
+    }
+    return C;
+}
+
 std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o)
 {
     const Tuning tu = tuning_of(o);
     std::vector<StagePlan> plans(BL.maxL + 1);
     const int c = BL.c;
-    const int H = 2 * g_fuse;
     for (int L = 0; L <= BL.maxL; ++L) {
         StagePlan& SP = plans[L];
         SP.L = L;
         for (int pc = 0; pc <= L; ++pc) {
             const int qc = L - pc;
             if (pc > kMaxIndex || qc > kMaxIndex) continue;
-            ClassPlan C;
-            C.pc = pc;
-            C.qc = qc;
-            C.L = L;
+            std::vector<int> samples;
             for (int s = 0; s < BL.S; ++s)
-                if (BL.P[s] >= pc && BL.Q[s] >= qc) C.samples.push_back(s);
-            if (C.samples.empty()) continue;
-            C.K = (int)C.samples.size();
-            C.goff.assign((size_t)(pc + 1) * (qc + 1), 0);
-            int64_t off = 0;
-            for (int a = 0; a <= pc; ++a)
-                for (int b = 0; b <= qc; ++b) {
-                    C.goff[a * (qc + 1) + b] = off;
-                    off += grid_cells(c, a, b);
-                }
-            C.stride = off;
+                if (BL.P[s] >= pc && BL.Q[s] >= qc) samples.push_back(s);
+            if (samples.empty()) continue;
+            ClassPlan C = plan_class(c, pc, qc, std::move(samples), o, tu, false);
             C.first = SP.K;
             C.arena = SP.arena_cells;
             SP.K += C.K;
             SP.arena_cells += C.stride * C.K;
-            // classes whose whole rectangle fits in LDS run their adaptive
-            // cycles inside one FP64 kernel; the others cycle on the host
-            // down to a tail of levels 0..tail_top < L
-            const size_t b64 = L < kMaxTailLevels ? tail_layout<double>(c, pc, qc, L, C.goff, C.tail64) : 0;
-            C.tail64_lds = b64;
-            if (o.tail_levels >= 0) C.solve_in_tail = L <= o.tail_levels && b64 > 0;
-            else C.solve_in_tail = b64 > 0 && b64 <= (size_t)g_solve_lds;
-            if (L == 0) C.solve_in_tail = b64 > 0;
-            const int mcap = std::max(0, L - 1);
-            C.tail_top = o.precision == MSG_MIXED ? choose_tail<float>(c, pc, qc, mcap, o.tail_levels, tu.tail_budget, C.goff)
-                                                   : choose_tail<double>(c, pc, qc, mcap, o.tail_levels, tu.tail_budget, C.goff);
-            C.tail_lds = o.precision == MSG_MIXED ? tail_layout<float>(c, pc, qc, C.tail_top, C.goff, C.tail)
-                                                   : tail_layout<double>(c, pc, qc, C.tail_top, C.goff, C.tail);
-            C.top1d = level_1d(c, pc, qc, L, C.goff, 1, qc);
-            C.rb.resize(L + 1);
-            C.rbc.resize(L + 1);
-            C.pro.resize(L + 1);
-            C.res.resize(L + 1);
-            for (int lev = 1; lev <= L; ++lev) {
-                C.rb[lev] = level_rbgs(c, pc, qc, lev, C.goff, H, tu);
-                C.rbc[lev] = C.rb[lev];
-                for (int g = 0; g < C.rbc[lev].ngrids; ++g) {
-                    KGrid& G = C.rbc[lev].g[g];
-                    G.aoff_x = G.p > 0 ? C.goff[(G.p - 1) * (qc + 1) + G.q] : -1;
-                    G.aoff_y = G.q > 0 ? C.goff[G.p * (qc + 1) + G.q - 1] : -1;
-                }
-                C.pro[lev] = level_1d(c, pc, qc, lev, C.goff, 1, qc, -1);
-                C.res[lev] = level_1d(c, pc, qc, lev - 1, C.goff, 2, qc, -1);
-            }
             C.part0 = SP.part_slots;
             SP.part_slots += (int64_t)C.top1d.ntiles * C.K;
             if (!C.solve_in_tail && C.tail_lds > 0) {
@@ -554,8 +570,8 @@ struct Profiler {
     }
     ~Profiler()
     {
-        for (hipEvent_t e : pool) hipEventDestroy(e);
-        for (Rec& r : pending) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        for (Rec& r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     }
 };
 
@@ -1548,6 +1564,307 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
     }
     for (int k = 0; k < kParts; ++k)
         if (res[k] != MSG_OK) return fail(res[k], "part %d: %s", k, err[k].c_str());
+    return MSG_OK;
+}
+
+// ---------------------------------------------------------------- plain cycles
+namespace {
+
+// Standard multigrid on the grids (P-k, Q-k), k = 0..m, of a sample: their
+// arena offsets and the launches on each.
+struct MgPlan {
+    int m = 0;
+    int64_t stride = 0;                 // arena cells per problem
+    std::vector<int64_t> goff;          // arena offset of grid k
+    std::vector<KLevel> rb;             // smoother tiles of grid k
+    std::vector<KLevel> res;            // restriction into grid k (k >= 1) from grid k-1
+    std::vector<KLevel> pro;            // prolongation onto grid k (k < m) from grid k+1
+    KLevel top1d;                       // grid 0, 1-D tiles of kBlock cells
+};
+
+KLevel one_grid(KLevel L, int64_t aoff, int64_t aoff_x)
+{
+    L.g[0].aoff = aoff;
+    L.g[0].aoff_x = aoff_x;
+    L.g[0].aoff_y = -1;
+    return L;
+}
+
+MgPlan plan_mg(int c, int P, int Q, const Tuning& tu)
+{
+    MgPlan M;
+    M.m = std::min(P, Q);
+    const int H = 2 * g_fuse;
+    for (int k = 0; k <= M.m; ++k) {
+        M.goff.push_back(M.stride);
+        M.stride += grid_cells(c, P - k, Q - k);
+    }
+    M.rb.resize(M.m + 1);
+    M.res.resize(M.m + 1);
+    M.pro.resize(M.m + 1);
+    for (int k = 0; k <= M.m; ++k) {
+        // the class (a,b) on its own level a+b holds the single grid (a,b)
+        const int a = P - k, b = Q - k;
+        const std::vector<int64_t> zero((size_t)(a + 1) * (b + 1), 0);
+        M.rb[k] = one_grid(level_rbgs(c, a, b, a + b, zero, H, tu), M.goff[k], -1);
+        const KLevel l1 = level_1d(c, a, b, a + b, zero, 0, b);
+        if (k > 0) M.res[k] = one_grid(l1, M.goff[k], M.goff[k - 1]);
+        if (k < M.m) M.pro[k] = one_grid(l1, M.goff[k], M.goff[k + 1]);
+        if (k == 0) M.top1d = one_grid(l1, M.goff[0], -1);
+    }
+    return M;
+}
+
+struct CycWs {
+    size_t chol, v0, v1, b, part, active, probs, sbase, tails, tpack, total;
+};
+
+CycWs cycles_ws(const BatchLayout& BL, int64_t stride, int64_t top_tiles, int64_t nstat)
+{
+    const int64_t S = BL.S, n0 = (int64_t)BL.c * BL.c;
+    CycWs w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
+    w.chol = take(sizeof(double) * S * n0 * n0);
+    w.v0 = take(sizeof(double) * S * stride);
+    w.v1 = take(sizeof(double) * S * stride);
+    w.b = take(sizeof(double) * S * stride);
+    w.part = take(sizeof(double) * 2 * S * top_tiles);
+    w.active = take(sizeof(int32_t) * S);
+    w.probs = take(sizeof(KProb) * S);
+    w.sbase = take(sizeof(SampleBase) * S);
+    w.tails = take(sizeof(KTail) * 2);
+    w.tpack = take(sizeof(double) * std::max<int64_t>(1, nstat * S));
+    w.total = off;
+    return w;
+}
+
+msg_status check_cycles(const msg_batch_desc* batch, const msg_solve_opts* opts, int kind)
+{
+    msg_status st = check_batch(batch);
+    if (st != MSG_OK) return st;
+    if ((st = check_opts(opts)) != MSG_OK) return st;
+    if (kind != MSG_CYCLES_MSG && kind != MSG_CYCLES_MG) return fail(MSG_ERR_ARG, "unknown cycle kind %d", kind);
+    if (opts->precision != MSG_FP64) return fail(MSG_ERR_UNSUPPORTED, "plain cycles run in FP64 only");
+    const int P = batch->P[0], Q = batch->Q[0];
+    for (int s = 1; s < batch->n_samples; ++s)
+        if (batch->P[s] != P || batch->Q[s] != Q)
+            return fail(MSG_ERR_UNSUPPORTED, "plain cycles need the same (P,Q) for every sample (sample %d)", s);
+    if (kind == MSG_CYCLES_MG && P != Q)
+        return fail(MSG_ERR_UNSUPPORTED, "standard multigrid needs P == Q (got %d, %d)", P, Q);
+    return MSG_OK;
+}
+
+// the MSG class (P,Q) cycled on the host down to its on-chip tail
+ClassPlan cycles_class(const BatchLayout& BL, const msg_solve_opts& o)
+{
+    std::vector<int> samples(BL.S);
+    for (int s = 0; s < BL.S; ++s) samples[s] = s;
+    ClassPlan C = plan_class(BL.c, BL.P[0], BL.Q[0], std::move(samples), o, tuning_of(o), true);
+    C.tpack = 0;
+    return C;
+}
+
+size_t cycles_ws_bytes(const BatchLayout& BL, const msg_solve_opts& o, int kind)
+{
+    if (kind == MSG_CYCLES_MG) {
+        const MgPlan M = plan_mg(BL.c, BL.P[0], BL.Q[0], tuning_of(o));
+        return cycles_ws(BL, M.stride, M.top1d.ntiles, 0).total;
+    }
+    const ClassPlan C = cycles_class(BL, o);
+    return cycles_ws(BL, C.stride, C.top1d.ntiles, C.tail.nstat).total;
+}
+
+// One standard-multigrid mu-cycle on grid k (the comparison method of
+// Section 2): pre-smoothing, 2D restriction of the residual, mu cycles on the
+// next coarser grid (the exact solve on grid m), bilinear correction,
+// post-smoothing.
+msg_status mg_cycle(const Ctx& X, const MgPlan& M, int k, Iter<double>& it, double* B, const double* KX,
+                    const double* KY)
+{
+    const int K = (int)X.kact;
+    msg_status st;
+    if (k == M.m) {
+        double* v = it.now(k);
+        return timed(X, MSG_KERNEL_TAIL, 0.0, [&]() -> msg_status {
+            hipError_t e = launch_dense_apply(K, X.probs, X.active, X.c * X.c, M.goff[k], X.chol, v, B, X.s);
+            if (e != hipSuccess) return fail(MSG_ERR_HIP, "coarsest solve: %s", hipGetErrorString(e));
+            return MSG_OK;
+        });
+    }
+    auto smooth = [&](int sweeps) -> msg_status {
+        const KLevel& L = M.rb[k];
+        while (sweeps > 0) {
+            const int ns = (sweeps >= 2 && g_fuse == 2) ? 2 : 1;
+            const double* vin = it.now(k);
+            double* vout = it.v[1 - it.cur[k]];
+            msg_status r = timed(X, MSG_KERNEL_SMOOTH, level_bytes<double>(L, 0, K), [&] {
+                return chunked(L, K, [&](int k0, int kn) {
+                    return launch_rbgs<double>(ns, L, kn, X.probs + k0, X.active + k0, X.c, vin, vout, B, KX, KY,
+                                               nullptr, X.o->omega, X.s);
+                });
+            });
+            if (r != MSG_OK) return r;
+            it.cur[k] ^= 1;
+            sweeps -= ns;
+        }
+        return MSG_OK;
+    };
+    if ((st = smooth(X.o->nu1)) != MSG_OK) return st;
+    {
+        const KLevel& L = M.res[k + 1];
+        const double* vf = it.now(k);
+        double* vc = it.v[0];
+        const KGrid& G = L.g[0];
+        // fine v, b and faces read; coarse b and v written
+        const double fine = 4.0 * G.nx * G.ny;
+        const double bytes = (2.0 * fine + (2.0 * G.nx + 1) * 2 * G.ny + 2.0 * G.nx * (2 * G.ny + 1) +
+                              2.0 * G.nx * G.ny) * sizeof(double) * K;
+        st = timed(X, MSG_KERNEL_RESTRICT, bytes, [&] {
+            return chunked(L, K, [&](int k0, int kn) {
+                return launch_restrict2d(L, kn, X.probs + k0, X.active + k0, X.c, vf, vc, B, KX, KY, X.s);
+            });
+        });
+        if (st != MSG_OK) return st;
+        it.cur[k + 1] = 0;
+    }
+    for (int t = 0; t < X.o->mu; ++t)
+        if ((st = mg_cycle(X, M, k + 1, it, B, KX, KY)) != MSG_OK) return st;
+    {
+        const KLevel& L = M.pro[k];
+        const double* vc = it.now(k + 1);
+        double* vf = it.now(k);
+        const KGrid& G = L.g[0];
+        const double bytes = (2.0 * G.nx * G.ny + G.nx * G.ny / 4.0) * sizeof(double) * K;
+        st = timed(X, MSG_KERNEL_PROLONG, bytes, [&] {
+            return chunked(L, K, [&](int k0, int kn) {
+                return launch_prolong2d(L, kn, X.probs + k0, X.active + k0, X.o->omega, vc, vf, X.s);
+            });
+        });
+        if (st != MSG_OK) return st;
+    }
+    return smooth(X.o->nu2);
+}
+
+}  // namespace
+
+extern "C" msg_status msg_cycles_workspace_size(msg_handle, const msg_batch_desc* batch, const msg_solve_opts* opts,
+                                                int kind, size_t* bytes)
+{
+    if (!bytes) return fail(MSG_ERR_ARG, "output is required");
+    msg_status st = check_cycles(batch, opts, kind);
+    if (st != MSG_OK) return st;
+    *bytes = cycles_ws_bytes(make_layout(batch), *opts, kind);
+    return MSG_OK;
+}
+
+extern "C" msg_status msg_cycles(msg_handle h, const msg_batch_desc* batch, const msg_solve_opts* opts, int kind,
+                                 int ncycles, const double* d_kx, const double* d_ky, const double* d_rhs,
+                                 double* d_u_top, double* d_ratios, void* d_ws, size_t ws_bytes, msg_stream stream)
+{
+    if (!h) return fail(MSG_ERR_ARG, "handle is NULL");
+    msg_status st = check_cycles(batch, opts, kind);
+    if (st != MSG_OK) return st;
+    if (ncycles < 0 || ncycles > 10000) return fail(MSG_ERR_ARG, "ncycles must be 0..10000 (got %d)", ncycles);
+    if (!d_kx || !d_ky || !d_u_top || !d_ratios || !d_ws)
+        return fail(MSG_ERR_ARG, "kx, ky, u_top, ratios and the workspace are required");
+    if ((uintptr_t)d_ws % kAlign) return fail(MSG_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+    const BatchLayout BL = make_layout(batch);
+    const int c = BL.c, S = BL.S, P = BL.P[0], Q = BL.Q[0];
+    const bool mg = kind == MSG_CYCLES_MG;
+    const Tuning tu = tuning_of(*opts);
+    MgPlan M;
+    ClassPlan C;
+    if (mg) {
+        M = plan_mg(c, P, Q, tu);
+    } else {
+        C = cycles_class(BL, *opts);
+        if (C.tail_lds == 0 || C.tail_lds > 160 * 1024)
+            return fail(MSG_ERR_UNSUPPORTED, "tail of class (%d,%d) does not fit LDS; lower tail_levels", P, Q);
+    }
+    const int64_t stride = mg ? M.stride : C.stride;
+    const KLevel top1d = mg ? M.top1d : C.top1d;
+    const int64_t top_off = mg ? M.goff[0] : C.goff[P * (Q + 1) + Q];
+    const CycWs W = cycles_ws(BL, stride, top1d.ntiles, mg ? 0 : C.tail.nstat);
+    if (ws_bytes < W.total) return fail(MSG_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, W.total);
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    Lane& ln = h->lane[0];
+
+    // host tables, alive until the final synchronisation
+    const std::vector<SampleBase> bases = sample_bases(BL);
+    std::vector<KProb> probs(S);
+    for (int k = 0; k < S; ++k) {
+        KProb& p = probs[k];
+        std::memset(&p, 0, sizeof p);
+        p.sample = k;
+        p.Qs = Q;
+        p.cell_base = BL.cell[k];
+        p.fx_base = BL.xf[k];
+        p.fy_base = BL.yf[k];
+        p.arena_base = (int64_t)k * stride;
+        p.part_base = (int64_t)k * top1d.ntiles;
+        p.grid_index = P * (Q + 1) + Q;
+    }
+    const std::vector<int32_t> ones(S, 1);
+    KTail tails[2] = {C.tail, C.tail64};
+    HIPCHK(hipMemcpyAsync(ws + W.sbase, bases.data(), sizeof(SampleBase) * S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws + W.probs, probs.data(), sizeof(KProb) * S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws + W.active, ones.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, s));
+    if (!mg) HIPCHK(hipMemcpyAsync(ws + W.tails, tails, sizeof tails, hipMemcpyHostToDevice, s));
+
+    Ctx X;
+    X.BL = &BL;
+    X.o = opts;
+    X.s = s;
+    X.c = c;
+    X.chol = (const double*)(ws + W.chol);
+    X.probs = (KProb*)(ws + W.probs);
+    X.active = (int32_t*)(ws + W.active);
+    X.prof = &ln.prof;
+    X.kact = S;
+    X.tails = (const KTail*)(ws + W.tails);
+    X.tpack = ws + W.tpack;
+    double* B = (double*)(ws + W.b);
+    double* part = (double*)(ws + W.part);
+    Iter<double> it;
+    it.v[0] = (double*)(ws + W.v0);
+    it.v[1] = (double*)(ws + W.v1);
+    std::fill(std::begin(it.cur), std::end(it.cur), 0);
+
+    {
+        hipError_t e = launch_chol(S, c, (const SampleBase*)(ws + W.sbase), d_kx, d_ky, (double*)(ws + W.chol), s);
+        if (e != hipSuccess) return fail(MSG_ERR_HIP, "cholesky launch: %s", hipGetErrorString(e));
+    }
+    if (!mg) {
+        hipError_t e = launch_tail_pack<double>(X.tails, S, X.probs, c, d_kx, d_ky, (double*)X.tpack, s);
+        if (e != hipSuccess) return fail(MSG_ERR_HIP, "tail image: %s", hipGetErrorString(e));
+    }
+    // the finest grid: v = 0, b = h
+    KLevel top = top1d;
+    top.g[0].aoff = top_off;
+    st = chunked(top, S, [&](int k0, int kn) { return launch_plain_init(top, kn, X.probs + k0, d_rhs, it.v[0], B, s); });
+    if (st != MSG_OK) return st;
+    const int lev_top = mg ? 0 : P + Q;
+    for (int k = 0; k <= ncycles; ++k) {
+        const double* v = it.now(lev_top);
+        st = chunked(top, S, [&](int k0, int kn) {
+            return launch_resnorm(top, kn, X.probs + k0, X.active + k0, c, v, B, d_kx, d_ky, part, nullptr, nullptr,
+                                  s);
+        });
+        if (st != MSG_OK) return st;
+        hipError_t e = launch_ratio(S, top.ntiles, X.probs, part, d_ratios, k, ncycles + 1, s);
+        if (e != hipSuccess) return fail(MSG_ERR_HIP, "ratio: %s", hipGetErrorString(e));
+        if (k == ncycles) break;
+        st = mg ? mg_cycle(X, M, 0, it, B, d_kx, d_ky) : mu_cycle<double>(X, C, Span{0, S}, P + Q, it, B, d_kx, d_ky);
+        if (st != MSG_OK) return st;
+    }
+    const int64_t ntop = grid_cells(c, P, Q);
+    HIPCHK(hipMemcpy2DAsync(d_u_top, sizeof(double) * ntop, it.now(lev_top) + top_off, sizeof(double) * stride,
+                            sizeof(double) * ntop, S, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (ln.prof.on) ln.prof.resolve();
     return MSG_OK;
 }
 

@@ -1103,6 +1103,117 @@ k_delta_q(int S, const int32_t* __restrict__ PQ, const int64_t* __restrict__ gba
 }
 
 // ------------------------------------------------------------------------
+// Plain cycles from zero (the convergence-factor comparison of Section 2):
+// the finest grid's iterate zero and right-hand side h = 1 or the caller's
+// values (sample-major, one finest grid after the other); standard
+// multigrid's transfers between grid (p,q) and (p-1,q-1), the products of the
+// one-directional cell-centred operators; the coarsest solve by the sample's
+// inverse; residual-norm ratios per problem.
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_plain_init(KLevel L, const KProb* __restrict__ probs, const double* __restrict__ rhs, double* __restrict__ V,
+             double* __restrict__ B)
+{
+    const Where w = locate(L);
+    if (w.k < 0) return;
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int64_t n = (int64_t)G.nx * G.ny;
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
+    if (cell >= n) return;
+    V[pr.arena_base + G.aoff + cell] = 0.0;
+    B[pr.arena_base + G.aoff + cell] = rhs ? rhs[(int64_t)pr.sample * n + cell] : 1.0;
+}
+
+// coarse grid (I,J) of G takes the average of the residuals of the four fine
+// cells of grid (p+1,q+1) at aoff_x; its iterate is zeroed
+__global__ void __launch_bounds__(kBlock)
+k_restrict2d(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c,
+             const double* __restrict__ Vf, double* __restrict__ Vc, double* __restrict__ B,
+             const double* __restrict__ KX, const double* __restrict__ KY)
+{
+    const Where w = locate(L);
+    if (w.k < 0 || !active[w.k]) return;
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
+    const int nx = G.nx, ny = G.ny;
+    if (cell >= (int64_t)nx * ny) return;
+    const int I = (int)(cell % nx), J = (int)(cell / nx);
+    const int fnx = 2 * nx, fny = 2 * ny;
+    const double* vf = Vf + pr.arena_base + G.aoff_x;
+    const double* bf = B + pr.arena_base + G.aoff_x;
+    const double* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p + 1, G.q + 1);
+    const double* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p + 1, G.q + 1);
+    const double ihx2 = (double)fnx * fnx, ihy2 = (double)fny * fny;
+    const double r00 = residual_at(vf, bf, kx, ky, fnx, fny, 2 * I, 2 * J, ihx2, ihy2);
+    const double r10 = residual_at(vf, bf, kx, ky, fnx, fny, 2 * I + 1, 2 * J, ihx2, ihy2);
+    const double r01 = residual_at(vf, bf, kx, ky, fnx, fny, 2 * I, 2 * J + 1, ihx2, ihy2);
+    const double r11 = residual_at(vf, bf, kx, ky, fnx, fny, 2 * I + 1, 2 * J + 1, ihx2, ihy2);
+    B[pr.arena_base + G.aoff + cell] = 0.5 * (0.5 * (r00 + r10) + 0.5 * (r01 + r11));
+    Vc[pr.arena_base + G.aoff + cell] = 0.0;
+}
+
+// fine grid G += omega * bilinear interpolation (odd reflection at the walls)
+// of the coarse iterate of grid (p-1,q-1) at aoff_x
+__global__ void __launch_bounds__(kBlock)
+k_prolong2d(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, double omega,
+            const double* __restrict__ Vc, double* __restrict__ Vf)
+{
+    const Where w = locate(L);
+    if (w.k < 0 || !active[w.k]) return;
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
+    const int nx = G.nx, ny = G.ny;
+    if (cell >= (int64_t)nx * ny) return;
+    const int i = (int)(cell % nx), j = (int)(cell / nx);
+    const int ncx = nx / 2, ncy = ny / 2;
+    const double* vc = Vc + pr.arena_base + G.aoff_x;
+    const int J = j >> 1, Jn = (j & 1) ? J + 1 : J - 1;
+    const double r0 = linear_at(vc + (int64_t)J * ncx, (int64_t)1, ncx, i);
+    const double r1 = (Jn >= 0 && Jn < ncy) ? linear_at(vc + (int64_t)Jn * ncx, (int64_t)1, ncx, i) : -r0;
+    Vf[pr.arena_base + G.aoff + cell] += omega * (0.75 * r0 + 0.25 * r1);
+}
+
+// v = A^-1 b on the coarsest (c x c) grid of each problem, lane k unknown k
+__global__ void __launch_bounds__(64)
+k_dense_apply(int K, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int n, int64_t aoff,
+              const double* __restrict__ inv, double* __restrict__ V, const double* __restrict__ B)
+{
+    const int k = blockIdx.x;
+    if (k >= K || !active[k]) return;
+    const KProb pr = probs[k];
+    const double* Ai = inv + (int64_t)pr.sample * n * n;
+    const double* b = B + pr.arena_base + aoff;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        double x = 0.0;
+        for (int j = 0; j < n; ++j) x += Ai[r * n + j] * b[j];
+        V[pr.arena_base + aoff + r] = x;
+    }
+}
+
+// ratio ||b - A v|| / ||b|| of each problem from the residual-norm partial sums
+__global__ void __launch_bounds__(64)
+k_ratio(int K, int ntiles, const KProb* __restrict__ probs, const double* __restrict__ part,
+        double* __restrict__ ratios, int col, int ncols)
+{
+    const int k = blockIdx.x;
+    if (k >= K) return;
+    const KProb pr = probs[k];
+    double rr = 0.0, bb = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += 64) {
+        rr += part[2 * (pr.part_base + t)];
+        bb += part[2 * (pr.part_base + t) + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        rr += __shfl_down(rr, off, 64);
+        bb += __shfl_down(bb, off, 64);
+    }
+    if (threadIdx.x == 0) ratios[(int64_t)pr.sample * ncols + col] = sqrt(rr) / sqrt(bb);
+}
+
+// ------------------------------------------------------------------------
 // Quantities of interest of Section 5 per grid, one workgroup per (grid,
 // sample): the mean of u; u at (1/2,1/2) by bilinear interpolation of the
 // cell centres; the average over [1/4,1/2]^2 of the cell-wise constant
@@ -1349,6 +1460,44 @@ hipError_t launch_delta_q(int S, int max_grids, const int32_t* PQ, const int64_t
                           hipStream_t st)
 {
     hipLaunchKernelGGL(k_delta_q, dim3((max_grids + kBlock - 1) / kBlock, S), dim3(kBlock), 0, st, S, PQ, gbase, q, dq);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_plain_init(const KLevel& L, int K, const KProb* probs, const double* rhs, double* V, double* B,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_plain_init, level_grid(L, K), dim3(threads_of(L)), 0, st, with_blocks(L, K), probs, rhs, V, B);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_restrict2d(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
+                             const double* Vf, double* Vc, double* B, const double* KX, const double* KY,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_restrict2d, level_grid(L, K), dim3(threads_of(L)), 0, st, with_blocks(L, K), probs, active, c,
+                       Vf, Vc, B, KX, KY);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_prolong2d(const KLevel& L, int K, const KProb* probs, const int32_t* active, double omega,
+                            const double* Vc, double* Vf, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_prolong2d, level_grid(L, K), dim3(threads_of(L)), 0, st, with_blocks(L, K), probs, active,
+                       omega, Vc, Vf);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_dense_apply(int K, const KProb* probs, const int32_t* active, int n, int64_t aoff,
+                              const double* inv, double* V, const double* B, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dense_apply, dim3(K), dim3(64), 0, st, K, probs, active, n, aoff, inv, V, B);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_ratio(int K, int ntiles, const KProb* probs, const double* part, double* ratios, int col, int ncols,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ratio, dim3(K), dim3(64), 0, st, K, ntiles, probs, part, ratios, col, ncols);
     return LAUNCH_CHECK();
 }
 

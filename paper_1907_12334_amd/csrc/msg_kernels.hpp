@@ -83,6 +83,18 @@ hipError_t launch_qreduce(int K, int ntiles, int64_t cells, const KProb* probs, 
                           hipStream_t st);
 hipError_t launch_rhs_top(const KLevel& L, int K, const KProb* probs, double* BP, const double* rhs,
                           const int64_t* rhs_base, hipStream_t st);
+// plain cycles from zero and standard multigrid (one grid per level, full coarsening)
+hipError_t launch_plain_init(const KLevel& L, int K, const KProb* probs, const double* rhs, double* V, double* B,
+                             hipStream_t st);
+hipError_t launch_restrict2d(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
+                             const double* Vf, double* Vc, double* B, const double* KX, const double* KY,
+                             hipStream_t st);
+hipError_t launch_prolong2d(const KLevel& L, int K, const KProb* probs, const int32_t* active, double omega,
+                            const double* Vc, double* Vf, hipStream_t st);
+hipError_t launch_dense_apply(int K, const KProb* probs, const int32_t* active, int n, int64_t aoff,
+                              const double* inv, double* V, const double* B, hipStream_t st);
+hipError_t launch_ratio(int K, int ntiles, const KProb* probs, const double* part, double* ratios, int col, int ncols,
+                        hipStream_t st);
 // quantities of interest (the same values as the C-ABI's MSG_QOI_*)
 enum QoiKind { QOI_MEAN = 0, QOI_POINT = 1, QOI_SUBDOMAIN = 2, QOI_FLUX = 3 };
 // quantity of interest `kind` of every grid of S samples

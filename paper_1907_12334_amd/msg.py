@@ -23,7 +23,8 @@ FP64, MIXED = 0, 1
 
 EXPORTS = ("msg_default_opts", "msg_create", "msg_destroy", "msg_last_error", "msg_layout",
            "msg_workspace_size", "msg_sample_field", "msg_solve_batch", "msg_quantity", "mimc_delta_q",
-           "msg_set_profiling", "msg_get_profile")
+           "msg_set_profiling", "msg_get_profile", "msg_cycles_workspace_size", "msg_cycles")
+CYCLES_MSG, CYCLES_MG = 0, 1
 QOI_MEAN, QOI_POINT, QOI_SUBDOMAIN, QOI_FLUX = range(4)
 (KERNEL_SMOOTH, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_TAIL, KERNEL_RESIDUAL_NORM, KERNEL_SMOOTH_STAGE,
  KERNEL_RESTRICT_STAGE) = range(7)
@@ -88,8 +89,13 @@ def lib():
         L.msg_quantity.argtypes = [ctypes.POINTER(BatchDescC), ctypes.c_int, vp, vp, vp, vp]
         L.msg_set_profiling.argtypes = [vp, ctypes.c_int]
         L.msg_get_profile.argtypes = [vp, ctypes.c_int, ctypes.POINTER(KernelStatsC)]
+        L.msg_cycles_workspace_size.argtypes = [vp, ctypes.POINTER(BatchDescC), ctypes.POINTER(SolveOptsC),
+                                                ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.msg_cycles.argtypes = [vp, ctypes.POINTER(BatchDescC), ctypes.POINTER(SolveOptsC), ctypes.c_int,
+                                 ctypes.c_int, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         for n in ("msg_create", "msg_layout", "msg_workspace_size", "msg_sample_field", "msg_solve_batch",
-                  "msg_quantity", "mimc_delta_q", "msg_set_profiling", "msg_get_profile"):
+                  "msg_quantity", "mimc_delta_q", "msg_set_profiling", "msg_get_profile",
+                  "msg_cycles_workspace_size", "msg_cycles"):
             getattr(L, n).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -227,6 +233,15 @@ class Handle:
             out[name] = (st.launches, st.milliseconds, st.bytes)
         return out
 
+    def cycles(self, batch: Batch, opts: SolveOpts, kind: int, ncycles: int, kx, ky, rhs, u_top, ratios, ws,
+               stream=None):
+        """Plain cycles from zero (CYCLES_MSG or CYCLES_MG) on every sample's finest grid."""
+        o = opts.c_struct()
+        _check(lib().msg_cycles(self.h, ctypes.byref(batch.c_struct), ctypes.byref(o), int(kind), int(ncycles),
+                                _ptr(kx), _ptr(ky), _ptr(rhs), _ptr(u_top), _ptr(ratios), _ptr(ws),
+                                ws.numel() * ws.element_size() if ws is not None else 0, _stream(stream)),
+               "msg_cycles")
+
     # ---- raw entry points (device tensors in, device tensors out)
     def sample_field(self, spec: FieldSpec, batch: Batch, xi, kx, ky, kx32=None, ky32=None, stream=None):
         _check(lib().msg_sample_field(self.h, ctypes.byref(spec.c_struct), ctypes.byref(batch.c_struct), _ptr(xi),
@@ -241,6 +256,14 @@ class Handle:
                                      _ptr(cycles), _ptr(ws), ws.numel() * ws.element_size() if ws is not None else 0,
                                      _stream(stream)),
                "msg_solve_batch")
+
+
+def cycles_workspace_size(batch: Batch, opts: SolveOpts, kind: int, handle=None) -> int:
+    n = ctypes.c_size_t(0)
+    o = opts.c_struct()
+    _check(lib().msg_cycles_workspace_size(handle, ctypes.byref(batch.c_struct), ctypes.byref(o), int(kind),
+                                           ctypes.byref(n)), "msg_cycles_workspace_size")
+    return n.value
 
 
 def quantity(batch: Batch, kind: int, kx, u, q, stream=None):

@@ -117,3 +117,27 @@ def test_create_reports_missing_device():
     code = msg.lib().msg_create(ctypes.byref(h), 0)
     assert code in (msg.MSG_ERR_HIP, msg.MSG_ERR_ARG)
     assert msg.last_error()
+
+
+def test_plain_cycles_workspace_and_validation():
+    o = msg.SolveOpts()
+    msg_ws = msg.cycles_workspace_size(msg.Batch(2, [4] * 8, [4] * 8), o, msg.CYCLES_MSG)
+    mg_ws = msg.cycles_workspace_size(msg.Batch(2, [4] * 8, [4] * 8), o, msg.CYCLES_MG)
+    # standard multigrid holds one grid per level, MSG all (P+1)(Q+1) grids
+    assert 0 < mg_ws < msg_ws
+    assert msg.cycles_workspace_size(msg.Batch(2, [4] * 16, [4] * 16), o, msg.CYCLES_MG) > mg_ws
+    assert msg.cycles_workspace_size(msg.Batch(2, [3] * 4, [5] * 4), o, msg.CYCLES_MSG) > 0
+    for batch, opts, kind, code in [
+        (msg.Batch(2, [3, 4], [4, 4]), o, msg.CYCLES_MSG, msg.MSG_ERR_UNSUPPORTED),     # ragged
+        (msg.Batch(2, [3] * 2, [5] * 2), o, msg.CYCLES_MG, msg.MSG_ERR_UNSUPPORTED),    # P != Q for MG
+        (msg.Batch(2, [3] * 2, [3] * 2), msg.SolveOpts(precision=msg.MIXED), msg.CYCLES_MG, msg.MSG_ERR_UNSUPPORTED),
+        (msg.Batch(2, [3] * 2, [3] * 2), o, 2, msg.MSG_ERR_ARG),
+        (msg.Batch(2, [3] * 2, [3] * 2), msg.SolveOpts(mu=4), msg.CYCLES_MSG, msg.MSG_ERR_ARG),
+    ]:
+        with pytest.raises(msg.MsgError) as e:
+            msg.cycles_workspace_size(batch, opts, kind)
+        assert e.value.code == code, (kind, msg.last_error())
+    b = msg.Batch(2, [3], [3])
+    code = msg.lib().msg_cycles(None, ctypes.byref(b.c_struct), ctypes.byref(o.c_struct()), 0, 2,
+                                *([None] * 6), 0, None)
+    assert code == msg.MSG_ERR_ARG
