@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--skip-ragged", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--skip-mimc", action="store_true")
+    ap.add_argument("--skip-factors", action="store_true", help="no MG-versus-MSG convergence-factor study")
     ap.add_argument("--skip-one-stream", action="store_true", help="no extra one-stream profiled step")
     ap.add_argument("--no-tune", action="store_true", help="library default plan instead of the autotuner's")
     ap.add_argument("--tune-cycles", type=int, default=1, help="cycles per stage in each autotuner trial")
@@ -222,6 +223,9 @@ def main():
     if not args.skip_mimc:
         extra["msg_mimc"] = mimc_leg(h, msg, I)
 
+    if not args.skip_factors:
+        extra["convergence_factors"] = factors_leg(h)
+
     cpu = None
     if not args.skip_cpu:
         cpu = cpu_baseline(w, args.cpu_samples)
@@ -369,6 +373,34 @@ def mimc_leg(h, msg, I):
                      "learned_rates": [round(x, 3) for x in r.rates],
                      "most_drawn_indices": [[list(k), v] for k, v in top]}
         log(f"MSG-MIMC {name}: E={r.E:.6f} rmse={r.rmse:.2e} N={r.N} in {r.seconds:.1f} s")
+    return out
+
+
+def factors_leg(h):
+    """Expected convergence factors of standard multigrid and MSG (plain
+    W(nu,nu) cycles from zero, h = 1, 100 samples, 50 cycles) on lognormal
+    fields with correlation lengths 1/4 and eta/4: eta and nu on 64 x 64
+    cells, then the grid size at eta = 1/16 with W(2,2).  Entries are
+    [MG, MSG]; null where some sample did not converge."""
+    from paper_1907_12334_amd.factors import Experiment
+    ex = Experiment(h, c=2, samples=100, cycles=50)
+    t0 = time.perf_counter()
+    by_eta = ex.table((1.0, 0.25, 1.0 / 16), [5], [1, 2, 3, 4, 5])
+    by_grid = ex.table((1.0 / 16,), [2, 3, 4, 6, 7], [2])
+    secs = time.perf_counter() - t0
+
+    def r(x):
+        return None if x is None else round(x, 4)
+
+    out = {"setup": "c=2, 100 samples, 50 cycles from zero, separable SE lognormal, sigma2=1, lx=1/4, ly=eta/4, "
+                    "factor = (r_k/r_0)^(1/k) at the last k with r_k >= 1e-10, [MG, MSG]",
+           "seconds": round(secs, 2), "64x64": {}, "eta=1/16,W(2,2)": {}}
+    for row in by_eta:
+        key = f"eta={row['eta']:.4g}"
+        out["64x64"].setdefault(key, {})[f"W({row['nu']},{row['nu']})"] = [r(row["MG"]), r(row["MSG"])]
+    for row in by_grid:
+        out["eta=1/16,W(2,2)"][row["cells"]] = [r(row["MG"]), r(row["MSG"])]
+    log(f"convergence factors ({secs:.1f} s): {out['64x64']} {out['eta=1/16,W(2,2)']}")
     return out
 
 

@@ -70,6 +70,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        # torch carries its own HIP runtime; loading it first lets the library
+        # bind to that same runtime, so the process holds one device context
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
         L.msg_default_opts.argtypes = [ctypes.POINTER(SolveOptsC)]
