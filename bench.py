@@ -377,30 +377,39 @@ def mimc_leg(h, msg, I):
 
 
 def factors_leg(h):
-    """Expected convergence factors of standard multigrid and MSG (plain
-    W(nu,nu) cycles from zero, h = 1, 100 samples, 50 cycles) on lognormal
-    fields with correlation lengths 1/4 and eta/4: eta and nu on 64 x 64
-    cells, then the grid size at eta = 1/16 with W(2,2).  Entries are
-    [MG, MSG]; null where some sample did not converge."""
+    """Standard multigrid against MSG on the paper's Matern fields (lambda =
+    1/4, nu = 1/2): plain cycles from zero, h = 1, 100 samples, 50 cycles,
+    c = 2.  (a) 64 x 64 cells, W(2,2), eta in {1/4, 1/8, 1/16}, theta in {0,
+    10, 20, 30} degrees: expected factor and median residual ratio after 10
+    cycles; (b) eta = 1/16: W(nu,nu), nu = 1..5, on 8^2 .. 128^2 cells.
+    Entries are [MG, MSG]; a factor is null where some sample did not
+    converge."""
     from paper_1907_12334_amd.factors import Experiment
     ex = Experiment(h, c=2, samples=100, cycles=50)
     t0 = time.perf_counter()
-    by_eta = ex.table((1.0, 0.25, 1.0 / 16), [5], [1, 2, 3, 4, 5])
-    by_grid = ex.table((1.0 / 16,), [2, 3, 4, 6, 7], [2])
+    thetas = (0, 10, 20, 30)
+    a = ex.table((0.25, 0.125, 0.0625), thetas, [5], [2])
+    b = ex.table((0.0625,), thetas, [2, 3, 4, 5, 6], [1, 2, 3, 4, 5])
     secs = time.perf_counter() - t0
 
-    def r(x):
-        return None if x is None else round(x, 4)
+    def r(x, d=4):
+        return None if x is None else float(f"{x:.{d}g}")
 
-    out = {"setup": "c=2, 100 samples, 50 cycles from zero, separable SE lognormal, sigma2=1, lx=1/4, ly=eta/4, "
-                    "factor = (r_k/r_0)^(1/k) at the last k with r_k >= 1e-10, [MG, MSG]",
-           "seconds": round(secs, 2), "64x64": {}, "eta=1/16,W(2,2)": {}}
-    for row in by_eta:
-        key = f"eta={row['eta']:.4g}"
-        out["64x64"].setdefault(key, {})[f"W({row['nu']},{row['nu']})"] = [r(row["MG"]), r(row["MSG"])]
-    for row in by_grid:
-        out["eta=1/16,W(2,2)"][row["cells"]] = [r(row["MG"]), r(row["MSG"])]
-    log(f"convergence factors ({secs:.1f} s): {out['64x64']} {out['eta=1/16,W(2,2)']}")
+    out = {"setup": "Matern lambda=1/4, nu=1/2 (circulant embedding), c=2, 100 samples, 50 cycles from zero, h=1; "
+                    "factor = (r_k/r_0)^(1/k) at the last k with r_k >= 1e-10; [MG, MSG]",
+           "seconds": round(secs, 2), "min_embedding_eig_ratio": ex.min_eig_ratio,
+           "fields_seconds": round(ex.field_seconds, 3), "field_samples": ex.field_samples,
+           "64x64_W(2,2)_factor": {}, "64x64_W(2,2)_median_r10": {}, "eta=1/16_factor_by_cells": {}}
+    for row in a:
+        k1, k2 = f"eta={row['eta']:g}", f"theta={row['theta']}"
+        out["64x64_W(2,2)_factor"].setdefault(k1, {})[k2] = [r(row["MG"]), r(row["MSG"])]
+        out["64x64_W(2,2)_median_r10"].setdefault(k1, {})[k2] = [r(row["MG_median_r10"], 2),
+                                                                  r(row["MSG_median_r10"], 2)]
+    for row in b:
+        d = out["eta=1/16_factor_by_cells"].setdefault(f"theta={row['theta']}", {}).setdefault(
+            f"W({row['nu']},{row['nu']})", {})
+        d[row["cells"]] = [r(row["MG"], 3), r(row["MSG"], 3)]
+    log(f"convergence factors ({secs:.1f} s): {out['64x64_W(2,2)_factor']}")
     return out
 
 

@@ -203,6 +203,46 @@ msg_status msg_quantity(const msg_batch_desc *batch, int kind, const double *d_k
 msg_status mimc_delta_q(const msg_batch_desc *batch, const double *d_q, double *d_dq,
                         msg_stream stream);
 
+/* Matern lognormal fields by circulant embedding (Section 1, eq. matern;
+ * Section 5): k = exp(Z) with Z Gaussian, zero mean, covariance
+ * C(r) = 2^(1-nu)/Gamma(nu) (2 sqrt(nu) r)^nu K_nu(2 sqrt(nu) r), r = |T (x1 - x2)|,
+ * T = S R, S = diag(1/sqrt(eta lambda), 1/sqrt(lambda)), R the rotation by theta.
+ * Each sample is drawn exactly on the lattice of half its finest mesh width
+ * (which holds every face midpoint of every grid (p,q) <= (P,Q), so all grids
+ * of a sample see one realisation) from a periodic embedding enlarged by
+ * m = 1 + 2 ceil(sqrt(nu) log2(max(c 2^P, c 2^Q))) per direction (or `pad`),
+ * rounded up to a power of two of at most 4096 points per direction.  The
+ * normals come from Philox4x64-10 with counter (frequency pair, sample id,
+ * 0, 0) and key (seed, 0x6D617465726E), through u = ((w >> 12) + 1/2) 2^-52
+ * and the Box-Muller transform.
+ *   eta, theta: host [n_samples] (theta in radians; eta > 0), the paper's
+ *               hyperparameters drawn per sample;
+ *   sample_id:  host [n_samples] or NULL (0..n_samples-1): the random stream;
+ * d_kx, d_ky (and optional FP32 copies): as msg_sample_field.  d_ratio: NULL
+ * or device FP64 [n_samples], min/max eigenvalue of each sample's embedding;
+ * a negative value means the embedding is indefinite (negative eigenvalues
+ * are clamped to zero and that sample is approximate; raise `pad`).
+ * Workspace: msg_matern_workspace_size bytes hold chunks of up to 8 samples;
+ * any size that holds one sample of the largest embedding works, in more
+ * chunks.  Errors: MSG_ERR_ARG, MSG_ERR_LAYOUT, MSG_ERR_UNSUPPORTED (an
+ * embedding above 4096 points per direction), MSG_ERR_WORKSPACE.  Enqueued
+ * on `stream`. */
+typedef struct {
+    double lambda;             /* length scale, > 0 */
+    double nu;                 /* smoothness, 0 < nu <= 8 */
+    const double *eta;         /* host [n_samples] */
+    const double *theta;       /* host [n_samples] */
+    const int64_t *sample_id;  /* host [n_samples] or NULL */
+    uint64_t seed;
+    int32_t pad;               /* 0: the paper's factor, else 1..64 */
+    int32_t reserved;
+} msg_matern_spec;
+msg_status msg_matern_workspace_size(const msg_batch_desc *batch, const msg_matern_spec *spec,
+                                     size_t *bytes);
+msg_status msg_sample_matern(msg_handle h, const msg_matern_spec *spec, const msg_batch_desc *batch,
+                             double *d_kx, double *d_ky, float *d_kx32, float *d_ky32,
+                             double *d_ratio, void *d_ws, size_t ws_bytes, msg_stream stream);
+
 /* Plain cycles from zero, the convergence-factor comparison of Section 2.
  * Every sample runs `ncycles` cycles on its finest grid (P,Q), started from
  * v = 0 with right-hand side h = 1 (d_rhs NULL) or d_rhs, and reports the

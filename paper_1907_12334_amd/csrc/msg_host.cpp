@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/msg.h"
+#include "matern_kernels.hpp"
 #include "msg_device.hpp"
 #include "msg_kernels.hpp"
 
@@ -1865,6 +1866,196 @@ extern "C" msg_status msg_cycles(msg_handle h, const msg_batch_desc* batch, cons
                             sizeof(double) * ntop, S, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     if (ln.prof.on) ln.prof.resolve();
+    return MSG_OK;
+}
+
+// ---------------------------------------------------------------- Matern fields
+namespace {
+
+constexpr uint64_t kMaternKey1 = 0x6D617465726Eull;
+constexpr int kMaternMaxLog = 12;        // rows of up to 4096 points: one row in 64 KB of LDS
+constexpr int kMaternChunk = 8;          // samples per chunk at the suggested workspace size
+constexpr int kMaternBlocks = 256;       // partial min/max blocks per sample
+
+int log2_ceil(int64_t x)
+{
+    int l = 0;
+    while (((int64_t)1 << l) < x) ++l;
+    return l;
+}
+
+// log2 of the embedding lattice per direction for a sample of rectangle (P,Q)
+void matern_shape(int c, int P, int Q, double nu, int pad, int& lx, int& ly)
+{
+    const int64_t Nx = (int64_t)c << P, Ny = (int64_t)c << Q;
+    int m = pad > 0 ? pad : 1 + 2 * (int)std::ceil(std::sqrt(nu) * std::log2((double)std::max(Nx, Ny)));
+    m = std::max(m, 2);                  // at least the minimal embedding
+    lx = log2_ceil(m * 2 * Nx);
+    ly = log2_ceil(m * 2 * Ny);
+}
+
+msg_status check_matern(const msg_batch_desc* batch, const msg_matern_spec* sp)
+{
+    msg_status st = check_batch(batch);
+    if (st != MSG_OK) return st;
+    if (!sp || !sp->eta || !sp->theta) return fail(MSG_ERR_ARG, "spec with eta and theta arrays is required");
+    if (!(sp->lambda > 0.0) || !std::isfinite(sp->lambda)) return fail(MSG_ERR_ARG, "lambda must be positive");
+    if (!(sp->nu > 0.0) || sp->nu > 8.0) return fail(MSG_ERR_ARG, "nu must be in (0, 8]");
+    if (sp->pad < 0 || sp->pad > 64) return fail(MSG_ERR_ARG, "pad must be 0..64");
+    for (int s = 0; s < batch->n_samples; ++s) {
+        if (!(sp->eta[s] > 0.0) || !std::isfinite(sp->eta[s]) || !std::isfinite(sp->theta[s]))
+            return fail(MSG_ERR_ARG, "sample %d: eta must be positive and theta finite", s);
+        int lx, ly;
+        matern_shape(batch->c, batch->P[s], batch->Q[s], sp->nu, sp->pad, lx, ly);
+        if (lx > kMaternMaxLog || ly > kMaternMaxLog)
+            return fail(MSG_ERR_UNSUPPORTED, "sample %d: embedding of 2^%d x 2^%d points exceeds 4096 per direction", s,
+                        lx, ly);
+    }
+    return MSG_OK;
+}
+
+struct MatWs {
+    size_t tw, smp, idx, part, a, b, total;
+    int chunk;
+};
+
+// workspace with room for `chunk` samples of the largest embedding
+MatWs matern_ws(const msg_batch_desc* batch, const msg_matern_spec* sp, int chunk)
+{
+    int64_t mmax = 1;
+    int lmax = 1;
+    for (int s = 0; s < batch->n_samples; ++s) {
+        int lx, ly;
+        matern_shape(batch->c, batch->P[s], batch->Q[s], sp->nu, sp->pad, lx, ly);
+        mmax = std::max<int64_t>(mmax, (int64_t)1 << (lx + ly));
+        lmax = std::max(lmax, std::max(lx, ly));
+    }
+    MatWs w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
+    w.tw = take(sizeof(double2) * ((size_t)1 << (lmax - 1)));
+    w.smp = take(sizeof(MaternSample) * batch->n_samples);
+    w.idx = take(sizeof(int32_t) * batch->n_samples);
+    w.part = take(sizeof(double2) * kMaternBlocks * chunk);
+    w.a = take(sizeof(double2) * mmax * chunk);
+    w.b = take(sizeof(double2) * mmax * chunk);
+    w.total = off;
+    w.chunk = chunk;
+    return w;
+}
+
+}  // namespace
+
+extern "C" msg_status msg_matern_workspace_size(const msg_batch_desc* batch, const msg_matern_spec* spec,
+                                                size_t* bytes)
+{
+    if (!bytes) return fail(MSG_ERR_ARG, "output is required");
+    msg_status st = check_matern(batch, spec);
+    if (st != MSG_OK) return st;
+    *bytes = matern_ws(batch, spec, std::min(batch->n_samples, kMaternChunk)).total;
+    return MSG_OK;
+}
+
+extern "C" msg_status msg_sample_matern(msg_handle h, const msg_matern_spec* sp, const msg_batch_desc* batch,
+                                        double* d_kx, double* d_ky, float* d_kx32, float* d_ky32, double* d_ratio,
+                                        void* d_ws, size_t ws_bytes, msg_stream stream)
+{
+    if (!h) return fail(MSG_ERR_ARG, "handle is NULL");
+    msg_status st = check_matern(batch, sp);
+    if (st != MSG_OK) return st;
+    if (!d_kx || !d_ky || !d_ws) return fail(MSG_ERR_ARG, "kx, ky and the workspace are required");
+    if ((d_kx32 == nullptr) != (d_ky32 == nullptr)) return fail(MSG_ERR_ARG, "give both FP32 copies or neither");
+    if ((uintptr_t)d_ws % kAlign) return fail(MSG_ERR_ARG, "workspace must be %zu-byte aligned", kAlign);
+    // as many samples per chunk as the workspace holds
+    int chunk = 0;
+    for (int k = std::min(batch->n_samples, 1 << 16); k >= 1; k = k > 64 ? k / 2 : k - 1)
+        if (matern_ws(batch, sp, k).total <= ws_bytes) {
+            chunk = k;
+            break;
+        }
+    if (chunk == 0)
+        return fail(MSG_ERR_WORKSPACE, "workspace of %zu bytes holds no sample; need %zu", ws_bytes,
+                    matern_ws(batch, sp, 1).total);
+    const MatWs W = matern_ws(batch, sp, chunk);
+    HIPCHK(hipSetDevice(h->device));
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    const int c = batch->c, S = batch->n_samples;
+    const BatchLayout BL = make_layout(batch);
+
+    // samples grouped by rectangle; per-sample table in group order
+    std::map<std::pair<int, int>, std::vector<int>> rects;
+    for (int k = 0; k < S; ++k) rects[{BL.P[k], BL.Q[k]}].push_back(k);
+    std::vector<MaternSample> tab;
+    std::vector<int32_t> idx;
+    tab.reserve(S);
+    idx.reserve(S);
+    for (auto& kv : rects)
+        for (int k : kv.second) {
+            MaternSample m;
+            const double a = 1.0 / std::sqrt(sp->eta[k] * sp->lambda), b = 1.0 / std::sqrt(sp->lambda);
+            const double cs = std::cos(sp->theta[k]), sn = std::sin(sp->theta[k]);
+            m.t00 = a * cs;
+            m.t01 = -a * sn;
+            m.t10 = b * sn;
+            m.t11 = b * cs;
+            m.id = sp->sample_id ? sp->sample_id[k] : k;
+            m.fx_base = BL.xf[k];
+            m.fy_base = BL.yf[k];
+            tab.push_back(m);
+            idx.push_back(k);
+        }
+    MaternSample* d_tab = (MaternSample*)(ws + W.smp);
+    int32_t* d_idx = (int32_t*)(ws + W.idx);
+    double2* tw = (double2*)(ws + W.tw);
+    double2* part = (double2*)(ws + W.part);
+    double2* A = (double2*)(ws + W.a);
+    double2* B = (double2*)(ws + W.b);
+    HIPCHK(hipMemcpyAsync(d_tab, tab.data(), sizeof(MaternSample) * S, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_idx, idx.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, s));
+    int lmax = 1;
+    for (auto& kv : rects) {
+        int lx, ly;
+        matern_shape(c, kv.first.first, kv.first.second, sp->nu, sp->pad, lx, ly);
+        lmax = std::max(lmax, std::max(lx, ly));
+    }
+    auto chk = [&](hipError_t e, const char* what) -> msg_status {
+        return e == hipSuccess ? MSG_OK : fail(MSG_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    };
+    if ((st = chk(launch_mat_twiddles(1 << lmax, tw, s), "twiddles")) != MSG_OK) return st;
+    const double coef = std::pow(2.0, 1.0 - sp->nu) / std::tgamma(sp->nu);
+    int first = 0;
+    for (auto& kv : rects) {
+        const int P = kv.first.first, Q = kv.first.second, n = (int)kv.second.size();
+        int lx, ly;
+        matern_shape(c, P, Q, sp->nu, sp->pad, lx, ly);
+        const int Mx = 1 << lx, My = 1 << ly;
+        const int64_t M = (int64_t)Mx * My;
+        const double hx = 1.0 / (2.0 * (double)((int64_t)c << P)), hy = 1.0 / (2.0 * (double)((int64_t)c << Q));
+        for (int k0 = 0; k0 < n; k0 += chunk) {
+            const int K = std::min(chunk, n - k0);
+            const MaternSample* t = d_tab + first + k0;
+            if ((st = chk(launch_mat_row(K, Mx, My, hx, hy, sp->nu, coef, t, A, s), "embedding row")) != MSG_OK ||
+                (st = chk(launch_fft_rows((int64_t)K * My, lx, (1 << lmax) >> lx, tw, A, s), "fft")) != MSG_OK ||
+                (st = chk(launch_transpose(K, My, Mx, A, B, s), "transpose")) != MSG_OK ||
+                (st = chk(launch_fft_rows((int64_t)K * Mx, ly, (1 << lmax) >> ly, tw, B, s), "fft")) != MSG_OK)
+                return st;
+            if (d_ratio &&
+                (st = chk(launch_eig_ratio(K, M, kMaternBlocks, B, part, d_idx + first + k0, d_ratio, s),
+                          "eigenvalue check")) != MSG_OK)
+                return st;
+            if ((st = chk(launch_mat_xi(K, Mx, My, sp->seed, kMaternKey1, t, B, s), "normals")) != MSG_OK ||
+                (st = chk(launch_fft_rows((int64_t)K * Mx, ly, (1 << lmax) >> ly, tw, B, s), "fft")) != MSG_OK ||
+                (st = chk(launch_transpose(K, Mx, My, B, A, s), "transpose")) != MSG_OK ||
+                (st = chk(launch_fft_rows((int64_t)K * My, lx, (1 << lmax) >> lx, tw, A, s), "fft")) != MSG_OK ||
+                (st = chk(launch_mat_faces(K, c, P, Q, Mx, My, t, A, d_kx, d_ky, d_kx32, d_ky32, s), "faces")) !=
+                    MSG_OK)
+                return st;
+        }
+        first += n;
+    }
+    // the host tables above are read by the copies on the stream
+    HIPCHK(hipStreamSynchronize(s));
     return MSG_OK;
 }
 

@@ -23,7 +23,8 @@ FP64, MIXED = 0, 1
 
 EXPORTS = ("msg_default_opts", "msg_create", "msg_destroy", "msg_last_error", "msg_layout",
            "msg_workspace_size", "msg_sample_field", "msg_solve_batch", "msg_quantity", "mimc_delta_q",
-           "msg_set_profiling", "msg_get_profile", "msg_cycles_workspace_size", "msg_cycles")
+           "msg_set_profiling", "msg_get_profile", "msg_cycles_workspace_size", "msg_cycles",
+           "msg_matern_workspace_size", "msg_sample_matern")
 CYCLES_MSG, CYCLES_MG = 0, 1
 QOI_MEAN, QOI_POINT, QOI_SUBDOMAIN, QOI_FLUX = range(4)
 (KERNEL_SMOOTH, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_TAIL, KERNEL_RESIDUAL_NORM, KERNEL_SMOOTH_STAGE,
@@ -48,6 +49,13 @@ class FieldSpecC(ctypes.Structure):
 class BatchDescC(ctypes.Structure):
     _fields_ = [("n_samples", ctypes.c_int32), ("c", ctypes.c_int32),
                 ("P", ctypes.POINTER(ctypes.c_int32)), ("Q", ctypes.POINTER(ctypes.c_int32))]
+
+
+class MaternSpecC(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("nu", ctypes.c_double),
+                ("eta", ctypes.POINTER(ctypes.c_double)), ("theta", ctypes.POINTER(ctypes.c_double)),
+                ("sample_id", ctypes.POINTER(ctypes.c_int64)), ("seed", ctypes.c_uint64),
+                ("pad", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class KernelStatsC(ctypes.Structure):
@@ -96,9 +104,13 @@ def lib():
                                                 ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
         L.msg_cycles.argtypes = [vp, ctypes.POINTER(BatchDescC), ctypes.POINTER(SolveOptsC), ctypes.c_int,
                                  ctypes.c_int, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.msg_matern_workspace_size.argtypes = [ctypes.POINTER(BatchDescC), ctypes.POINTER(MaternSpecC),
+                                                ctypes.POINTER(ctypes.c_size_t)]
+        L.msg_sample_matern.argtypes = [vp, ctypes.POINTER(MaternSpecC), ctypes.POINTER(BatchDescC),
+                                        vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         for n in ("msg_create", "msg_layout", "msg_workspace_size", "msg_sample_field", "msg_solve_batch",
                   "msg_quantity", "mimc_delta_q", "msg_set_profiling", "msg_get_profile",
-                  "msg_cycles_workspace_size", "msg_cycles"):
+                  "msg_cycles_workspace_size", "msg_cycles", "msg_matern_workspace_size", "msg_sample_matern"):
             getattr(L, n).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -236,6 +248,18 @@ class Handle:
             out[name] = (st.launches, st.milliseconds, st.bytes)
         return out
 
+    def sample_matern(self, spec: MaternSpec, batch: Batch, kx, ky, kx32=None, ky32=None, ratio=None, ws=None,
+                      stream=None):
+        """Matern fields of every sample (k at every face of every grid)."""
+        if ws is None:
+            import torch
+            n = matern_workspace_size(batch, spec)
+            ws = torch.empty((n + 7) // 8, dtype=torch.float64, device=kx.device)
+        _check(lib().msg_sample_matern(self.h, ctypes.byref(spec.c_struct), ctypes.byref(batch.c_struct), _ptr(kx),
+                                       _ptr(ky), _ptr(kx32), _ptr(ky32), _ptr(ratio), _ptr(ws),
+                                       ws.numel() * ws.element_size(), _stream(stream)),
+               "msg_sample_matern")
+
     def cycles(self, batch: Batch, opts: SolveOpts, kind: int, ncycles: int, kx, ky, rhs, u_top, ratios, ws,
                stream=None):
         """Plain cycles from zero (CYCLES_MSG or CYCLES_MG) on every sample's finest grid."""
@@ -259,6 +283,29 @@ class Handle:
                                      _ptr(cycles), _ptr(ws), ws.numel() * ws.element_size() if ws is not None else 0,
                                      _stream(stream)),
                "msg_solve_batch")
+
+
+class MaternSpec:
+    """Matern field parameters: length scale lam, smoothness nu, per-sample
+    anisotropic ratio eta and rotation theta (radians), random streams
+    (sample ids, seed) and the embedding factor pad (0: the paper's)."""
+
+    def __init__(self, lam: float, nu: float, eta, theta, sample_id=None, seed: int = 0, pad: int = 0):
+        self.eta = np.ascontiguousarray(eta, dtype=np.float64)
+        self.theta = np.ascontiguousarray(theta, dtype=np.float64)
+        self.ids = None if sample_id is None else np.ascontiguousarray(sample_id, dtype=np.int64)
+        self.c_struct = MaternSpecC(float(lam), float(nu),
+                                    self.eta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    self.theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    self.ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if self.ids is not None
+                                    else None, int(seed), int(pad), 0)
+
+
+def matern_workspace_size(batch: Batch, spec: MaternSpec) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().msg_matern_workspace_size(ctypes.byref(batch.c_struct), ctypes.byref(spec.c_struct),
+                                           ctypes.byref(n)), "msg_matern_workspace_size")
+    return n.value
 
 
 def cycles_workspace_size(batch: Batch, opts: SolveOpts, kind: int, handle=None) -> int:

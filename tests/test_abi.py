@@ -141,3 +141,29 @@ def test_plain_cycles_workspace_and_validation():
     code = msg.lib().msg_cycles(None, ctypes.byref(b.c_struct), ctypes.byref(o.c_struct()), 0, 2,
                                 *([None] * 6), 0, None)
     assert code == msg.MSG_ERR_ARG
+
+
+def test_matern_workspace_and_validation():
+    b = msg.Batch(2, [3, 1, 3], [3, 2, 3])
+    spec = msg.MaternSpec(0.25, 0.5, [1 / 16, 0.25, 0.1], [0.0, 0.3, -0.5])
+    n = msg.matern_workspace_size(b, spec)
+    # three samples (fewer than a chunk); largest embedding: 16 cells, m = 1 + 2 ceil(0.707 * 4) = 7,
+    # 7 * 2 * 16 = 224 -> 256 points per direction; two complex buffers
+    assert n >= 2 * 3 * 256 * 256 * 16
+    assert msg.matern_workspace_size(b, msg.MaternSpec(0.25, 0.5, [0.1] * 3, [0.0] * 3, pad=16)) > n
+    bad = [dict(lam=0.0), dict(nu=0.0), dict(nu=9.0), dict(eta=[0.1, -1.0, 0.1]), dict(theta=[0.0, float("nan"), 0.0]),
+           dict(pad=65)]
+    for kw in bad:
+        args = dict(lam=0.25, nu=0.5, eta=[0.1] * 3, theta=[0.0] * 3, pad=0)
+        args.update(kw)
+        with pytest.raises(msg.MsgError) as e:
+            msg.matern_workspace_size(b, msg.MaternSpec(**args))
+        assert e.value.code == msg.MSG_ERR_ARG, kw
+    # 256 x 256 cells: the paper's factor 13 needs 8192 points per direction
+    with pytest.raises(msg.MsgError) as e:
+        msg.matern_workspace_size(msg.Batch(2, [7], [7]), msg.MaternSpec(0.25, 0.5, [0.1], [0.0]))
+    assert e.value.code == msg.MSG_ERR_UNSUPPORTED
+    assert msg.matern_workspace_size(msg.Batch(2, [7], [7]), msg.MaternSpec(0.25, 0.5, [0.1], [0.0], pad=3)) > 0
+    code = msg.lib().msg_sample_matern(None, ctypes.byref(spec.c_struct), ctypes.byref(b.c_struct),
+                                       *([None] * 6), 0, None)
+    assert code == msg.MSG_ERR_ARG

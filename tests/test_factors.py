@@ -4,7 +4,7 @@ import math
 
 import numpy as np
 
-from paper_1907_12334_amd.factors import averaged_factors, expected_factor, field
+from paper_1907_12334_amd.factors import averaged_factors, expected_factor
 
 
 def test_geometric_history_gives_its_ratio():
@@ -32,8 +32,3 @@ def test_divergence_and_non_finite_are_not_converged():
 def test_exact_first_cycle():
     r = np.array([[1.0, 1e-16, 1e-17]])
     assert averaged_factors(r)[0] == 1e-16
-
-
-def test_field_anisotropy():
-    s = field(1 / 16)
-    assert s.kind == "separable" and s.lx == 0.25 and s.ly == 0.25 / 16 and s.n_terms == 16 * 64
