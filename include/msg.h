@@ -105,9 +105,10 @@ typedef struct {
     int32_t overlap;            /* -1 = automatic (2 for 1024 samples or more, else 0);
                                    0 = every launch on `stream`; 1 = the cycles of the classes
                                    of a level alternate over two streams forked from and
-                                   joined back to `stream`; 2 = the batch is split in two
-                                   halves solved concurrently by two host threads, each half
-                                   on one stream of its own.  Results do not depend on it; the
+                                   joined back to `stream`; 2 = the batch is split in parts
+                                   (three by default; environment MSG_PARTS = 2..4) solved
+                                   concurrently by one host thread each, each part on one
+                                   stream of its own.  Results do not depend on it; the
                                    workspace size does (msg_workspace_size). */
     /* Plan tuning (0 = the library's defaults; see paper_1907_12334_amd/autotune.py).
      * None changes results beyond rounding; all change the workspace size. */

@@ -610,12 +610,16 @@ struct Lane {
     }
 };
 
-constexpr int kParts = 2;          // a large batch is solved as this many concurrent parts
+constexpr int kMaxParts = 4;       // most concurrent parts a large batch is split into
+// parts used (2..kMaxParts); 256x256 x 4096 FP64: 233 samples/s with 2, 253
+// with 3, 210 with 4 (one stream per part plus the caller's: four parts
+// exceed the device's four hardware queues)
+int g_parts = 3;
 constexpr int kSplitMin = 1024;    // smallest batch split by the automatic overlap
 
 struct msg_handle_s {
     int device;
-    Lane lane[kParts];
+    Lane lane[kMaxParts];
 };
 
 // Bytes of workspace of a part, and the split of a batch into parts.
@@ -635,22 +639,24 @@ size_t part_ws_bytes(const msg_batch_desc* batch, const msg_solve_opts* opts)
 int overlap_mode(const msg_batch_desc* batch, const msg_solve_opts* opts)
 {
     const int m = opts->overlap < 0 ? (batch->n_samples >= kSplitMin ? 2 : 0) : opts->overlap;
-    return (m == 2 && batch->n_samples < kParts) ? 1 : m;
+    return (m == 2 && batch->n_samples < g_parts) ? 1 : m;
 }
 
 struct Split {
-    msg_batch_desc part[kParts];
-    int first[kParts];
-    size_t ws_off[kParts], ws_bytes[kParts], total;
+    int n;
+    msg_batch_desc part[kMaxParts];
+    int first[kMaxParts];
+    size_t ws_off[kMaxParts], ws_bytes[kMaxParts], total;
 };
 
 Split split_batch(const msg_batch_desc* batch, const msg_solve_opts* opts)
 {
     Split sp;
     size_t off = 0;
-    for (int k = 0; k < kParts; ++k) {
-        const int a = (int)((int64_t)batch->n_samples * k / kParts);
-        const int b = (int)((int64_t)batch->n_samples * (k + 1) / kParts);
+    sp.n = g_parts;
+    for (int k = 0; k < sp.n; ++k) {
+        const int a = (int)((int64_t)batch->n_samples * k / sp.n);
+        const int b = (int)((int64_t)batch->n_samples * (k + 1) / sp.n);
         sp.first[k] = a;
         sp.part[k] = msg_batch_desc{b - a, batch->c, batch->P + a, batch->Q + a};
         sp.ws_off[k] = off;
@@ -659,6 +665,29 @@ Split split_batch(const msg_batch_desc* batch, const msg_solve_opts* opts)
     }
     sp.total = off;
     return sp;
+}
+
+}  // namespace
+
+namespace {
+
+// tuning overrides from the environment, read once per process (handles may
+// be created from several threads; sizes may be asked for before any handle)
+void read_env()
+{
+    static std::once_flag env_once;
+    std::call_once(env_once, [] {
+        if (const char* f = std::getenv("MSG_RBGS_FUSE")) g_fuse = std::atoi(f) == 1 ? 1 : 2;
+        if (const char* t = std::getenv("MSG_TAIL_LDS")) g_tail_lds = std::max(1024, std::atoi(t));
+        if (const char* t = std::getenv("MSG_SPLIT_INNER")) g_split_inner = std::atoi(t) > 0 ? 1 : 0;
+        if (const char* t = std::getenv("MSG_SOLVE_LDS")) g_solve_lds = std::max(0, std::atoi(t));
+        if (const char* t = std::getenv("MSG_DEBUG_STAGES")) g_debug_stages = std::atoi(t) != 0;
+        if (const char* t = std::getenv("MSG_HANDOFF")) g_handoff = std::max(0, std::atoi(t));
+        if (const char* t = std::getenv("MSG_RBGS_TW")) g_rbgs_tw = std::max(4, std::min(256, std::atoi(t)));
+        if (const char* t = std::getenv("MSG_RBGS_CELLS")) g_rbgs_cells = std::max(64, std::min(4096, std::atoi(t)));
+        if (const char* t = std::getenv("MSG_RBGS_LDS")) g_rbgs_lds = std::max(1024, std::min(kRbgsLdsMax, std::atoi(t)));
+        if (const char* t = std::getenv("MSG_PARTS")) g_parts = std::max(2, std::min(kMaxParts, std::atoi(t)));
+    });
 }
 
 }  // namespace
@@ -697,20 +726,7 @@ msg_status msg_create(msg_handle* h, int device)
     HIPCHK(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(MSG_ERR_ARG, "device %d not present (%d devices)", device, n);
     HIPCHK(hipSetDevice(device));
-    // tuning overrides from the environment, read once per process (handles
-    // may be created from several threads)
-    static std::once_flag env_once;
-    std::call_once(env_once, [] {
-        if (const char* f = std::getenv("MSG_RBGS_FUSE")) g_fuse = std::atoi(f) == 1 ? 1 : 2;
-        if (const char* t = std::getenv("MSG_TAIL_LDS")) g_tail_lds = std::max(1024, std::atoi(t));
-        if (const char* t = std::getenv("MSG_SPLIT_INNER")) g_split_inner = std::atoi(t) > 0 ? 1 : 0;
-        if (const char* t = std::getenv("MSG_SOLVE_LDS")) g_solve_lds = std::max(0, std::atoi(t));
-        if (const char* t = std::getenv("MSG_DEBUG_STAGES")) g_debug_stages = std::atoi(t) != 0;
-        if (const char* t = std::getenv("MSG_HANDOFF")) g_handoff = std::max(0, std::atoi(t));
-        if (const char* t = std::getenv("MSG_RBGS_TW")) g_rbgs_tw = std::max(4, std::min(256, std::atoi(t)));
-        if (const char* t = std::getenv("MSG_RBGS_CELLS")) g_rbgs_cells = std::max(64, std::min(4096, std::atoi(t)));
-        if (const char* t = std::getenv("MSG_RBGS_LDS")) g_rbgs_lds = std::max(1024, std::min(kRbgsLdsMax, std::atoi(t)));
-    });
+    read_env();
     *h = new msg_handle_s{device};
     return MSG_OK;
 }
@@ -738,6 +754,7 @@ msg_status msg_workspace_size(msg_handle, const msg_batch_desc* batch, const msg
     if (st != MSG_OK) return st;
     if ((st = check_opts(opts)) != MSG_OK) return st;
     if (!bytes) return fail(MSG_ERR_ARG, "bytes is NULL");
+    read_env();
     *bytes = overlap_mode(batch, opts) == 2 ? split_batch(batch, opts).total : part_ws_bytes(batch, opts);
     return MSG_OK;
 }
@@ -1526,22 +1543,22 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
         return solve_part(h, h->lane[0], mode, batch, opts, d_kx, d_ky, d_kx32, d_ky32, d_rhs, d_u_out, d_q_out,
                           d_status, d_cycles, d_ws, ws_bytes, s);
 
-    // two halves of the batch, each a whole F-cycle of its own on one stream
-    // of its own (forked from and joined back to the caller's), driven by two
-    // host threads: one half's long-running problems, latency-bound tails and
-    // host round trips overlap the other's work.  Each half uses a single
+    // parts of the batch, each a whole F-cycle of its own on one stream of
+    // its own (forked from and joined back to the caller's), driven by one
+    // host thread each: one part's long-running problems, latency-bound tails
+    // and host round trips overlap the others' work.  Each part uses a single
     // stream: more streams than the device's hardware queues share queues and
     // serialise (measured: 244 samples/s against 210 with the classes of
-    // each half also on two streams, 256x256 x 4096)
+    // each of two halves also on two streams, 256x256 x 4096)
     const Split sp = split_batch(batch, opts);
     if (ws_bytes < sp.total) return fail(MSG_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, sp.total);
     const BatchLayout BL = make_layout(batch);
     HIPCHK(hipSetDevice(h->device));
-    for (int k = 0; k < kParts; ++k) HIPCHK(h->lane[k].streams());
+    for (int k = 0; k < sp.n; ++k) HIPCHK(h->lane[k].streams());
     HIPCHK(hipEventRecord(h->lane[0].done, s));
-    for (int k = 0; k < kParts; ++k) HIPCHK(hipStreamWaitEvent(h->lane[k].own, h->lane[0].done, 0));
-    msg_status res[kParts];
-    std::string err[kParts];
+    for (int k = 0; k < sp.n; ++k) HIPCHK(hipStreamWaitEvent(h->lane[k].own, h->lane[0].done, 0));
+    msg_status res[kMaxParts];
+    std::string err[kMaxParts];
     auto part = [&](int k) {
         const int a = sp.first[k];
         if (hipSetDevice(h->device) != hipSuccess) {
@@ -1556,14 +1573,15 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
                             sp.ws_bytes[k], h->lane[k].own);
         if (res[k] != MSG_OK) err[k] = msg_last_error();
     };
-    std::thread t1(part, 1);
+    std::vector<std::thread> threads;
+    for (int k = 1; k < sp.n; ++k) threads.emplace_back(part, k);
     part(0);
-    t1.join();
-    for (int k = 0; k < kParts; ++k) {
+    for (std::thread& t : threads) t.join();
+    for (int k = 0; k < sp.n; ++k) {
         HIPCHK(hipEventRecord(h->lane[k].done, h->lane[k].own));
         HIPCHK(hipStreamWaitEvent(s, h->lane[k].done, 0));
     }
-    for (int k = 0; k < kParts; ++k)
+    for (int k = 0; k < sp.n; ++k)
         if (res[k] != MSG_OK) return fail(res[k], "part %d: %s", k, err[k].c_str());
     return MSG_OK;
 }

@@ -118,10 +118,10 @@ def test_cycle_kinds_and_sweep_counts(handle, mu, nu1, nu2):
 
 
 def test_overlap_modes_give_identical_results(handle):
-    """Every launch on the caller's stream, classes over two streams, and two
-    concurrently solved halves of the batch: bitwise the same answers."""
+    """Every launch on the caller's stream, classes over two streams, and
+    concurrently solved parts of the batch: bitwise the same answers."""
     c, spec = 2, I.separable(0.3, 0.03, 1.0, m=20)
-    P, Q = [5] * 520 + [4] * 8, [4] * 520 + [5] * 8          # the halves get different rectangles
+    P, Q = [5] * 520 + [4] * 8, [4] * 520 + [5] * 8          # the parts get different rectangles
     xi = I.draw_xi(spec.n_terms, range(len(P)))
     outs = [PR.gpu_solve(c, P, Q, spec, xi, msg.SolveOpts(max_cycles=400, overlap=ov), handle=handle)
             for ov in (0, 1, 2)]
