@@ -457,8 +457,24 @@ def cpu_baseline(w, n=None):
     with ThreadPoolExecutor(cores) as ex:
         list(ex.map(one, range(n)))
     dt = time.perf_counter() - t0
+    # the same oracle on one core: its first sample alone
+    t1 = time.perf_counter()
+    one(0)
+    d1 = time.perf_counter() - t1
     return {"value": round(n / dt, 4), "unit": "samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} samples of {w.name}, one per thread", "seconds": round(dt, 2)}
+            "sample": f"first {n} samples of {w.name}, one per thread", "seconds": round(dt, 2),
+            "one_core": {"value": round(1.0 / d1, 4), "unit": "samples/s", "sample": "sample 0 alone"},
+            "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":
