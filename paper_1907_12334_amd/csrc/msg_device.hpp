@@ -104,6 +104,16 @@ struct KTail {
     int32_t nstat;             // elements [0, nstat): every face conductance run (a multiple of 4)
     KTailLevel lvl[kMaxTailLevels];
     int64_t top_aoff[kMaxLevelGrids];    // arena offsets of the top level's grids
+    // Red-black slot table (grids with an even number of columns): per level,
+    // one entry per pair of cells (2k, j), (2k+1, j) of every grid, holding the
+    // LDS offsets of cell (2k, j), of its west x-face and of its south y-face,
+    // and bits: nx (0-15), j odd (16), k first pair (17), k last pair (18),
+    // j first row (19), j last row (20).  Built once per stage on the device;
+    // null: the smoother decodes each slot itself.
+    const int4* slots;
+    int32_t slot_off[kMaxTailLevels];    // first entry of each level
+    int32_t nslots;                      // entries of all levels 0..top
+    int32_t pad2;
 };
 
 struct KCosTable {

@@ -139,6 +139,7 @@ int g_tail_lds = 20480;      // LDS budget of the W-cycle tail (sets its depth)
 int g_split_inner = 0;       // overlap mode inside each concurrently solved half (0 or 1)
 int g_handoff = 1024;        // hand a class's last cycling problems to one kernel at or below this count
 int g_solve_lds = 65536;     // LDS budget under which a class is solved entirely in one kernel
+bool g_tail_table = true;    // tails smooth from a red-black slot table (false: decode every slot)
 bool g_debug_stages = false; // per-level timing on stderr
 
 // LDS elements of a smoother tile tw x th with halo H: its iterate with H
@@ -214,6 +215,7 @@ struct StagePlan {
     int64_t arena_cells = 0;
     int64_t part_slots = 0;
     int64_t tpack_elems = 0;       // tail conductance images of the classes cycled on the host
+    int64_t slot_entries = 0;      // red-black slot tables of the classes' tails
 };
 
 int64_t grid_cells(int c, int a, int b) { return ((int64_t)c << a) * ((int64_t)c << b); }
@@ -321,6 +323,13 @@ size_t tail_layout(int c, int pc, int qc, int m, const std::vector<int64_t>& gof
         L.b0 = (int)off; off += (int64_t)L.cells * L.ng;
     }
     if (off > (int64_t)1 << 30) return 0;
+    // red-black slot table entries (pairs of cells: grids with an even width)
+    int32_t ns = 0;
+    for (int lev = 0; lev <= m; ++lev) {
+        TL.slot_off[lev] = ns;
+        ns += (TL.lvl[lev].cells / 2) * TL.lvl[lev].ng;
+    }
+    TL.nslots = (c & 1) ? 0 : ns;
     TL.lds_elems = (int)off;
     TL.chol_off = (int)(((size_t)off * sizeof(T) + 15) / 16 * 16);
     return (size_t)TL.chol_off + sizeof(double) * (size_t)c * c * c * c;
@@ -442,6 +451,7 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
                 C.tpack = SP.tpack_elems;
                 SP.tpack_elems += (int64_t)C.tail.nstat * C.K;
             }
+            SP.slot_entries += C.tail.nslots + C.tail64.nslots;
             C.ci = (int)SP.classes.size();
             SP.classes.push_back(std::move(C));
         }
@@ -452,14 +462,15 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
 // ---------------------------------------------------------------- workspace
 struct Ws {
     size_t bpyr, chol, a64v, a64v2, a64b, a32v, a32v2, a32b, part, active, pcycles, dead, nactive, sbase, gbase, rbase, probs,
-        pyrprobs, tails, cls, tpack, total;
+        pyrprobs, tails, cls, tpack, slots, total;
 };
 
 Ws ws_layout(const BatchLayout& BL, const std::vector<StagePlan>& plans, bool mixed)
 {
-    int64_t arena = 0, parts = 0, probs = 0, tpack = 0;
+    int64_t arena = 0, parts = 0, probs = 0, tpack = 0, slots = 0;
     for (const StagePlan& SP : plans) {
         tpack = std::max(tpack, SP.tpack_elems);
+        slots = std::max(slots, SP.slot_entries);
         arena = std::max(arena, SP.arena_cells);
         parts = std::max(parts, SP.part_slots);
         probs = std::max<int64_t>(probs, SP.K);
@@ -489,6 +500,7 @@ Ws ws_layout(const BatchLayout& BL, const std::vector<StagePlan>& plans, bool mi
     w.tails = take(sizeof(KTail) * 2 * (kMaxIndex + 1));
     w.cls = take(sizeof(int32_t) * std::max<int64_t>(probs, 1));
     w.tpack = take((mixed ? sizeof(float) : sizeof(double)) * std::max<int64_t>(tpack, 1));
+    w.slots = take(sizeof(int4) * std::max<int64_t>(slots, 1));
     w.total = off;
     return w;
 }
@@ -687,6 +699,7 @@ void read_env()
         if (const char* t = std::getenv("MSG_RBGS_CELLS")) g_rbgs_cells = std::max(64, std::min(4096, std::atoi(t)));
         if (const char* t = std::getenv("MSG_RBGS_LDS")) g_rbgs_lds = std::max(1024, std::min(kRbgsLdsMax, std::atoi(t)));
         if (const char* t = std::getenv("MSG_PARTS")) g_parts = std::max(2, std::min(kMaxParts, std::atoi(t)));
+        if (const char* t = std::getenv("MSG_TAIL_TABLE")) g_tail_table = std::atoi(t) != 0;
     });
 }
 
@@ -1284,11 +1297,28 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
             }
         HIPCHK(hipMemcpyAsync(X.probs, probs.data(), sizeof(KProb) * SP.K, hipMemcpyHostToDevice, s));
         tails.assign(2 * SP.classes.size(), KTail{});
-        for (const ClassPlan& C : SP.classes) {
-            tails[2 * C.ci] = C.tail;
-            tails[2 * C.ci + 1] = C.tail64;
+        {
+            int4* d_slots = (int4*)(ws + W.slots);
+            int64_t so = 0;
+            for (const ClassPlan& C : SP.classes) {
+                tails[2 * C.ci] = C.tail;
+                tails[2 * C.ci + 1] = C.tail64;
+                for (int t = 0; t < 2; ++t) {
+                    KTail& TL = tails[2 * C.ci + t];
+                    if (TL.nslots > 0 && g_tail_table) {
+                        TL.slots = d_slots + so;
+                        so += TL.nslots;
+                    }
+                }
+            }
         }
         HIPCHK(hipMemcpyAsync(ws + W.tails, tails.data(), sizeof(KTail) * tails.size(), hipMemcpyHostToDevice, s));
+        // the red-black slot table of every tail of the stage
+        for (size_t t = 0; t < tails.size(); ++t) {
+            if (!tails[t].slots) continue;
+            hipError_t e = launch_tail_slots(X.tails + t, const_cast<int4*>(tails[t].slots), s);
+            if (e != hipSuccess) return fail(MSG_ERR_HIP, "slot table: %s", hipGetErrorString(e));
+        }
         {
             hipError_t e = launch_activate(SP.K, X.probs, dead, SP.L, X.active, pcycles, s);
             if (e != hipSuccess) return fail(MSG_ERR_HIP, "activate: %s", hipGetErrorString(e));

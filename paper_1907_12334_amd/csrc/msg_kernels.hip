@@ -806,11 +806,68 @@ k_tail_pack(const KTail* __restrict__ table, const KProb* __restrict__ probs, in
 
 // every grid of level lev, `sweeps` red-then-black sweeps; one colour of all
 // the level's grids is spread over the lanes
+// The slot table of a tail (see KTail::slots), from the same decoding the
+// smoother uses without it.  One workgroup per tail.
+__global__ void __launch_bounds__(kBlock)
+k_tail_slots(const KTail* __restrict__ table, int4* __restrict__ out)
+{
+    const KTail& TL = *table;
+    for (int lev = 0; lev <= TL.top; ++lev) {
+        const KTailLevel L = TL.lvl[lev];
+        const int per = L.cells >> 1;
+        const int psh = L.csh >= 0 ? L.csh - 1 : -1;
+        for (int sl = threadIdx.x; sl < per * L.ng; sl += blockDim.x) {
+            int g, local, k, j;
+            split_slot(sl, per, psh, g, local);
+            const TGrid G = tgrid(TL, L, lev, g);
+            cell_ij(local, G.nx >> 1, G.sh >= 1 ? G.sh - 1 : -1, k, j);
+            const int bits = G.nx | ((j & 1) << 16) | ((k == 0) << 17) | ((2 * k + 2 == G.nx) << 18) | ((j == 0) << 19) |
+                             ((j == G.ny - 1) << 20);
+            out[TL.slot_off[lev] + sl] = make_int4(G.v + j * G.nx + 2 * k, G.x + j * (G.nx + 1) + 2 * k,
+                                                   G.y + j * G.nx + 2 * k, bits);
+        }
+    }
+}
+
+// every grid of level lev, `sweeps` red-then-black sweeps from the slot
+// table: the same updates, in the same arithmetic, as the decoding loop below
+template <typename T, int NT>
+__device__ __forceinline__ void tail_smooth_table(const KTail& TL, T* sm, int lev, int sweeps)
+{
+    const KTailLevel L = TL.lvl[lev];
+    const int total = (L.cells >> 1) * L.ng;
+    const int db = L.b0 - L.v0;                     // right-hand side of a cell, relative to its iterate
+    const int4* tab = TL.slots + TL.slot_off[lev];
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int sl = threadIdx.x; sl < total; sl += NT) {
+                const int4 e = tab[sl];
+                const int nx = e.w & 0xffff;
+                const int d = (colour + (e.w >> 16)) & 1;     // this colour's cell of the pair
+                const int off = e.x + d, fx = e.y + d, fy = e.z + d;
+                const T cW = sm[fx], cE = sm[fx + 1];
+                const T cS = sm[fy], cN = sm[fy + nx];
+                const T bb = sm[off + db];
+                const bool w = !((e.w >> 17) & 1) || d, ea = !((e.w >> 18) & 1) || !d;
+                const bool so = !((e.w >> 19) & 1), no = !((e.w >> 20) & 1);
+                const T xW = sm[w ? off - 1 : off], xE = sm[ea ? off + 1 : off];
+                const T xS = sm[so ? off - nx : off], xN = sm[no ? off + nx : off];
+                const Nbr<T> nb{w ? xW : T(0), ea ? xE : T(0), so ? xS : T(0), no ? xN : T(0)};
+                sm[off] = (bb + cW * nb.W + cE * nb.E + cS * nb.S + cN * nb.N) / (cW + cE + cS + cN);
+            }
+            __syncthreads();
+        }
+}
+
 template <typename T, int NT>
 __device__ __forceinline__ void tail_smooth(const KTail& TL, T* sm, int lev, int sweeps)
 {
     const KTailLevel L = TL.lvl[lev];
     const bool pairs = !(TL.c & 1);                 // nx even on every grid
+    if (pairs && TL.slots) {
+        tail_smooth_table<T, NT>(TL, sm, lev, sweeps);
+        return;
+    }
     const int per = pairs ? L.cells >> 1 : L.cells;
     const int psh = L.csh >= 0 ? (pairs ? L.csh - 1 : L.csh) : -1;
     const int total = per * L.ng;
@@ -1383,6 +1440,12 @@ hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int th
     else
         hipLaunchKernelGGL((k_tail<T, 64>), dim3(K), dim3(64), lds_bytes, st, tables, cls, tidx, probs, active, c,
                            mu, nu1, nu2, omega, count, V, B, KX, KY, pack, chol, ad);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_tail_slots(const KTail* table, int4* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tail_slots, dim3(1), dim3(kBlock), 0, st, table, out);
     return LAUNCH_CHECK();
 }
 

@@ -57,6 +57,7 @@ hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int3
                           const T* Vc, T* Vf, const T* KX, const T* KY, hipStream_t st);
 // block b uses class descriptor tables[cls[b]] (cls given, -1 skips the
 // block) or tables[tidx]; threads is 64 or 256
+hipError_t launch_tail_slots(const KTail* table, int4* out, hipStream_t st);
 template <typename T>
 hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int threads, size_t lds_bytes, int K,
                        const KProb* probs, const int32_t* active, int c, int mu, int nu1, int nu2, T omega,
