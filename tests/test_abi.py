@@ -167,3 +167,12 @@ def test_matern_workspace_and_validation():
     code = msg.lib().msg_sample_matern(None, ctypes.byref(spec.c_struct), ctypes.byref(b.c_struct),
                                        *([None] * 6), 0, None)
     assert code == msg.MSG_ERR_ARG
+
+
+def test_empty_batch_is_rejected():
+    with pytest.raises(msg.MsgError) as e:
+        msg.Batch(4, [], []).layout()
+    assert e.value.code == msg.MSG_ERR_ARG
+    with pytest.raises(msg.MsgError) as e:
+        msg.workspace_size(msg.Batch(4, [], []), msg.SolveOpts())
+    assert e.value.code == msg.MSG_ERR_ARG
