@@ -643,7 +643,7 @@ size_t part_ws_bytes(const msg_batch_desc* batch, const msg_solve_opts* opts)
     return ws_layout(BL, make_plans(BL, *opts), opts->precision == MSG_MIXED).total;
 }
 
-// overlap mode actually used: -1 picks 2 (two concurrent halves) for large
+// overlap mode actually used: -1 picks 2 (concurrent parts) for large
 // batches and 0 otherwise.  Extra streams pay only while the device has
 // hardware queues to spare: with several callers solving concurrently (the
 // request loop), class streams made every batch wait on the others (median
@@ -1155,7 +1155,7 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, I
 
 namespace {
 
-// One part of a batch (the whole batch, or one of the halves solved
+// One part of a batch (the whole batch, or one of the parts solved
 // concurrently) on stream s with lane ln; ov > 0 lets the classes of a level
 // alternate over the lane's two side streams.  Arguments are validated by
 // the caller; the part's arrays start at its first sample.
