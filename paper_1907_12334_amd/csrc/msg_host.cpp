@@ -1803,6 +1803,7 @@ extern "C" msg_status msg_cycles_workspace_size(msg_handle, const msg_batch_desc
     if (!bytes) return fail(MSG_ERR_ARG, "output is required");
     msg_status st = check_cycles(batch, opts, kind);
     if (st != MSG_OK) return st;
+    read_env();
     *bytes = cycles_ws_bytes(make_layout(batch), *opts, kind);
     return MSG_OK;
 }
