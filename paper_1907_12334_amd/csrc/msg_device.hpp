@@ -65,6 +65,9 @@ struct KGrid {
     int64_t aoff;          // arena offset of the grid inside a problem
     int64_t aoff_x;        // arena offset of the x-related grid ((p+1,q) or (p-1,q)), -1 if none
     int64_t aoff_y;        // arena offset of the y-related grid ((p,q+1) or (p,q-1)), -1 if none
+    int32_t rflags;        // restricting pass: bit 0, grid (p-1,q) has a second parent (p-1,q+1);
+                           // bit 1, grid (p,q-1) has a second parent (p+1,q-1)
+    int32_t pad;
 };
 
 struct KLevel {

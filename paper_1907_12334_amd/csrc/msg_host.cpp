@@ -140,6 +140,7 @@ int g_split_inner = 0;       // overlap mode inside each concurrently solved hal
 int g_handoff = 1024;        // hand a class's last cycling problems to one kernel at or below this count
 int g_solve_lds = 65536;     // LDS budget under which a class is solved entirely in one kernel
 bool g_tail_table = true;    // tails smooth from a red-black slot table (false: decode every slot)
+bool g_fuse_restrict = true; // pre-smoothing passes of nu1 = 2 also restrict their residual
 bool g_debug_stages = false; // per-level timing on stderr
 
 // LDS elements of a smoother tile tw x th with halo H: its iterate with H
@@ -203,6 +204,7 @@ struct ClassPlan {
     KLevel top1d;                  // the finest grid, 1-D tiles
     std::vector<KLevel> rb, rbc, pro, res;   // per level: smoother tiles (rbc: with the correction's
                                              // children), prolongation, restriction into level-1
+    std::vector<KLevel> rbr;                 // per level: the restricting pre-smoothing pass
     int64_t part0 = 0;             // first partial-sum slot
     int64_t tpack = -1;            // element offset of the class's tail conductance images, -1 if none
     std::vector<int> samples;
@@ -282,6 +284,31 @@ KLevel level_rbgs(int c, int pc, int qc, int lev, const std::vector<int64_t>& go
     }
     K.ntiles = tiles;
     K.bs = area <= 256 ? 64 : kBlock;     // small tiles: more, smaller workgroups per CU
+    return K;
+}
+
+// The restricting pre-smoothing pass of level lev (halo H + 1 = 5): tiles of
+// grids with q >= 1 get an even height so that row pairs stay in one tile;
+// aoff_x / aoff_y point at the children (p-1,q) and (p,q-1), and rflags says
+// which child has a second parent.
+KLevel level_rbgs_restrict(int c, int pc, int qc, int lev, const std::vector<int64_t>& goff, int H, const Tuning& tu)
+{
+    KLevel K = level_rbgs(c, pc, qc, lev, goff, H + 1, tu);
+    int tiles = 0, lds = 0, area = 0;
+    for (int g = 0; g < K.ngrids; ++g) {
+        KGrid& G = K.g[g];
+        if (G.q >= 1 && (G.th & 1)) G.th = std::max(2, G.th - 1);
+        G.tile0 = tiles;
+        tiles += G.tiles_x * (int)ceil_div(G.ny, G.th);
+        lds = std::max(lds, rbgs_lds(G.nx, G.ny, H + 1, G.tw, G.th));
+        area = std::max(area, G.tw * G.th);
+        G.aoff_x = G.p > 0 ? goff[(G.p - 1) * (qc + 1) + G.q] : -1;
+        G.aoff_y = G.q > 0 ? goff[G.p * (qc + 1) + G.q - 1] : -1;
+        G.rflags = (G.q + 1 <= qc ? 1 : 0) | (G.p + 1 <= pc ? 2 : 0);
+    }
+    K.ntiles = tiles;
+    K.lds = lds;
+    K.bs = area <= 256 ? 64 : kBlock;
     return K;
 }
 
@@ -411,8 +438,10 @@ ClassPlan plan_class(int c, int pc, int qc, std::vector<int> samples, const msg_
     C.rbc.resize(L + 1);
     C.pro.resize(L + 1);
     C.res.resize(L + 1);
+    C.rbr.resize(L + 1);
     for (int lev = 1; lev <= L; ++lev) {
         C.rb[lev] = level_rbgs(c, pc, qc, lev, C.goff, H, tu);
+        C.rbr[lev] = level_rbgs_restrict(c, pc, qc, lev, C.goff, H, tu);
         C.rbc[lev] = C.rb[lev];
         for (int g = 0; g < C.rbc[lev].ngrids; ++g) {
             KGrid& G = C.rbc[lev].g[g];
@@ -700,6 +729,7 @@ void read_env()
         if (const char* t = std::getenv("MSG_RBGS_LDS")) g_rbgs_lds = std::max(1024, std::min(kRbgsLdsMax, std::atoi(t)));
         if (const char* t = std::getenv("MSG_PARTS")) g_parts = std::max(2, std::min(kMaxParts, std::atoi(t)));
         if (const char* t = std::getenv("MSG_TAIL_TABLE")) g_tail_table = std::atoi(t) != 0;
+        if (const char* t = std::getenv("MSG_FUSE_RESTRICT")) g_fuse_restrict = std::atoi(t) != 0;
     });
 }
 
@@ -958,7 +988,8 @@ struct Ctx {
 
 // algorithmic bytes: data a kernel must touch at least once per active problem
 template <typename T>
-double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolong, 3 correction children, 4 copy*/,
+double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolong, 3 correction children, 4 copy,
+                                                   5 restricted outputs of a pass, 6 combination*/,
                    int64_t K)
 {
     double per = 0.0;
@@ -979,6 +1010,11 @@ double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolo
         } else if (kind_rel == 3) {
             if (G.aoff_x >= 0) per += cells / 2;              // coarse iterates of the children
             if (G.aoff_y >= 0) per += cells / 2;
+        } else if (kind_rel == 5) {
+            if (G.aoff_x >= 0) per += cells / 2;              // restricted residual into each child
+            if (G.aoff_y >= 0) per += cells / 2;
+        } else if (kind_rel == 6) {
+            if (G.aoff_x >= 0 && G.aoff_y >= 0) per += 4 * cells;   // two halves combined, iterate zeroed
         } else {
             per += 2 * cells;                                 // iterate read and written
         }
@@ -1109,6 +1145,41 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, I
         }
         return MSG_OK;
     };
+    if (g_fuse_restrict && g_fuse == 2 && X.o->nu1 == 2) {
+        // pre-smoothing and the restriction of its residual in one pass, then
+        // the coarse grids with two parents combine their halves
+        {
+            const KLevel& L = C.rbr[lev];
+            const T* vin = it.now(lev);
+            T* vout = it.v[1 - it.cur[lev]];
+            T* vc = it.v[0];
+            st = timed(
+                X, MSG_KERNEL_SMOOTH, level_bytes<T>(L, 0, X.kact) + level_bytes<T>(L, 5, X.kact),
+                [&] {
+                    return chunked(L, sp.kn, [&](int k0, int kn) {
+                        return launch_rbgs_restrict<T>(L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, vc, X.s);
+                    });
+                },
+                lev == C.L ? MSG_KERNEL_SMOOTH_STAGE : -1);
+            if (st != MSG_OK) return st;
+            it.cur[lev] ^= 1;
+            ++flips;
+        }
+        {
+            const KLevel& R = C.res[lev];
+            T* vc = it.v[0];
+            st = timed(
+                X, MSG_KERNEL_RESTRICT, level_bytes<T>(R, 6, X.kact),
+                [&] {
+                    return chunked(R, sp.kn, [&](int k0, int kn) {
+                        return launch_restrict_combine<T>(R, kn, pr + k0, act + k0, vc, B, X.s);
+                    });
+                },
+                lev == C.L ? MSG_KERNEL_RESTRICT_STAGE : -1);
+            if (st != MSG_OK) return st;
+            it.cur[lev - 1] = 0;
+        }
+    } else {
     if ((st = smooth(X.o->nu1, false)) != MSG_OK) return st;
     {
         const KLevel& L = C.res[lev];
@@ -1124,6 +1195,7 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, I
             lev == C.L ? MSG_KERNEL_RESTRICT_STAGE : -1);
         if (st != MSG_OK) return st;
         it.cur[lev - 1] = 0;
+    }
     }
     if (lev - 1 <= C.tail_top) {
         if ((st = tail(X.o->mu)) != MSG_OK) return st;

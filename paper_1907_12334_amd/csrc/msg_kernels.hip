@@ -340,13 +340,22 @@ __device__ __forceinline__ T correction_at(const KGrid& G, const KProb& pr, int 
     return hx ? ex : ey;
 }
 
-template <typename T, int NS, bool CORR, int NT>
+//
+// RS (with NS = 2, no correction): the pre-smoothing pass also forms the
+// residual of its tile's cells and restricts it into level l-1 (eq.
+// restriction), so the iterate, right-hand side and conductances are not read
+// again.  The halo is one cell wider, so that the cells just outside the tile
+// hold their final values too.  A coarse grid with one parent gets its
+// right-hand side and a zero iterate here; one with two parents gets the
+// x-parent's half in its right-hand side and the y-parent's in its iterate,
+// and k_restrict_combine adds them.
+template <typename T, int NS, bool CORR, int NT, bool RS = false>
 __global__ void __launch_bounds__(NT)
 k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c,
        const T* __restrict__ Vin, T* __restrict__ Vout, const T* __restrict__ B, const T* __restrict__ KX,
-       const T* __restrict__ KY, const T* __restrict__ Vc, T omega)
+       const T* __restrict__ KY, const T* __restrict__ Vc, T omega, T* __restrict__ Bco, T* __restrict__ Vco)
 {
-    constexpr int H = 2 * NS;
+    constexpr int H = 2 * NS + (RS ? 1 : 0);
     extern __shared__ __align__(16) unsigned char smem_rb[];
     T* sv = reinterpret_cast<T*>(smem_rb);
     const Where w = locate(L);
@@ -400,6 +409,82 @@ k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ ac
         const int li = idx % tw, lj = idx / tw, i = i0 + li, j = j0 + lj;
         if (i < nx && j < ny) vout[(int64_t)j * nx + i] = sv[(lj + Hy) * RW + li + Hx];
     }
+    if constexpr (RS) {
+        // b - A v at a cell of the tile, from the swept tile in LDS (the
+        // arithmetic of residual_at)
+        auto tres = [&](int i, int j) -> T {
+            const Stencil<T> st = stencil_at(kx, ky, nx, ny, i, j, ihx2, ihy2);
+            const int r = (j - j0 + Hy) * RW + (i - i0 + Hx);
+            const T u = sv[r];
+            const T uW = i > 0 ? sv[r - 1] : T(0);
+            const T uE = i < nx - 1 ? sv[r + 1] : T(0);
+            const T uS = j > 0 ? sv[r - RW] : T(0);
+            const T uN = j < ny - 1 ? sv[r + RW] : T(0);
+            return b[(int64_t)j * nx + i] - (st.wW * (u - uW) + st.wE * (u - uE) + st.wS * (u - uS) + st.wN * (u - uN));
+        };
+        // each iteration takes a block of 2 x 2 fine cells (2 x 1 or 1 x 2 when
+        // the grid restricts in one direction only) and computes each
+        // residual once for both children
+        const int iw = min(tw, nx - i0), jh = min(th, ny - j0);
+        const bool hx = G.aoff_x >= 0, hy = G.aoff_y >= 0;
+        const int bw = hx ? 2 : 1, bh = hy ? 2 : 1, nbx = iw / bw, nby = jh / bh;
+        const int nxc = nx >> 1;
+        for (int idx = threadIdx.x; idx < nbx * nby; idx += NT) {
+            const int by = idx / nbx, i = i0 + (idx - by * nbx) * bw, j = j0 + by * bh;
+            const T r00 = tres(i, j);
+            const T r10 = hx ? tres(i + 1, j) : T(0);
+            const T r01 = hy ? tres(i, j + 1) : T(0);
+            const T r11 = (hx && hy) ? tres(i + 1, j + 1) : T(0);
+            if (hx) {                               // into (p-1,q): pairs of columns
+                const int64_t cx = pr.arena_base + G.aoff_x + (int64_t)j * nxc + (i >> 1);
+                Bco[cx] = T(0.5) * (r00 + r10);
+                if (!(G.rflags & 1)) Vco[cx] = T(0);
+                if (hy) {
+                    Bco[cx + nxc] = T(0.5) * (r01 + r11);
+                    if (!(G.rflags & 1)) Vco[cx + nxc] = T(0);
+                }
+            }
+            if (hy) {                               // into (p,q-1): pairs of rows
+                const int64_t cy = pr.arena_base + G.aoff_y + (int64_t)(j >> 1) * nx + i;
+                const T ry0 = T(0.5) * (r00 + r01);
+                if (G.rflags & 2) {
+                    Vco[cy] = ry0;
+                } else {
+                    Bco[cy] = ry0;
+                    Vco[cy] = T(0);
+                }
+                if (hx) {
+                    const T ry1 = T(0.5) * (r10 + r11);
+                    if (G.rflags & 2) {
+                        Vco[cy + 1] = ry1;
+                    } else {
+                        Bco[cy + 1] = ry1;
+                        Vco[cy + 1] = T(0);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The coarse grids with two parents after a restricting pass: b = average
+// of the two halves (eq. restriction), iterate zeroed.  L is the coarse level
+// with its parents' offsets.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_restrict_combine(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, T* __restrict__ Vc,
+                   T* __restrict__ B)
+{
+    const Where w = locate(L);
+    if (w.k < 0 || !active[w.k]) return;
+    const KGrid& G = L.g[w.gi];
+    if (G.aoff_x < 0 || G.aoff_y < 0) return;
+    const KProb pr = probs[w.k];
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
+    if (cell >= (int64_t)G.nx * G.ny) return;
+    const int64_t a = pr.arena_base + G.aoff + cell;
+    B[a] = T(0.5) * B[a] + T(0.5) * Vc[a];
+    Vc[a] = T(0);
 }
 
 // ------------------------------------------------------------------------
@@ -1374,17 +1459,17 @@ static void rbgs_dispatch(int ns, bool corr, dim3 grid, size_t lds, hipStream_t 
                           const T* Vc, T omega)
 {
     if (ns == 0) {
-        hipLaunchKernelGGL((k_rbgs<T, 0, false, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+        hipLaunchKernelGGL((k_rbgs<T, 0, false, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega, nullptr, nullptr);
     } else if (corr) {
         if (ns == 1)
-            hipLaunchKernelGGL((k_rbgs<T, 1, true, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+            hipLaunchKernelGGL((k_rbgs<T, 1, true, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega, nullptr, nullptr);
         else
-            hipLaunchKernelGGL((k_rbgs<T, 2, true, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+            hipLaunchKernelGGL((k_rbgs<T, 2, true, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega, nullptr, nullptr);
     } else {
         if (ns == 1)
-            hipLaunchKernelGGL((k_rbgs<T, 1, false, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+            hipLaunchKernelGGL((k_rbgs<T, 1, false, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega, nullptr, nullptr);
         else
-            hipLaunchKernelGGL((k_rbgs<T, 2, false, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega);
+            hipLaunchKernelGGL((k_rbgs<T, 2, false, NT>), grid, dim3(NT), lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc, omega, nullptr, nullptr);
     }
 }
 
@@ -1401,6 +1486,31 @@ hipError_t launch_rbgs(int ns, const KLevel& L, int K, const KProb* probs, const
     else
         rbgs_dispatch<T, kBlock>(ns, Vc != nullptr, grid, lds, st, Lb, probs, active, c, Vin, Vout, B, KX, KY, Vc,
                                  omega);
+    return LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t launch_rbgs_restrict(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
+                                const T* Vin, T* Vout, T* B, const T* KX, const T* KY, T* Vco, hipStream_t st)
+{
+    const dim3 grid = level_grid(L, K);
+    const KLevel Lb = with_blocks(L, K);
+    const size_t lds = sizeof(T) * (size_t)L.lds;
+    if (L.bs == 64)
+        hipLaunchKernelGGL((k_rbgs<T, 2, false, 64, true>), grid, dim3(64), lds, st, Lb, probs, active, c, Vin, Vout, B,
+                           KX, KY, nullptr, T(0), B, Vco);
+    else
+        hipLaunchKernelGGL((k_rbgs<T, 2, false, kBlock, true>), grid, dim3(kBlock), lds, st, Lb, probs, active, c, Vin,
+                           Vout, B, KX, KY, nullptr, T(0), B, Vco);
+    return LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t launch_restrict_combine(const KLevel& L, int K, const KProb* probs, const int32_t* active, T* Vc, T* B,
+                                   hipStream_t st)
+{
+    hipLaunchKernelGGL((k_restrict_combine<T>), level_grid(L, K), dim3(threads_of(L)), 0, st, with_blocks(L, K), probs,
+                       active, Vc, B);
     return LAUNCH_CHECK();
 }
 
@@ -1579,6 +1689,14 @@ template hipError_t launch_rbgs<double>(int, const KLevel&, int, const KProb*, c
 template hipError_t launch_rbgs<float>(int, const KLevel&, int, const KProb*, const int32_t*, int, const float*,
                                        float*, const float*, const float*, const float*, const float*, float,
                                        hipStream_t);
+template hipError_t launch_rbgs_restrict<double>(const KLevel&, int, const KProb*, const int32_t*, int, const double*,
+                                                double*, double*, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_rbgs_restrict<float>(const KLevel&, int, const KProb*, const int32_t*, int, const float*,
+                                               float*, float*, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_restrict_combine<double>(const KLevel&, int, const KProb*, const int32_t*, double*, double*,
+                                                    hipStream_t);
+template hipError_t launch_restrict_combine<float>(const KLevel&, int, const KProb*, const int32_t*, float*, float*,
+                                                   hipStream_t);
 template hipError_t launch_restrict<double>(bool, const KLevel&, int, const KProb*, const int32_t*, int,
                                             const double*, double*, double*, const double*, const double*,
                                             hipStream_t);

@@ -49,6 +49,14 @@ template <typename T>
 hipError_t launch_rbgs(int ns, const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
                        const T* Vin, T* Vout, const T* B, const T* KX, const T* KY, const T* Vc, T omega,
                        hipStream_t st);
+// a two-sweep pass that also restricts its residual into level l-1, and the
+// combination of the two halves on coarse grids with two parents
+template <typename T>
+hipError_t launch_rbgs_restrict(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
+                                const T* Vin, T* Vout, T* B, const T* KX, const T* KY, T* Vco, hipStream_t st);
+template <typename T>
+hipError_t launch_restrict_combine(const KLevel& L, int K, const KProb* probs, const int32_t* active, T* Vc, T* B,
+                                   hipStream_t st);
 template <typename T>
 hipError_t launch_restrict(bool rhs, const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
                            const T* Vf, T* Vc, T* B, const T* KX, const T* KY, hipStream_t st);
