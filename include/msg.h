@@ -288,8 +288,11 @@ msg_status msg_cycles(msg_handle h, const msg_batch_desc *batch, const msg_solve
  * grids are the largest of the stage and stream from HBM.  Enabling or
  * disabling clears the totals. */
 enum {
-    MSG_KERNEL_SMOOTH = 0,        /* red-black Gauss-Seidel passes */
-    MSG_KERNEL_RESTRICT = 1,      /* residual + restriction (eq. restriction) */
+    MSG_KERNEL_SMOOTH = 0,        /* red-black Gauss-Seidel passes (with nu1 = 2 the
+                                     pre-smoothing pass also restricts its residual) */
+    MSG_KERNEL_RESTRICT = 1,      /* residual + restriction (eq. restriction); where the
+                                     pre-smoothing pass restricts its own residual (nu1 = 2),
+                                     only the combination on coarse grids with two parents */
     MSG_KERNEL_PROLONG = 2,       /* weighted correction (eq. interpolation) */
     MSG_KERNEL_TAIL = 3,          /* on-chip cycles of the lowest levels */
     MSG_KERNEL_RESIDUAL_NORM = 4, /* finest-grid residual norms */
