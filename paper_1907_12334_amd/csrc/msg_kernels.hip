@@ -90,13 +90,15 @@ __device__ __forceinline__ T odd_at(const T* __restrict__ line, int64_t stride, 
     return sign * line[(int64_t)I * stride];
 }
 
-// cell-centred linear interpolation (3/4, 1/4) of fine index i from a coarse line
+// cell-centred linear interpolation (3/4, 1/4) of fine index i (0 <= i < 2n)
+// from a coarse line of n values; the neighbour is at most one cell outside
+// the line, where the odd reflection is minus the edge value itself
 template <typename T>
 __device__ __forceinline__ T linear_at(const T* __restrict__ line, int64_t stride, int n, int i)
 {
-    const int I = i >> 1;
-    const T e0 = odd_at(line, stride, n, I);
-    const T e1 = odd_at(line, stride, n, (i & 1) ? I + 1 : I - 1);
+    const int I = i >> 1, In = (i & 1) ? I + 1 : I - 1;
+    const T e0 = line[(int64_t)I * stride];
+    const T e1 = (In >= 0 && In < n) ? line[(int64_t)In * stride] : -e0;
     return T(0.75) * e0 + T(0.25) * e1;
 }
 
