@@ -171,8 +171,7 @@ def main():
              "max_cycles_per_grid": int(cycles.max()),
              "roofline_stage_level": {
                  "note": "launches on each F-cycle stage's own level (its largest, HBM-resident grids)",
-                 "smooth": roofline_of(prof["smooth_stage"], SMOOTH_KERNEL),
-                 "restrict": roofline_of(prof["restrict_stage"], "restriction after the restricting pre-smoothing pass (combination of two parents)")}}
+                 "smooth": roofline_of(prof["smooth_stage"], SMOOTH_KERNEL)}}
     if not args.no_profile and not args.skip_one_stream:
         # the same step with every launch on one stream: kernel times without
         # another class's kernels sharing the device
@@ -189,8 +188,7 @@ def main():
             "note": "one extra step with overlap = 0 (no concurrent classes), same inputs",
             "step_s": round(t_iso, 3), "samples_per_s": round(S / t_iso, 2),
             "smooth": roofline_of(p0["smooth"], SMOOTH_KERNEL),
-            "smooth_stage_level": roofline_of(p0["smooth_stage"], SMOOTH_KERNEL),
-            "restrict_stage_level": roofline_of(p0["restrict_stage"], "restriction after the restricting pre-smoothing pass (combination of two parents)")}
+            "smooth_stage_level": roofline_of(p0["smooth_stage"], SMOOTH_KERNEL)}
         log(f"one-stream step: {S / t_iso:.1f} samples/s, smoother {extra['roofline_one_stream']['smooth']['achieved']} GB/s")
 
     # plain per-sample FP64 GPU MSG: one sample per call, same kernels
