@@ -298,6 +298,10 @@ hipError_t launch_mat_row(int K, int Mx, int My, double hx, double hy, double nu
 hipError_t launch_fft_rows(int64_t rows, int logn, int tw_stride, const double2* tw, double2* X, hipStream_t st)
 {
     const size_t lds = sizeof(double2) << logn;
+    if (lds > 65536) {                        // rows of 8192 points: 128 KB of the CU's 160 KB
+        hipError_t e = hipFuncSetAttribute((const void*)k_fft_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_fft_rows, dim3((unsigned)rows), dim3(256), lds, st, rows, logn, tw_stride, tw, X);
     return LAUNCH_CHECK();
 }

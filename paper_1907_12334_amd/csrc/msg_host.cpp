@@ -1994,7 +1994,7 @@ extern "C" msg_status msg_cycles(msg_handle h, const msg_batch_desc* batch, cons
 namespace {
 
 constexpr uint64_t kMaternKey1 = 0x6D617465726Eull;
-constexpr int kMaternMaxLog = 12;        // rows of up to 4096 points: one row in 64 KB of LDS
+constexpr int kMaternMaxLog = 13;        // rows of up to 8192 points: one row in 128 KB of LDS
 constexpr int kMaternChunk = 8;          // samples per chunk at the suggested workspace size
 constexpr int kMaternBlocks = 256;       // partial min/max blocks per sample
 
@@ -2029,7 +2029,7 @@ msg_status check_matern(const msg_batch_desc* batch, const msg_matern_spec* sp)
         int lx, ly;
         matern_shape(batch->c, batch->P[s], batch->Q[s], sp->nu, sp->pad, lx, ly);
         if (lx > kMaternMaxLog || ly > kMaternMaxLog)
-            return fail(MSG_ERR_UNSUPPORTED, "sample %d: embedding of 2^%d x 2^%d points exceeds 4096 per direction", s,
+            return fail(MSG_ERR_UNSUPPORTED, "sample %d: embedding of 2^%d x 2^%d points exceeds 8192 per direction", s,
                         lx, ly);
     }
     return MSG_OK;

@@ -124,3 +124,14 @@ def test_full_size_64x64_grid(handle):
     print("matern 64x64", flush=True)
     g = _gpu(handle, c, P, Q, spec)
     _compare(g, c, P, Q, 0.25, 0.5, eta, theta, [5, 9], 2019)
+
+
+def test_largest_embedding_256x256_grid(handle):
+    """256 x 256 cells: the paper's factor gives an 8192 x 8192 embedding,
+    rows of 8192 points in 128 KB of LDS."""
+    c, P, Q = 2, [7], [7]
+    eta, theta = np.array([1 / 16]), np.radians([20.0])
+    spec = msg.MaternSpec(0.25, 0.5, eta, theta, [3], seed=77)
+    print("matern 256x256", flush=True)
+    g = _gpu(handle, c, P, Q, spec)
+    _compare(g, c, P, Q, 0.25, 0.5, eta, theta, [3], 77)
