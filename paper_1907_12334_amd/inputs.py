@@ -12,7 +12,7 @@ id), so a sample's coefficients do not depend on the batch it is solved in.
 from __future__ import annotations
 
 import dataclasses
-from typing import List, Optional, Sequence
+from typing import Tuple, List, Optional, Sequence
 
 import numpy as np
 
@@ -117,6 +117,28 @@ def config(k: int) -> Workload:
         return uniform("se-1024x64-s1024-mixed", 4, 8, 4, 1024, separable(1.0, 0.01, 2.0),
                        precision="mixed", ir_tol=1e-8, seed=BASE_SEED + 4, max_cycles=1000)
     raise ValueError(f"no workload preset {k}")
+
+
+@dataclasses.dataclass(frozen=True)
+class MaternPrior:
+    """The paper's random coefficient of its multi-index experiments: Matern
+    covariance with length scale lam and smoothness nu, the anisotropic ratio
+    eta and the rotation theta drawn per sample, uniform on the given ranges
+    (theta in degrees), and the embedding factor pad (0: the paper's)."""
+    lam: float = 0.25
+    nu: float = 0.5
+    eta: Tuple[float, float] = (1.0 / 16, 1.0 / 4)
+    theta_deg: Tuple[float, float] = (-30.0, 30.0)
+    pad: int = 0
+
+    def hyperparameters(self, u: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+        """(eta, theta in radians) per sample from rows of two uniforms."""
+        eta = self.eta[0] + (self.eta[1] - self.eta[0]) * u[:, 0]
+        theta = np.radians(self.theta_deg[0] + (self.theta_deg[1] - self.theta_deg[0]) * u[:, 1])
+        return eta, theta
+
+
+MATERN_PAPER = MaternPrior()
 
 
 def mimc_uniforms(n: int, batch: int = 0, seed: int = BASE_SEED + 6, d: int = 2) -> np.ndarray:

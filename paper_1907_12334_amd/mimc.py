@@ -23,6 +23,16 @@ sizes.  Each sample keeps the p_tau of the distribution it was drawn from.
 Indices are capped at `lmax` per direction (tail mass exp(-r (lmax+1))).
 
 Random numbers are inputs (inputs.mimc_uniforms): L_j = floor(-log(U_j) / r_j).
+
+Two field models.  The default draws the coefficient from a truncated
+expansion (inputs.FieldSpec, normals from inputs.draw_xi).  With a Matern
+prior (inputs.MaternPrior) every sample is the paper's Section 5 setting: a
+lognormal field with Matern covariance whose anisotropic ratio eta and
+rotation theta are themselves uniform random hyperparameters, drawn per
+sample from a second stream of uniforms (inputs.mimc_uniforms with seed + 1),
+and sampled exactly by circulant embedding on the device (msg_sample_matern,
+the Philox stream keyed by the estimator's seed, the sample counter as id), so
+every sample recomputes its embedding's eigenvalues.
 """
 from __future__ import annotations
 
@@ -76,8 +86,11 @@ class MSGMIMC:
 
     def __init__(self, handle: msg.Handle, field: I.FieldSpec = I.KL10, c: int = 4,
                  kind: int = msg.QOI_POINT, opts: Optional[msg.SolveOpts] = None, lmax: int = 9,
-                 r0: Optional[np.ndarray] = None, seed: int = I.BASE_SEED + 6, learn: bool = True):
+                 r0: Optional[np.ndarray] = None, seed: int = I.BASE_SEED + 6, learn: bool = True,
+                 prior: Optional[I.MaternPrior] = None):
         self.h, self.field, self.c, self.kind = handle, field, c, kind
+        self.prior = prior
+        self.min_eig_ratio = math.inf
         self.opts = opts or msg.SolveOpts(tol=1e-8, max_cycles=200, precision=msg.MIXED)
         self.lmax, self.seed, self.learn = lmax, seed, learn
         self.r = np.array(initial_rates() if r0 is None else r0, dtype=float)
@@ -88,16 +101,29 @@ class MSGMIMC:
         self.next_sample_id = 0
 
     # -------------------------------------------------------------- one batch
+    def hyperparameters(self, n: int, batch: int) -> Tuple[np.ndarray, np.ndarray]:
+        """(eta, theta in radians) of the n samples of a batch under the prior."""
+        return self.prior.hyperparameters(I.mimc_uniforms(n, batch, self.seed + 1))
+
     def solve_batch(self, L: np.ndarray):
         """One ragged library call: per-grid Delta Q of every sample (host arrays)."""
         import torch
         P, Q = L[:, 0].astype(np.int32), L[:, 1].astype(np.int32)
         batch = msg.Batch(self.c, P, Q)
-        ids = range(self.next_sample_id, self.next_sample_id + len(P))
+        ids = np.arange(self.next_sample_id, self.next_sample_id + len(P), dtype=np.int64)
         self.next_sample_id += len(P)
-        xi = torch.tensor(I.draw_xi(self.field.n_terms, ids, self.seed), dtype=torch.float64, device="cuda:0")
         bufs = msg.Buffers(batch, self.opts)
-        msg.run(self.h, self.field, batch, self.opts, xi, bufs)
+        if self.prior is None:
+            xi = torch.tensor(I.draw_xi(self.field.n_terms, ids, self.seed), dtype=torch.float64, device="cuda:0")
+            msg.run(self.h, self.field, batch, self.opts, xi, bufs)
+        else:
+            pr = self.prior
+            eta, theta = self.hyperparameters(len(P), self.batches)
+            spec = msg.MaternSpec(pr.lam, pr.nu, eta, theta, ids, self.seed, pr.pad)
+            ratio = torch.empty(len(P), dtype=torch.float64, device="cuda:0")
+            self.h.sample_matern(spec, batch, bufs.kx, bufs.ky, bufs.kx32, bufs.ky32, ratio=ratio)
+            msg.run(self.h, None, batch, self.opts, None, bufs, field=False)
+            self.min_eig_ratio = min(self.min_eig_ratio, float(ratio.min()))
         if self.kind != msg.QOI_MEAN:
             msg.quantity(batch, self.kind, bufs.kx, bufs.u, bufs.q)
             msg.delta_q(batch, bufs.q, bufs.dq)

@@ -120,3 +120,58 @@ def test_batched_estimator_matches_reference_on_oracle_solutions():
     e0, v0 = MO.estimate(ys)
     assert abs(e - e0) <= 1e-9 * abs(e0) and abs(v - v0) <= 1e-7 * v0
     assert len(est.counts) > 3                        # the draws spread over several rectangles
+
+
+def test_matern_prior_hyperparameters_span_the_paper_ranges():
+    """Section 5's hyperparameters: eta uniform on [1/16, 1/4], theta uniform
+    on [-30, 30] degrees, mapped affinely from the uniforms."""
+    pr = I.MATERN_PAPER
+    assert (pr.lam, pr.nu, pr.pad) == (0.25, 0.5, 0)
+    eta, theta = pr.hyperparameters(np.array([[1.0, 1.0], [0.5, 0.5], [1e-12, 1e-12]]))
+    assert np.allclose(eta, [0.25, 0.15625, 1 / 16]) and np.allclose(np.degrees(theta), [30.0, 0.0, -30.0])
+    eta, theta = pr.hyperparameters(I.mimc_uniforms(20000, 0, 99))
+    assert eta.min() >= 1 / 16 and eta.max() <= 0.25 and abs(eta.mean() - 0.15625) < 2e-3
+    assert abs(np.degrees(theta)).max() <= 30.0 and abs(np.degrees(theta).mean()) < 0.5
+
+
+@pytest.mark.gpu
+def test_matern_prior_estimator_matches_reference_on_oracle_solutions():
+    """The paper's field model inside the estimator: every sample draws eta
+    and theta, its Matern field comes from the device sampler and its solve
+    from full MSG.  Two batches of 16 samples, fixed rates, indices capped at
+    2: E and V equal the reference estimator's on oracle fields and oracle
+    solutions of the same samples (same uniforms, same Philox stream)."""
+    import torch
+    from oracle import binding as O
+    from oracle import matern_oracle as MT
+    from paper_1907_12334_amd import msg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h = msg.Handle(0)
+    r = (0.6, 0.8)
+    est = M.MSGMIMC(h, c=4, kind=msg.QOI_POINT, opts=msg.SolveOpts(tol=1e-10), lmax=2, r0=np.array(r),
+                    learn=False, prior=I.MATERN_PAPER)
+    print("matern mimc: 2 batches of 16", flush=True)
+    est.add_batch(16)
+    est.add_batch(16)
+    e, v = est.estimate()
+    ys, sid = [], 0
+    for b in range(2):
+        u = I.mimc_uniforms(16, b, est.seed)
+        uh = I.mimc_uniforms(16, b, est.seed + 1)
+        for x, (ue, ut) in zip(u, uh):
+            L = MO.draw_index(r, tuple(x))
+            L = (min(L[0], 2), min(L[1], 2))
+            eta, theta = 1 / 16 + (1 / 4 - 1 / 16) * ue, math.radians(-30 + 60 * ut)
+            kx, ky, ratio = MT.hierarchy_field(4, L[0], L[1], 0.25, 0.5, eta, theta, sid, est.seed)
+            assert ratio > 0.0
+            sid += 1
+            res = O.fmsg_solve(4, L[0], L[1], kx, ky, O.opts(tol=1e-10))
+            assert res["status"] == 0
+            q = O.qoi(4, L[0], L[1], res["u"], kx, O.QOI_POINT)
+            dq = O.delta_q(L[0], L[1], q)
+            table = {(a, c): dq[a * (L[1] + 1) + c] for a in range(L[0] + 1) for c in range(L[1] + 1)}
+            ys.append(MO.sample_y(table, L, r))
+    e0, v0 = MO.estimate(ys)
+    assert abs(e - e0) <= 1e-9 * abs(e0) and abs(v - v0) <= 1e-7 * v0
+    assert len(est.counts) > 3 and est.min_eig_ratio > 0.0
