@@ -918,29 +918,97 @@ k_tail_slots(const KTail* __restrict__ table, int4* __restrict__ out)
 
 // every grid of level lev, `sweeps` red-then-black sweeps from the slot
 // table: the same updates, in the same arithmetic, as the decoding loop below
+// slot-table entries are read through a global (not flat) pointer: a flat
+// load in flight also holds the LDS counter, so every LDS read after it would
+// wait for the table as well
+typedef int SlotV __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) SlotV* SlotPtr;
+
+// one red-black update of the cell at `off` (this colour's cell of its pair)
+template <typename T>
+__device__ __forceinline__ T tail_cell_update(const T* sm, SlotV e, int d, int db, T inv)
+{
+    const int nx = e.w & 0xffff;
+    const int off = e.x + d, fx = e.y + d, fy = e.z + d;
+    const T cW = sm[fx], cE = sm[fx + 1];
+    const T cS = sm[fy], cN = sm[fy + nx];
+    const T bb = sm[off + db];
+    const bool w = !((e.w >> 17) & 1) || d, ea = !((e.w >> 18) & 1) || !d;
+    const bool so = !((e.w >> 19) & 1), no = !((e.w >> 20) & 1);
+    const T xW = sm[w ? off - 1 : off], xE = sm[ea ? off + 1 : off];
+    const T xS = sm[so ? off - nx : off], xN = sm[no ? off + nx : off];
+    const Nbr<T> nb{w ? xW : T(0), ea ? xE : T(0), so ? xS : T(0), no ? xN : T(0)};
+    return (bb + cW * nb.W + cE * nb.E + cS * nb.S + cN * nb.N) * inv;
+}
+
+template <typename T>
+__device__ __forceinline__ T tail_inv_diag(const T* sm, SlotV e, int d)
+{
+    const int nx = e.w & 0xffff;
+    const int fx = e.y + d, fy = e.z + d;
+    return T(1) / (sm[fx] + sm[fx + 1] + sm[fy] + sm[fy + nx]);
+}
+
+// Levels of at most R slots per thread: the entries and the reciprocal
+// diagonals of both cells of every slot stay in registers for all sweeps
+// (the conductances do not change while smoothing), so the table is read
+// once and each cell divides once per call.
+template <typename T, int NT, int R>
+__device__ __forceinline__ void tail_smooth_regs(T* sm, SlotPtr tab, int total, int db, int sweeps)
+{
+    SlotV e[R];
+    T i0[R], i1[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int sl = (int)threadIdx.x + r * NT;
+        e[r] = sl < total ? tab[sl] : SlotV{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        i0[r] = T(0);
+        i1[r] = T(0);
+        if ((int)threadIdx.x + r * NT < total) {
+            i0[r] = tail_inv_diag(sm, e[r], 0);
+            i1[r] = tail_inv_diag(sm, e[r], 1);
+        }
+    }
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if ((int)threadIdx.x + r * NT < total) {
+                    const int d = (colour + (e[r].w >> 16)) & 1;
+                    sm[e[r].x + d] = tail_cell_update(sm, e[r], d, db, d ? i1[r] : i0[r]);
+                }
+            }
+            __syncthreads();
+        }
+}
+
 template <typename T, int NT>
 __device__ __forceinline__ void tail_smooth_table(const KTail& TL, T* sm, int lev, int sweeps)
 {
     const KTailLevel L = TL.lvl[lev];
     const int total = (L.cells >> 1) * L.ng;
     const int db = L.b0 - L.v0;                     // right-hand side of a cell, relative to its iterate
-    const int4* tab = TL.slots + TL.slot_off[lev];
+    const SlotPtr tab = (SlotPtr)(TL.slots + TL.slot_off[lev]);
+    if (total <= NT) {
+        tail_smooth_regs<T, NT, 1>(sm, tab, total, db, sweeps);
+        return;
+    }
+    if (total <= 4 * NT) {
+        tail_smooth_regs<T, NT, 4>(sm, tab, total, db, sweeps);
+        return;
+    }
     for (int s = 0; s < sweeps; ++s)
         for (int colour = 0; colour < 2; ++colour) {
-            for (int sl = threadIdx.x; sl < total; sl += NT) {
-                const int4 e = tab[sl];
-                const int nx = e.w & 0xffff;
-                const int d = (colour + (e.w >> 16)) & 1;     // this colour's cell of the pair
-                const int off = e.x + d, fx = e.y + d, fy = e.z + d;
-                const T cW = sm[fx], cE = sm[fx + 1];
-                const T cS = sm[fy], cN = sm[fy + nx];
-                const T bb = sm[off + db];
-                const bool w = !((e.w >> 17) & 1) || d, ea = !((e.w >> 18) & 1) || !d;
-                const bool so = !((e.w >> 19) & 1), no = !((e.w >> 20) & 1);
-                const T xW = sm[w ? off - 1 : off], xE = sm[ea ? off + 1 : off];
-                const T xS = sm[so ? off - nx : off], xN = sm[no ? off + nx : off];
-                const Nbr<T> nb{w ? xW : T(0), ea ? xE : T(0), so ? xS : T(0), no ? xN : T(0)};
-                sm[off] = (bb + cW * nb.W + cE * nb.E + cS * nb.S + cN * nb.N) / (cW + cE + cS + cN);
+            int sl = threadIdx.x;
+            SlotV e = sl < total ? tab[sl] : SlotV{0, 0, 0, 0};
+            for (; sl < total; sl += NT) {
+                const SlotV en = sl + NT < total ? tab[sl + NT] : e;   // the next entry, in flight meanwhile
+                const int d = (colour + (e.w >> 16)) & 1;
+                sm[e.x + d] = tail_cell_update(sm, e, d, db, tail_inv_diag(sm, e, d));
+                e = en;
             }
             __syncthreads();
         }
