@@ -31,6 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HIP events around one launch in this many (hash-picked) in the timed steps:
+# an event pair around every launch costs about 6% of the step
+PROFILE_EVERY = 8
 
 
 def parse():
@@ -142,7 +145,7 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {k}: {time.perf_counter() - t0:.2f} s")
 
-    h.set_profiling(not args.no_profile)
+    h.set_profiling(not args.no_profile, every=PROFILE_EVERY)
     times = []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
@@ -168,6 +171,8 @@ def main():
     roofline = roofline_of(prof["smooth"], SMOOTH_KERNEL, traffic)
     kernel_share = {k: round((v[1] / 1000.0) / elapsed, 4) for k, v in prof.items() if not k.endswith("_stage")}
     extra = {"kernel_time_share": kernel_share, "samples_converged": converged, "autotune": tune,
+             "event_timing": f"HIP events around one launch in {PROFILE_EVERY}, picked by a hash of the launch "
+                             "counter; time shares scaled to all launches",
              "max_cycles_per_grid": int(cycles.max()),
              "roofline_stage_level": {
                  "note": "launches on each F-cycle stage's own level (its largest, HBM-resident grids)",
@@ -175,7 +180,7 @@ def main():
     if not args.no_profile and not args.skip_one_stream:
         # the same step with every launch on one stream: kernel times without
         # another class's kernels sharing the device
-        h.set_profiling(True)
+        h.set_profiling(True, every=PROFILE_EVERY)
         o0 = dataclasses.replace(opts, overlap=0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -306,6 +306,14 @@ typedef struct {
     double bytes;                 /* algorithmic bytes of those launches */
 } msg_kernel_stats;
 
+/* enable: 0 off, 1 an event pair around every launch, n > 1 around one
+ * launch in n (picked by a hash of a running launch counter, so the choice
+ * does not follow the regular launch pattern of a cycle).  Sampled totals
+ * are scaled to every launch: `launches` counts all launches of the kind,
+ * `milliseconds` and `bytes` are the timed launches' sums times (all /
+ * timed), so averages and bytes per millisecond are those of the timed
+ * launches (both zero for a kind none of whose launches was timed).
+ * MSG_ERR_ARG for a negative rate. */
 msg_status msg_set_profiling(msg_handle h, int enable);
 msg_status msg_get_profile(msg_handle h, int kind, msg_kernel_stats *out);
 

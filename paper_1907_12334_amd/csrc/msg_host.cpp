@@ -563,14 +563,24 @@ msg_status chunked(const KLevel& L, int K, F&& f)
 }  // namespace
 
 // Per-kernel-kind event timing while profiling is on: a pair of events
-// around each launch, resolved at the next synchronisation point.
+// around each timed launch, resolved at the next synchronisation point.
+// With every = n > 1 one launch in n is timed, picked by a hash of a running
+// launch counter (a fixed stride could alias with the regular pattern of
+// launches in a cycle); every launch is counted.  The few long launches
+// that solve whole classes are always timed and kept apart from the sampled
+// population, which alone is scaled.
 struct Profiler {
     bool on = false;
+    int every = 1;
+    uint64_t draw = 0;
+    int64_t seen[MSG_KERNEL_KINDS] = {};
+    msg_kernel_stats fixed[MSG_KERNEL_KINDS] = {};
     struct Rec {
         hipEvent_t a, b;
         int kind;
         double bytes;
         int also;          // a second kind the launch counts towards (a subset kind), or -1
+        bool always;       // outside the sampled population
     };
     std::vector<hipEvent_t> pool;
     std::vector<Rec> pending;
@@ -595,9 +605,10 @@ struct Profiler {
             if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
                 for (int k : {r.kind, r.also}) {
                     if (k < 0) continue;
-                    tot[k].launches += 1;
-                    tot[k].milliseconds += ms;
-                    tot[k].bytes += r.bytes;
+                    msg_kernel_stats& t = r.always ? fixed[k] : tot[k];
+                    t.launches += 1;
+                    t.milliseconds += ms;
+                    t.bytes += r.bytes;
                 }
             }
             pool.push_back(r.a);
@@ -609,6 +620,22 @@ struct Profiler {
     {
         pending.clear();
         for (auto& t : tot) t = msg_kernel_stats{0, 0.0, 0.0};
+        for (auto& t : fixed) t = msg_kernel_stats{0, 0.0, 0.0};
+        for (auto& n : seen) n = 0;
+        draw = 0;
+    }
+    // count a launch of `kind` (and `also`); true when it is to be timed
+    bool pick(int kind, int also, bool always)
+    {
+        if (always) return true;
+        seen[kind] += 1;
+        if (also >= 0) seen[also] += 1;
+        if (every <= 1) return true;
+        uint64_t z = (draw++) + 0x9E3779B97F4A7C15ull;          // splitmix64 finaliser
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return z % (uint64_t)every == 0;
     }
     ~Profiler()
     {
@@ -1023,11 +1050,11 @@ double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolo
 }
 
 template <typename F>
-msg_status timed(const Ctx& X, int kind, double bytes, F&& f, int also = -1)
+msg_status timed(const Ctx& X, int kind, double bytes, F&& f, int also = -1, bool always = false)
 {
     Profiler* P = X.prof;
-    if (!P || !P->on) return f();
-    Profiler::Rec r{P->get(), P->get(), kind, bytes, also};
+    if (!P || !P->on || !P->pick(kind, also, always)) return f();
+    Profiler::Rec r{P->get(), P->get(), kind, bytes, also, always};
     if (!r.a || !r.b) return fail(MSG_ERR_HIP, "event creation failed");
     HIPCHK(hipEventRecord(r.a, X.s));
     msg_status st = f();
@@ -1448,7 +1475,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                         if (e != hipSuccess) return fail(MSG_ERR_HIP, "tail launch: %s", hipGetErrorString(e));
                     }
                     return MSG_OK;
-                });
+                }, -1, true);
                 if (st != MSG_OK) return st;
             }
         }
@@ -1485,11 +1512,15 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                     if (n == 0) continue;
                     HIPCHK(hipMemcpyAsync(ws + W.cls, cls.data(), sizeof(int32_t) * SP.K, hipMemcpyHostToDevice, s));
                     TailSolve ad{opts->tol, opts->max_cycles, SP.L, pcycles, d_status, dead};
-                    hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls), 0,
-                                                       lds >= 24576 ? 256 : 64, lds, SP.K, X.probs, X.active, c,
-                                                       opts->mu, opts->nu1, opts->nu2, opts->omega, -1, it64.v[buf],
-                                                       a64b, d_kx, d_ky, nullptr, chol, ad, s);
-                    if (e != hipSuccess) return fail(MSG_ERR_HIP, "handoff launch: %s", hipGetErrorString(e));
+                    st = timed(X, MSG_KERNEL_TAIL, 0.0, [&]() -> msg_status {
+                        hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls), 0,
+                                                           lds >= 24576 ? 256 : 64, lds, SP.K, X.probs, X.active, c,
+                                                           opts->mu, opts->nu1, opts->nu2, opts->omega, -1,
+                                                           it64.v[buf], a64b, d_kx, d_ky, nullptr, chol, ad, s);
+                        if (e != hipSuccess) return fail(MSG_ERR_HIP, "handoff launch: %s", hipGetErrorString(e));
+                        return MSG_OK;
+                    }, -1, true);
+                    if (st != MSG_OK) return st;
                     // the device copy of cls must be consumed before the host vector is rebuilt
                     HIPCHK(hipStreamSynchronize(s));
                 }
@@ -2183,8 +2214,10 @@ extern "C" msg_status msg_sample_matern(msg_handle h, const msg_matern_spec* sp,
 extern "C" msg_status msg_set_profiling(msg_handle h, int enable)
 {
     if (!h) return fail(MSG_ERR_ARG, "handle is NULL");
+    if (enable < 0) return fail(MSG_ERR_ARG, "profiling rate %d is negative", enable);
     for (Lane& ln : h->lane) {
         ln.prof.on = enable != 0;
+        ln.prof.every = std::max(1, enable);
         ln.prof.reset();
     }
     return MSG_OK;
@@ -2195,10 +2228,27 @@ extern "C" msg_status msg_get_profile(msg_handle h, int kind, msg_kernel_stats* 
     if (!h || !out) return fail(MSG_ERR_ARG, "handle and output are required");
     if (kind < 0 || kind >= MSG_KERNEL_KINDS) return fail(MSG_ERR_ARG, "unknown kernel kind %d", kind);
     *out = msg_kernel_stats{0, 0.0, 0.0};
+    int64_t all = 0;
+    msg_kernel_stats fx{0, 0.0, 0.0};
     for (const Lane& ln : h->lane) {
         out->launches += ln.prof.tot[kind].launches;
         out->milliseconds += ln.prof.tot[kind].milliseconds;
         out->bytes += ln.prof.tot[kind].bytes;
+        all += ln.prof.seen[kind];
+        fx.launches += ln.prof.fixed[kind].launches;
+        fx.milliseconds += ln.prof.fixed[kind].milliseconds;
+        fx.bytes += ln.prof.fixed[kind].bytes;
     }
+    // sampled timing: totals over the sampled population estimated from its
+    // timed launches (zero when none was timed), plus the always-timed ones
+    if (all > out->launches) {
+        const double f = out->launches > 0 ? (double)all / (double)out->launches : 0.0;
+        out->milliseconds *= f;
+        out->bytes *= f;
+        out->launches = all;
+    }
+    out->launches += fx.launches;
+    out->milliseconds += fx.milliseconds;
+    out->bytes += fx.bytes;
     return MSG_OK;
 }

@@ -236,8 +236,9 @@ class Handle:
         except Exception:
             pass
 
-    def set_profiling(self, on: bool):
-        _check(lib().msg_set_profiling(self.h, int(bool(on))), "msg_set_profiling")
+    def set_profiling(self, on: bool, every: int = 1):
+        """Event timing of kernel launches; with every = n > 1, of one launch in n."""
+        _check(lib().msg_set_profiling(self.h, int(every) if on else 0), "msg_set_profiling")
 
     def profile(self):
         """{kernel name: (launches, milliseconds, algorithmic bytes)}"""

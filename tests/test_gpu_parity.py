@@ -305,3 +305,29 @@ def test_quantity_argument_errors(handle):
     q = torch.zeros(int(b.layout()["grid"][-1]), dtype=torch.float64, device="cuda:0")
     with pytest.raises(msg.MsgError):
         msg.quantity(b, msg.QOI_FLUX, None, u, q)                  # the flux needs kx
+
+
+def test_sampled_event_timing_counts_every_launch(handle):
+    """Event timing of one launch in 8: every launch is still counted (the
+    same counts as with every launch timed), the byte totals scaled from the
+    timed launches estimate the full ones, and the results do not change.  A
+    negative rate is refused."""
+    c, S = 2, 8
+    xi = I.draw_xi(I.KL10.n_terms, range(S))
+    opts = msg.SolveOpts()
+    runs = {}
+    for every in (1, 8):
+        print(f"profiling every {every}", flush=True)
+        handle.set_profiling(True, every=every)
+        out = PR.gpu_solve(c, [5] * S, [5] * S, I.KL10, xi, opts, handle=handle)
+        runs[every] = (out, handle.profile())
+        handle.set_profiling(False)
+    (o1, p1), (o8, p8) = runs[1], runs[8]
+    assert np.array_equal(o1["u"], o8["u"]) and np.array_equal(o1["cycles"], o8["cycles"])
+    for k in p1:
+        assert p1[k][0] == p8[k][0], k
+    n, b1, b8 = p1["smooth"][0], p1["smooth"][2], p8["smooth"][2]
+    print("smooth launches", n, "bytes", b1, b8, flush=True)
+    assert n > 100 and 0.7 * b1 <= b8 <= 1.4 * b1
+    assert p8["smooth"][1] > 0.0
+    assert msg.lib().msg_set_profiling(handle.h, -1) == msg.MSG_ERR_ARG
