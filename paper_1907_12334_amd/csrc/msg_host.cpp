@@ -663,14 +663,19 @@ struct Lane {
         if (fork) (void)hipEventDestroy(fork);
         if (done) (void)hipEventDestroy(done);
     }
-    // default-priority streams and their events, created on first use
-    hipError_t streams()
+    // default-priority streams and their events, created on first use; the
+    // side streams only for solves that use them (an idle stream still takes
+    // a share of the device's hardware queues)
+    hipError_t streams(bool with_side)
     {
-        if (fork) return hipSuccess;
-        hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
-        for (int k = 0; k < kSideStreams && e == hipSuccess; ++k) {
+        hipError_t e = hipSuccess;
+        if (!fork) {
+            e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
+        }
+        for (int k = 0; with_side && k < kSideStreams && e == hipSuccess; ++k) {
+            if (side[k]) continue;
             e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
         }
@@ -678,10 +683,12 @@ struct Lane {
     }
 };
 
-constexpr int kMaxParts = 4;       // most concurrent parts a large batch is split into
-// parts used (2..kMaxParts); 256x256 x 4096 FP64: 233 samples/s with 2, 253
-// with 3, 210 with 4 (one stream per part plus the caller's: four parts
-// exceed the device's four hardware queues)
+constexpr int kMaxParts = 8;       // most concurrent parts a large batch is split into
+// parts used (2..kMaxParts, MSG_PARTS); 256x256 x 4096 FP64: 233 samples/s
+// with 2, 253 with 3, 210 with 4 while each part also created two idle side
+// streams.  With the side streams made only when used: 313 with 3, 260 with
+// 4, and with GPU_MAX_HW_QUEUES = 8: 312 with 4, 296 with 6, 302 with 8
+// (16 queues); three parts already keep the device busy.
 int g_parts = 3;
 constexpr int kSplitMin = 1024;    // smallest batch split by the automatic overlap
 
@@ -1278,7 +1285,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                 return fail(MSG_ERR_UNSUPPORTED, "class (%d,%d) does not fit LDS; lower tail_levels", C.pc, C.qc);
         }
     HIPCHK(hipSetDevice(h->device));
-    if (ov > 0 || opts->graphs > 0) HIPCHK(ln.streams());
+    if (ov > 0 || opts->graphs > 0) HIPCHK(ln.streams(true));
     char* ws = (char*)d_ws;
     const int c = BL.c, S = BL.S;
 
@@ -1687,7 +1694,7 @@ extern "C" msg_status msg_solve_batch(msg_handle h, const msg_batch_desc* batch,
     if (ws_bytes < sp.total) return fail(MSG_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, sp.total);
     const BatchLayout BL = make_layout(batch);
     HIPCHK(hipSetDevice(h->device));
-    for (int k = 0; k < sp.n; ++k) HIPCHK(h->lane[k].streams());
+    for (int k = 0; k < sp.n; ++k) HIPCHK(h->lane[k].streams(g_split_inner > 0));
     HIPCHK(hipEventRecord(h->lane[0].done, s));
     for (int k = 0; k < sp.n; ++k) HIPCHK(hipStreamWaitEvent(h->lane[k].own, h->lane[0].done, 0));
     msg_status res[kMaxParts];
