@@ -1128,23 +1128,24 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, I
     const KProb* pr = X.probs + C.first + sp.k0;
     const int32_t* act = X.active + C.first + sp.k0;
     msg_status st;
-    auto tail = [&](int count) {
+    auto tail = [&](int count, int combine) {
         T* V = it.now(C.tail_top);
         const T* pack = C.tpack >= 0 ? (const T*)X.tpack + C.tpack + (int64_t)sp.k0 * C.tail.nstat : nullptr;
         const double bytes = tail_bytes(C.tail, sizeof(T)) * (double)X.kact;
         return timed(X, MSG_KERNEL_TAIL, bytes, [&] {
             return chunked(C.top1d, sp.kn, [&](int k0, int kn) {
                 return launch_tail<T>(X.tails, nullptr, 2 * C.ci, 64, C.tail_lds, kn, pr + k0, act + k0, X.c, X.o->mu,
-                                      X.o->nu1, X.o->nu2, (T)X.o->omega, count, V, B, KX, KY,
+                                      X.o->nu1, X.o->nu2, (T)X.o->omega, count, combine, V, B, KX, KY,
                                       pack ? pack + (int64_t)k0 * C.tail.nstat : nullptr, X.chol, TailSolve{}, X.s);
             });
         });
     };
-    if (lev <= C.tail_top) return tail(1);
+    if (lev <= C.tail_top) return tail(1, 0);
     // sweeps red-black sweeps on level lev, two fused per pass; with `corr`
     // the first pass also applies the coarse-grid correction (eq. interpolation).
     // ns = 0 is a copy pass (no sweep).
     int flips = 0;
+    int combine_in_tail = 0;        // the restriction into the tail's top level left two halves to average
     auto pass = [&](int ns, bool corr) -> msg_status {
         const KLevel& L = corr ? C.rbc[lev] : C.rb[lev];
         const T* vin = it.now(lev);
@@ -1199,7 +1200,12 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, I
             it.cur[lev] ^= 1;
             ++flips;
         }
-        {
+        // into the tail's top level, the tail's load averages the two
+        // halves instead
+        if (lev - 1 <= C.tail_top) {
+            combine_in_tail = 1;
+            it.cur[lev - 1] = 0;
+        } else {
             const KLevel& R = C.res[lev];
             T* vc = it.v[0];
             st = timed(
@@ -1232,7 +1238,7 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, I
     }
     }
     if (lev - 1 <= C.tail_top) {
-        if ((st = tail(X.o->mu)) != MSG_OK) return st;
+        if ((st = tail(X.o->mu, combine_in_tail)) != MSG_OK) return st;
     } else {
         for (int m = 0; m < X.o->mu; ++m)
             if ((st = mu_cycle<T>(X, C, sp, lev - 1, it, B, KX, KY)) != MSG_OK) return st;
@@ -1477,7 +1483,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                         TailSolve ad{opts->tol, opts->max_cycles, SP.L, pcycles + k0, d_status, dead};
                         hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls) + k0, 0, threads, lds,
                                                            kn, X.probs + k0, X.active + k0, c, opts->mu, opts->nu1,
-                                                           opts->nu2, opts->omega, -1, it64.v[0], a64b, d_kx, d_ky,
+                                                           opts->nu2, opts->omega, -1, 0, it64.v[0], a64b, d_kx, d_ky,
                                                            nullptr, chol, ad, s);
                         if (e != hipSuccess) return fail(MSG_ERR_HIP, "tail launch: %s", hipGetErrorString(e));
                     }
@@ -1522,7 +1528,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                     st = timed(X, MSG_KERNEL_TAIL, 0.0, [&]() -> msg_status {
                         hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls), 0,
                                                            lds >= 24576 ? 256 : 64, lds, SP.K, X.probs, X.active, c,
-                                                           opts->mu, opts->nu1, opts->nu2, opts->omega, -1,
+                                                           opts->mu, opts->nu1, opts->nu2, opts->omega, -1, 0,
                                                            it64.v[buf], a64b, d_kx, d_ky, nullptr, chol, ad, s);
                         if (e != hipSuccess) return fail(MSG_ERR_HIP, "handoff launch: %s", hipGetErrorString(e));
                         return MSG_OK;

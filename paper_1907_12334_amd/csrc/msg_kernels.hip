@@ -1220,7 +1220,7 @@ template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
 k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int tidx,
        const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c, int mu, int nu1,
-       int nu2, T omega, int count, T* __restrict__ V, T* __restrict__ B, const T* __restrict__ KX,
+       int nu2, T omega, int count, int combine, T* __restrict__ V, T* __restrict__ B, const T* __restrict__ KX,
        const T* __restrict__ KY, const T* __restrict__ pack, const double* __restrict__ chol, TailSolve ad)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1244,13 +1244,26 @@ k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int ti
         tail_faces<T, NT>(TL, pr, c, KX, KY, sm);
     }
     {
+        // combine: the top level was just restricted by the restricting
+        // pre-smoothing pass, which leaves a grid with two parents holding
+        // the x-parent's half in its right-hand side and the y-parent's in
+        // its iterate; they are averaged here (eq. restriction) and the
+        // iterate starts from zero
         const KTailLevel L = TL.lvl[TL.top];
         for (int g = 0; g < L.ng; ++g) {
             const int64_t a = pr.arena_base + TL.top_aoff[g];
             const int v0 = L.v0 + g * L.cells, b0 = L.b0 + g * L.cells;
-            for (int idx = threadIdx.x; idx < L.cells; idx += NT) {
-                sm[v0 + idx] = V[a + idx];
-                sm[b0 + idx] = B[a + idx];
+            const int p = L.pmin + g, q = TL.top - p;
+            if (combine && p + 1 <= TL.pc && q + 1 <= TL.qc) {
+                for (int idx = threadIdx.x; idx < L.cells; idx += NT) {
+                    sm[b0 + idx] = T(0.5) * B[a + idx] + T(0.5) * V[a + idx];
+                    sm[v0 + idx] = T(0);
+                }
+            } else {
+                for (int idx = threadIdx.x; idx < L.cells; idx += NT) {
+                    sm[v0 + idx] = V[a + idx];
+                    sm[b0 + idx] = B[a + idx];
+                }
             }
         }
     }
@@ -1606,8 +1619,8 @@ hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int3
 template <typename T>
 hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int threads, size_t lds_bytes, int K,
                        const KProb* probs, const int32_t* active, int c, int mu, int nu1, int nu2, T omega,
-                       int count, T* V, T* B, const T* KX, const T* KY, const T* pack, const double* chol,
-                       const TailSolve& ad, hipStream_t st)
+                       int count, int combine, T* V, T* B, const T* KX, const T* KY, const T* pack,
+                       const double* chol, const TailSolve& ad, hipStream_t st)
 {
     const void* fn = threads == 256 ? (const void*)k_tail<T, 256> : (const void*)k_tail<T, 64>;
     if (lds_bytes > 65536) {
@@ -1616,10 +1629,10 @@ hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int th
     }
     if (threads == 256)
         hipLaunchKernelGGL((k_tail<T, 256>), dim3(K), dim3(256), lds_bytes, st, tables, cls, tidx, probs, active, c,
-                           mu, nu1, nu2, omega, count, V, B, KX, KY, pack, chol, ad);
+                           mu, nu1, nu2, omega, count, combine, V, B, KX, KY, pack, chol, ad);
     else
         hipLaunchKernelGGL((k_tail<T, 64>), dim3(K), dim3(64), lds_bytes, st, tables, cls, tidx, probs, active, c,
-                           mu, nu1, nu2, omega, count, V, B, KX, KY, pack, chol, ad);
+                           mu, nu1, nu2, omega, count, combine, V, B, KX, KY, pack, chol, ad);
     return LAUNCH_CHECK();
 }
 
@@ -1777,11 +1790,11 @@ template hipError_t launch_prolong<double>(const KLevel&, int, const KProb*, con
 template hipError_t launch_prolong<float>(const KLevel&, int, const KProb*, const int32_t*, int, float, const float*,
                                           float*, const float*, const float*, hipStream_t);
 template hipError_t launch_tail<double>(const KTail*, const int32_t*, int, int, size_t, int, const KProb*,
-                                        const int32_t*, int, int, int, int, double, int, double*, double*,
+                                        const int32_t*, int, int, int, int, double, int, int, double*, double*,
                                         const double*, const double*, const double*, const double*,
                                         const TailSolve&, hipStream_t);
 template hipError_t launch_tail<float>(const KTail*, const int32_t*, int, int, size_t, int, const KProb*,
-                                       const int32_t*, int, int, int, int, float, int, float*, float*, const float*,
+                                       const int32_t*, int, int, int, int, float, int, int, float*, float*, const float*,
                                        const float*, const float*, const double*, const TailSolve&, hipStream_t);
 template hipError_t launch_tail_pack<double>(const KTail*, int, const KProb*, int, const double*, const double*,
                                              double*, hipStream_t);
