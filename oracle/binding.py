@@ -54,6 +54,7 @@ def lib():
         L.oracle_correction.argtypes = [ctypes.c_int] * 3 + [_D, _D, _D, _D, ctypes.c_int, _D]
         L.oracle_field_cos.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I, _I, _D, _D, _D, _D]
         L.oracle_field_separable.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 3 + [_D, _D, _D]
+        L.oracle_face_mean.argtypes = [ctypes.c_int] * 3 + [_D, _D, ctypes.c_int, ctypes.c_int, _D, _D]
         _lib = L
     return _lib
 
@@ -111,17 +112,38 @@ def field_separable(nx, ny, mx, my, lx, ly, sigma2, xi):
     return kx, ky
 
 
+def face_mean(c, P, Q, kxF, kyF, p, q):
+    """Face-mean coefficients of grid (p,q) from the finest grid's (P,Q) faces."""
+    nx, ny = c << p, c << q
+    kx = np.empty((nx + 1) * ny)
+    ky = np.empty(nx * (ny + 1))
+    kxF, kyF = f64(kxF), f64(kyF)
+    lib().oracle_face_mean(c, P, Q, _d(kxF), _d(kyF), p, q, _d(kx), _d(ky))
+    return kx, ky
+
+
+def _grid_field(nx, ny, spec, xi):
+    if spec["kind"] == "cos":
+        return field_cos(nx, ny, spec["a"], spec["b"], spec["amp"], xi)
+    return field_separable(nx, ny, spec["mx"], spec["my"], spec["lx"], spec["ly"], spec["sigma2"], xi)
+
+
 def hierarchy_field(c, P, Q, spec, xi):
-    """Face coefficients of every grid of the rectangle, packed."""
+    """Face coefficients of every grid of the rectangle, packed.  Face rule 0
+    evaluates k at every face midpoint of every grid; rule 1 evaluates it on
+    the finest grid only and gives every coarser face the mean along it."""
     kxs, kys = [], []
-    for _, _, nx, ny in grid_shapes(c, P, Q):
-        if spec["kind"] == "cos":
-            kx, ky = field_cos(nx, ny, spec["a"], spec["b"], spec["amp"], xi)
-        else:
-            kx, ky = field_separable(nx, ny, spec["mx"], spec["my"], spec["lx"], spec["ly"],
-                                     spec["sigma2"], xi)
-        kxs.append(kx)
-        kys.append(ky)
+    if spec.get("face_rule", 0) == 1:
+        kxF, kyF = _grid_field(c << P, c << Q, spec, xi)
+        for p, q, _, _ in grid_shapes(c, P, Q):
+            kx, ky = face_mean(c, P, Q, kxF, kyF, p, q)
+            kxs.append(kx)
+            kys.append(ky)
+    else:
+        for _, _, nx, ny in grid_shapes(c, P, Q):
+            kx, ky = _grid_field(nx, ny, spec, xi)
+            kxs.append(kx)
+            kys.append(ky)
     return np.concatenate(kxs), np.concatenate(kys)
 
 

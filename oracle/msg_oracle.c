@@ -899,6 +899,34 @@ static double z_sep(double x, double y, int mx, int my, const double *amp, doubl
     return sigma * z;
 }
 
+/* Face-mean coefficients of grid (p,q) of a sample whose finest grid is
+ * (P,Q) (reading R2b; direct discretisation on every grid, Section 2, with
+ * the face flux taken as the mean of k along the face).  An x-face of grid
+ * (p,q) lies on the line x = i/nx, which is also an x-face line of the
+ * finest grid, and spans m = 2^(Q-q) rows of the finest grid; its
+ * coefficient is the plain mean of k at the midpoints of those m finest
+ * x-faces (midpoint rule for the mean of k along the face).  Likewise a
+ * y-face spans 2^(P-p) columns of finest y-faces.  kxF, kyF: the finest
+ * grid's pointwise face values; kx, ky: grid (p,q)'s faces (outputs). */
+void oracle_face_mean(int c, int P, int Q, const double *kxF, const double *kyF, int p, int q,
+                      double *kx, double *ky)
+{
+    int nxF = c << P, nx = c << p, ny = c << q;
+    int rx = 1 << (P - p), ry = 1 << (Q - q);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+            double s = 0.0;
+            for (int t = 0; t < ry; ++t) s += kxF[(size_t)(j * ry + t) * (nxF + 1) + (size_t)i * rx];
+            kx[(size_t)j * (nx + 1) + i] = s / ry;
+        }
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            double s = 0.0;
+            for (int t = 0; t < rx; ++t) s += kyF[(size_t)j * ry * nxF + (size_t)i * rx + t];
+            ky[(size_t)j * nx + i] = s / rx;
+        }
+}
+
 void oracle_field_separable(int nx, int ny, int mx, int my, double lenx, double leny, double sigma2,
                             const double *xi, double *kx, double *ky)
 {

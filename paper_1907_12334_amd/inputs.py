@@ -30,7 +30,9 @@ KL10_AMP = tuple(1.0 / j for j in range(1, 11))
 class FieldSpec:
     """k = exp(Z).  kind 'cos': Z = sum_t amp_t xi_t cos(pi a_t x) cos(pi b_t y).
     kind 'separable': separable squared-exponential KL with mx*my terms,
-    correlation lengths lx, ly and variance sigma2."""
+    correlation lengths lx, ly and variance sigma2.  face_rule 0: k at every
+    face midpoint of every grid; 1: k at the finest grid's face midpoints and,
+    on every coarser face, the mean of those lying on it."""
     kind: str
     a: Sequence[int] = ()
     b: Sequence[int] = ()
@@ -40,6 +42,7 @@ class FieldSpec:
     lx: float = 0.0
     ly: float = 0.0
     sigma2: float = 0.0
+    face_rule: int = 0
 
     @property
     def n_terms(self) -> int:
@@ -52,8 +55,8 @@ class FieldSpec:
 KL10 = FieldSpec(kind="cos", a=KL10_A, b=KL10_B, amp=KL10_AMP)
 
 
-def separable(lx: float, ly: float, sigma2: float, m: int = 50) -> FieldSpec:
-    return FieldSpec(kind="separable", mx=m, my=m, lx=lx, ly=ly, sigma2=sigma2)
+def separable(lx: float, ly: float, sigma2: float, m: int = 50, face_rule: int = 0) -> FieldSpec:
+    return FieldSpec(kind="separable", mx=m, my=m, lx=lx, ly=ly, sigma2=sigma2, face_rule=face_rule)
 
 
 def constant_field(n_terms: int = 1) -> FieldSpec:
@@ -103,7 +106,8 @@ def config(k: int) -> Workload:
     if k == 1:   # 16 samples, finest 32x32 with 4x4 coarsest, KL-10, FP64, W(2,2) to 1e-10
         return uniform("kl10-32x32-s16", 4, 3, 3, 16, KL10, seed=BASE_SEED + 1)
     if k == 2:   # 4096 samples, finest 256x256, 2x2 coarsest (64 grids), separable SE 50x50
-        return uniform("se-256x256-s4096", 2, 7, 7, 4096, separable(0.3, 0.03, 1.0), seed=BASE_SEED + 2,
+        return uniform("se-256x256-s4096", 2, 7, 7, 4096, separable(0.3, 0.03, 1.0, face_rule=1),
+                       seed=BASE_SEED + 2,
                        max_cycles=1000)
     if k == 3:   # ragged MIMC index set l1+l2 <= 8, N_l = 8192 * 2^-(l1+l2), at least 16
         P, Q = [], []
@@ -114,7 +118,7 @@ def config(k: int) -> Workload:
                 Q += [l2] * n
         return Workload("kl10-ragged-l1+l2<=8", 4, P, Q, KL10, seed=BASE_SEED + 3)
     if k == 4:   # 1024 samples, finest 1024x64, strong anisotropy, mixed precision
-        return uniform("se-1024x64-s1024-mixed", 4, 8, 4, 1024, separable(1.0, 0.01, 2.0),
+        return uniform("se-1024x64-s1024-mixed", 4, 8, 4, 1024, separable(1.0, 0.01, 2.0, face_rule=1),
                        precision="mixed", ir_tol=1e-8, seed=BASE_SEED + 4, max_cycles=1000)
     raise ValueError(f"no workload preset {k}")
 
