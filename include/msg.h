@@ -73,6 +73,22 @@ enum {
 
 enum { MSG_FP64 = 0, MSG_MIXED = 1 };
 
+/* How k enters the face conductances of each grid (direct discretisation
+ * on every grid, Section 2; the paper does not say where k is sampled):
+ *   MSG_FACE_POINT  k at the midpoint of every face of every grid;
+ *   MSG_FACE_MEAN   k at the midpoints of the finest grid's faces, and on
+ *                   every coarser grid the plain mean of the finest-grid
+ *                   values along each face: an x-face of grid (p,q) lies on
+ *                   an x-face line of the finest grid (P,Q) and spans 2^(Q-q)
+ *                   of its faces; a y-face spans 2^(P-p) finest y-faces.
+ *                   The coarse operators are then those of the mean flux
+ *                   through each face, which keeps them consistent with the
+ *                   finer grids when k varies below the coarse mesh width.
+ *                   A grid's coefficients depend on the sample's finest
+ *                   grid, so samples whose differences are combined in one
+ *                   estimator must share their finest grid. */
+enum { MSG_FACE_POINT = 0, MSG_FACE_MEAN = 1 };
+
 typedef struct {
     int32_t kind;               /* MSG_FIELD_* */
     int32_t n_terms;            /* COS_TABLE: number of terms; SEPARABLE_SE: mx*my */
@@ -81,6 +97,17 @@ typedef struct {
     const double *amp;          /* COS_TABLE: host [n_terms] amplitudes */
     int32_t mx, my;             /* SEPARABLE_SE: modes per direction */
     double lx, ly, sigma2;      /* SEPARABLE_SE: correlation lengths and variance */
+    int32_t face_rule;          /* MSG_FACE_POINT or MSG_FACE_MEAN */
+    int32_t reserved;           /* 0 */
+    /* Used when msg_sample_field gets d_xi = NULL: the standard normals are
+     * drawn on the device, xi[t] of a sample being normal t of the stream
+     * (seed, sample id): Philox4x64-10 (Salmon et al. 2011) at counter
+     * (t / 4, sample id, 0, 0) with key (seed, 0x4B4C2D7869), whose four
+     * words w give u = ((w >> 12) + 1/2) 2^-52 and, by the Box-Muller
+     * transform of words (0,1) and (2,3), the normals t = 4n, 4n+1 (cosine,
+     * sine of the first pair) and 4n+2, 4n+3 (of the second pair). */
+    uint64_t seed;
+    const int64_t *sample_id;   /* host [n_samples], or NULL for 0..n_samples-1 */
 } msg_field_spec;
 
 typedef struct {
@@ -143,12 +170,16 @@ msg_status msg_layout(const msg_batch_desc *batch, int64_t *cell_off, int64_t *x
 msg_status msg_workspace_size(msg_handle h, const msg_batch_desc *batch,
                               const msg_solve_opts *opts, size_t *bytes);
 
-/* Coefficient field k = exp(Z) at every face midpoint of every grid of every
- * sample (direct discretisation on each grid, Section 2; the paper samples
- * Z exactly, Section 5 -- here Z is the KL sum of msg_field_spec).
- * d_xi: device [S][n_terms] standard normal coefficients, row per sample.
+/* Coefficient field k = exp(Z) on the faces of every grid of every sample
+ * (direct discretisation on each grid, Section 2; the paper samples Z
+ * exactly, Section 5 -- here Z is the KL sum of msg_field_spec, and
+ * spec->face_rule says where k is taken on each face).
+ * d_xi: device [S][n_terms] standard normal coefficients, row per sample, or
+ * NULL to draw them on the device from spec->seed and spec->sample_id.
  * d_kx, d_ky: device FP64 outputs in the face layout.  d_kx32, d_ky32: NULL,
- * or FP32 copies (needed by MSG_MIXED solves).  Enqueued on `stream`. */
+ * or FP32 copies (needed by MSG_MIXED solves).  Errors: MSG_ERR_ARG (bad
+ * spec, missing outputs, unknown face rule).  Enqueued on `stream`; returns
+ * after it completes. */
 msg_status msg_sample_field(msg_handle h, const msg_field_spec *spec, const msg_batch_desc *batch,
                             const double *d_xi, double *d_kx, double *d_ky,
                             float *d_kx32, float *d_ky32, msg_stream stream);

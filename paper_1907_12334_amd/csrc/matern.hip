@@ -27,6 +27,7 @@
 
 #include "matern_kernels.hpp"
 #include "msg_device.hpp"
+#include "philox.hpp"
 
 namespace msg {
 
@@ -198,27 +199,7 @@ k_eig_ratio(int nb, const double2* __restrict__ part, const int32_t* __restrict_
 }
 
 // ------------------------------------------------------------------ normals
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
-{
-    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += W0;
-            k1 += W1;
-        }
-        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-__device__ __forceinline__ double uniform52(uint64_t w) { return ((double)(w >> 12) + 0.5) * 0x1p-52; }
+// Philox4x64-10 and uniform52: philox.hpp
 
 // W = sqrt(max(Lambda, 0) / M) xi on the transposed layout [kx][ky]; xi of
 // the frequency at row-major position l = ky Mx + kx is the Box-Muller pair

@@ -843,8 +843,10 @@ msg_status msg_sample_field(msg_handle h, const msg_field_spec* spec, const msg_
     if (!h) return fail(MSG_ERR_ARG, "handle is NULL");
     msg_status st = check_batch(batch);
     if (st != MSG_OK) return st;
-    if (!spec || !d_xi || !d_kx || !d_ky) return fail(MSG_ERR_ARG, "spec, xi, kx and ky are required");
+    if (!spec || !d_kx || !d_ky) return fail(MSG_ERR_ARG, "spec, kx and ky are required");
     if ((d_kx32 == nullptr) != (d_ky32 == nullptr)) return fail(MSG_ERR_ARG, "give both FP32 copies or neither");
+    if (spec->face_rule != MSG_FACE_POINT && spec->face_rule != MSG_FACE_MEAN)
+        return fail(MSG_ERR_ARG, "unknown face rule %d", spec->face_rule);
     hipStream_t s = (hipStream_t)stream;
     FieldArgs A;
     std::memset(&A, 0, sizeof A);
@@ -892,24 +894,49 @@ msg_status msg_sample_field(msg_handle h, const msg_field_spec* spec, const msg_
     }
     const BatchLayout BL = make_layout(batch);
     const std::vector<SampleBase> bases = sample_bases(BL);
-    // samples grouped by grid index: one launch per (grid, face kind)
-    std::map<std::pair<int, int>, std::vector<int32_t>> bygrid;
+    const bool mean = spec->face_rule == MSG_FACE_MEAN;
+    // samples grouped by grid index: one launch per (grid, face kind).  The
+    // synthesis covers every grid (MSG_FACE_POINT) or each sample's finest
+    // grid only (MSG_FACE_MEAN), whose coarser grids then take face means.
+    std::map<std::pair<int, int>, std::vector<int32_t>> bygrid, coarse;
     for (int s = 0; s < BL.S; ++s)
         for (int p = 0; p <= BL.P[s]; ++p)
-            for (int q = 0; q <= BL.Q[s]; ++q) bygrid[{p, q}].push_back(s);
+            for (int q = 0; q <= BL.Q[s]; ++q) {
+                if (!mean || (p == BL.P[s] && q == BL.Q[s])) bygrid[{p, q}].push_back(s);
+                if (mean && !(p == BL.P[s] && q == BL.Q[s])) coarse[{p, q}].push_back(s);
+            }
     size_t nlist = 0;
     for (auto& kv : bygrid) nlist += kv.second.size();
+    for (auto& kv : coarse) nlist += kv.second.size();
+    std::vector<int64_t> ids;
+    if (!d_xi) {
+        ids.resize(BL.S);
+        for (int k = 0; k < BL.S; ++k) ids[k] = spec->sample_id ? spec->sample_id[k] : k;
+    }
     HIPCHK(hipSetDevice(h->device));
     void* dmem = nullptr;
-    const size_t bytes = align_up(sizeof(SampleBase) * BL.S) + sizeof(int32_t) * nlist;
+    const size_t o_lists = align_up(sizeof(SampleBase) * BL.S);
+    const size_t o_ids = o_lists + align_up(sizeof(int32_t) * nlist);
+    const size_t o_xi = o_ids + align_up(sizeof(int64_t) * ids.size());
+    const size_t bytes = o_xi + (d_xi ? 0 : sizeof(double) * (size_t)BL.S * A.n_terms);
     HIPCHK(hipMallocAsync(&dmem, bytes, s));
     SampleBase* d_bases = (SampleBase*)dmem;
-    int32_t* d_lists = (int32_t*)((char*)dmem + align_up(sizeof(SampleBase) * BL.S));
+    int32_t* d_lists = (int32_t*)((char*)dmem + o_lists);
     std::vector<int32_t> lists;
     lists.reserve(nlist);
     for (auto& kv : bygrid) lists.insert(lists.end(), kv.second.begin(), kv.second.end());
+    for (auto& kv : coarse) lists.insert(lists.end(), kv.second.begin(), kv.second.end());
     HIPCHK(hipMemcpyAsync(d_bases, bases.data(), sizeof(SampleBase) * BL.S, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(d_lists, lists.data(), sizeof(int32_t) * nlist, hipMemcpyHostToDevice, s));
+    const double* xi = d_xi;
+    if (!d_xi) {
+        int64_t* d_ids = (int64_t*)((char*)dmem + o_ids);
+        double* d_draw = (double*)((char*)dmem + o_xi);
+        HIPCHK(hipMemcpyAsync(d_ids, ids.data(), sizeof(int64_t) * BL.S, hipMemcpyHostToDevice, s));
+        hipError_t e = launch_kl_xi(BL.S, A.n_terms, spec->seed, d_ids, d_draw, s);
+        if (e != hipSuccess) return fail(MSG_ERR_HIP, "normals launch: %s", hipGetErrorString(e));
+        xi = d_draw;
+    }
     size_t at = 0;
     for (auto& kv : bygrid) {
         A.p = kv.first.first;
@@ -920,11 +947,21 @@ msg_status msg_sample_field(msg_handle h, const msg_field_spec* spec, const msg_
         for (int kind = 0; kind < 2; ++kind) {
             A.kind_faces = kind;
             for (int s0 = 0; s0 < n; s0 += 65535) {
-                hipError_t e = launch_field(A, std::min(65535, n - s0), d_lists + at + s0, d_bases, d_xi, d_kx, d_ky,
+                hipError_t e = launch_field(A, std::min(65535, n - s0), d_lists + at + s0, d_bases, xi, d_kx, d_ky,
                                             d_kx32, d_ky32, s);
                 if (e != hipSuccess) return fail(MSG_ERR_HIP, "field launch: %s", hipGetErrorString(e));
             }
         }
+        at += n;
+    }
+    for (auto& kv : coarse) {
+        const int n = (int)kv.second.size();
+        for (int kind = 0; kind < 2; ++kind)
+            for (int s0 = 0; s0 < n; s0 += 65535) {
+                hipError_t e = launch_face_mean(batch->c, kv.first.first, kv.first.second, kind, std::min(65535, n - s0),
+                                                d_lists + at + s0, d_bases, d_kx, d_ky, d_kx32, d_ky32, s);
+                if (e != hipSuccess) return fail(MSG_ERR_HIP, "face mean launch: %s", hipGetErrorString(e));
+            }
         at += n;
     }
     HIPCHK(hipFreeAsync(dmem, s));

@@ -15,6 +15,7 @@
 
 #include "msg_device.hpp"
 #include "msg_kernels.hpp"
+#include "philox.hpp"
 
 namespace msg {
 
@@ -215,6 +216,80 @@ k_field(FieldArgs A, const int32_t* __restrict__ samples, const SampleBase* __re
         const int64_t o = base + (int64_t)j * fw + i;
         out[o] = k;
         if (out32) out32[o] = (float)k;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Face-mean coefficients (MSG_FACE_MEAN): every face of grid (p,q) of a
+// sample takes the mean of the finest grid's face values lying on it, summed
+// in order along the face.  An x-face (i,j) lies on the finest x-face column
+// i 2^(P-p) and spans its rows j 2^(Q-q) .. (j+1) 2^(Q-q) - 1; a y-face (i,j)
+// lies on the finest y-face row j 2^(Q-q) and spans its columns
+// i 2^(P-p) .. (i+1) 2^(P-p) - 1.  The finest grid itself is left as
+// synthesised.  One thread per output face; blockIdx.y is the sample of the
+// list.  The reads of neighbouring threads are strided by 2^(P-p) elements
+// (x-faces) or contiguous runs (y-faces), served mostly from L2: the finest
+// grid of a sample is a few hundred KB.
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_face_mean(int c, int p, int q, int kind_faces, const int32_t* __restrict__ samples,
+            const SampleBase* __restrict__ bases, double* __restrict__ KX, double* __restrict__ KY,
+            float* __restrict__ KX32, float* __restrict__ KY32)
+{
+    const SampleBase sb = bases[samples[blockIdx.y]];
+    if (p == sb.P && q == sb.Q) return;
+    const int nx = c << p, ny = c << q, nxF = c << sb.P;
+    const int rx = 1 << (sb.P - p), ry = 1 << (sb.Q - q);
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (kind_faces == 0) {
+        if (f >= (int64_t)(nx + 1) * ny) return;
+        const int i = (int)(f % (nx + 1)), j = (int)(f / (nx + 1));
+        const double* src = KX + sb.fx + xface_off(c, sb.Q, sb.P, sb.Q) + (int64_t)j * ry * (nxF + 1) + (int64_t)i * rx;
+        double sum = 0.0;
+        for (int t = 0; t < ry; ++t) sum += src[(int64_t)t * (nxF + 1)];
+        const double k = sum / (double)ry;
+        const int64_t o = sb.fx + xface_off(c, sb.Q, p, q) + f;
+        KX[o] = k;
+        if (KX32) KX32[o] = (float)k;
+    } else {
+        if (f >= (int64_t)nx * (ny + 1)) return;
+        const int i = (int)(f % nx), j = (int)(f / nx);
+        const double* src = KY + sb.fy + yface_off(c, sb.Q, sb.P, sb.Q) + (int64_t)j * ry * nxF + (int64_t)i * rx;
+        double sum = 0.0;
+        for (int t = 0; t < rx; ++t) sum += src[t];
+        const double k = sum / (double)rx;
+        const int64_t o = sb.fy + yface_off(c, sb.Q, p, q) + f;
+        KY[o] = k;
+        if (KY32) KY32[o] = (float)k;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Standard normal KL coefficients drawn on the device: xi[s][t] is normal t
+// of the stream (seed, id[s]): Philox4x64-10 at counter (t/4, id, 0, 0),
+// key (seed, kKlKey); words (0,1) give normals 4n (rho cos) and 4n+1
+// (rho sin) by the Box-Muller transform, words (2,3) normals 4n+2 and 4n+3.
+// One thread per group of four normals.
+// ------------------------------------------------------------------------
+constexpr uint64_t kKlKey = 0x4B4C2D7869ull;
+
+__global__ void __launch_bounds__(kBlock)
+k_kl_xi(int S, int n_terms, uint64_t seed, const int64_t* __restrict__ ids, double* __restrict__ xi)
+{
+    const int groups = (n_terms + 3) / 4;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)S * groups) return;
+    const int s = (int)(g / groups), n = (int)(g % groups);
+    uint64_t w[4] = {(uint64_t)n, (uint64_t)ids[s], 0, 0};
+    philox4x64_10(w, seed, kKlKey);
+    double* out = xi + (int64_t)s * n_terms;
+    for (int h = 0; h < 2; ++h) {
+        const double rho = sqrt(-2.0 * log(uniform52(w[2 * h])));
+        double sn, cs;
+        sincos(2.0 * M_PI * uniform52(w[2 * h + 1]), &sn, &cs);
+        const int t = 4 * n + 2 * h;
+        if (t < n_terms) out[t] = rho * cs;
+        if (t + 1 < n_terms) out[t + 1] = rho * sn;
     }
 }
 
@@ -1515,6 +1590,24 @@ hipError_t launch_field(const FieldArgs& A, int nsamples, const int32_t* samples
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_field, dim3(tiles, nsamples), dim3(kBlock), lds, st, A, samples, bases, xi, kx, ky, kx32, ky32);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_face_mean(int c, int p, int q, int kind_faces, int nsamples, const int32_t* samples,
+                            const SampleBase* bases, double* kx, double* ky, float* kx32, float* ky32, hipStream_t st)
+{
+    const int nx = c << p, ny = c << q;
+    const int64_t n = kind_faces == 0 ? (int64_t)(nx + 1) * ny : (int64_t)nx * (ny + 1);
+    hipLaunchKernelGGL(k_face_mean, dim3((unsigned)((n + kBlock - 1) / kBlock), nsamples), dim3(kBlock), 0, st, c, p,
+                       q, kind_faces, samples, bases, kx, ky, kx32, ky32);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_kl_xi(int S, int n_terms, uint64_t seed, const int64_t* ids, double* xi, hipStream_t st)
+{
+    const int64_t n = (int64_t)S * ((n_terms + 3) / 4);
+    hipLaunchKernelGGL(k_kl_xi, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, S, n_terms, seed, ids,
+                       xi);
     return LAUNCH_CHECK();
 }
 

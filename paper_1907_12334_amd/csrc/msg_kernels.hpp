@@ -41,6 +41,12 @@ struct FieldArgs {
 
 hipError_t launch_field(const FieldArgs& A, int nsamples, const int32_t* samples, const SampleBase* bases,
                         const double* xi, double* kx, double* ky, float* kx32, float* ky32, hipStream_t st);
+// the faces of grid (p,q) (kind 0: x, 1: y) of each listed sample as means of
+// its finest grid's faces (MSG_FACE_MEAN); the finest grids must be filled
+hipError_t launch_face_mean(int c, int p, int q, int kind_faces, int nsamples, const int32_t* samples,
+                            const SampleBase* bases, double* kx, double* ky, float* kx32, float* ky32, hipStream_t st);
+// standard normals xi[S][n_terms] of the streams (seed, ids[s])
+hipError_t launch_kl_xi(int S, int n_terms, uint64_t seed, const int64_t* ids, double* xi, hipStream_t st);
 hipError_t launch_chol(int S, int c, const SampleBase* bases, const double* kx, const double* ky, double* chol,
                        hipStream_t st);
 // Vc != nullptr: the pass first adds omega * (coarse-grid correction from the

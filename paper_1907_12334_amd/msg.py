@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmsg.so")
 MSG_OK, MSG_ERR_ARG, MSG_ERR_LAYOUT, MSG_ERR_WORKSPACE, MSG_ERR_HIP, MSG_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 SAMPLE_CONVERGED, SAMPLE_MAXITER, SAMPLE_NONFINITE = 0, 1, 2
 FIELD_COS_TABLE, FIELD_SEPARABLE_SE = 0, 1
+FACE_POINT, FACE_MEAN = 0, 1
 FP64, MIXED = 0, 1
 
 EXPORTS = ("msg_default_opts", "msg_create", "msg_destroy", "msg_last_error", "msg_layout",
@@ -43,7 +44,9 @@ class FieldSpecC(ctypes.Structure):
                 ("a", ctypes.POINTER(ctypes.c_int32)), ("b", ctypes.POINTER(ctypes.c_int32)),
                 ("amp", ctypes.POINTER(ctypes.c_double)),
                 ("mx", ctypes.c_int32), ("my", ctypes.c_int32),
-                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("sigma2", ctypes.c_double)]
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("sigma2", ctypes.c_double),
+                ("face_rule", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("sample_id", ctypes.POINTER(ctypes.c_int64))]
 
 
 class BatchDescC(ctypes.Structure):
@@ -193,21 +196,28 @@ def default_opts() -> SolveOpts:
 
 
 class FieldSpec:
-    """msg_field_spec from an inputs.FieldSpec-like object."""
+    """msg_field_spec from an inputs.FieldSpec-like object.  seed and
+    sample_id (host int64 [n_samples] or None for 0..n-1) name the random
+    streams of the normals when msg_sample_field draws them on the device."""
 
-    def __init__(self, spec):
+    def __init__(self, spec, seed: int = 0, sample_id=None):
         self._keep = []
+        face_rule = int(getattr(spec, "face_rule", 0))
+        ids = None if sample_id is None else np.ascontiguousarray(sample_id, dtype=np.int64)
+        pid = ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if ids is not None else None
         if spec.kind == "cos":
             a = np.ascontiguousarray(spec.a, dtype=np.int32)
             b = np.ascontiguousarray(spec.b, dtype=np.int32)
             amp = np.ascontiguousarray(spec.amp, dtype=np.float64)
-            self._keep = [a, b, amp]
+            self._keep = [a, b, amp, ids]
             self.c_struct = FieldSpecC(FIELD_COS_TABLE, len(a), a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                       amp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0, 0, 0.0, 0.0, 0.0)
+                                       amp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0, 0, 0.0, 0.0, 0.0,
+                                       face_rule, 0, int(seed) & ((1 << 64) - 1), pid)
         else:
+            self._keep = [ids]
             self.c_struct = FieldSpecC(FIELD_SEPARABLE_SE, spec.mx * spec.my, None, None, None, spec.mx, spec.my,
-                                       spec.lx, spec.ly, spec.sigma2)
+                                       spec.lx, spec.ly, spec.sigma2, face_rule, 0, int(seed) & ((1 << 64) - 1), pid)
 
 
 def workspace_size(batch: Batch, opts: SolveOpts, handle=None) -> int:
@@ -351,11 +361,14 @@ class Buffers:
 
 
 def run(handle: Handle, spec, batch: Batch, opts: SolveOpts, xi, bufs: Optional[Buffers] = None, rhs=None,
-        stream=None, field=True):
-    """Field synthesis, full-MSG solve of every sample, multi-index differences."""
+        stream=None, field=True, seed: int = 0, sample_id=None):
+    """Field synthesis, full-MSG solve of every sample, multi-index differences.
+    xi: device normals [S][n_terms], or None to draw them on the device from
+    the streams (seed, sample_id)."""
     bufs = bufs or Buffers(batch, opts)
     if field:
-        handle.sample_field(FieldSpec(spec), batch, xi, bufs.kx, bufs.ky, bufs.kx32, bufs.ky32, stream)
+        handle.sample_field(FieldSpec(spec, seed, sample_id), batch, xi, bufs.kx, bufs.ky, bufs.kx32, bufs.ky32,
+                            stream)
     handle.solve_batch(batch, opts, bufs.kx, bufs.ky, bufs.kx32, bufs.ky32, rhs, bufs.u, bufs.q, bufs.status,
                        bufs.cycles, bufs.ws, stream)
     delta_q(batch, bufs.q, bufs.dq, stream)

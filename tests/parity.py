@@ -7,14 +7,16 @@ from paper_1907_12334_amd import inputs as I
 from paper_1907_12334_amd import msg
 
 
-def gpu_solve(c, P, Q, spec, xi, opts, rhs=None, handle=None):
+def gpu_solve(c, P, Q, spec, xi, opts, rhs=None, handle=None, seed=0, sample_id=None):
+    """xi: host normals [S][n_terms], or None to draw them on the device from
+    the streams (seed, sample_id)."""
     import torch
     h = handle or msg.Handle(0)
     b = msg.Batch(c, P, Q)
     bufs = msg.Buffers(b, opts)
-    xi_d = torch.tensor(np.ascontiguousarray(xi), dtype=torch.float64, device="cuda:0")
+    xi_d = torch.tensor(np.ascontiguousarray(xi), dtype=torch.float64, device="cuda:0") if xi is not None else None
     rhs_d = torch.tensor(rhs, dtype=torch.float64, device="cuda:0") if rhs is not None else None
-    msg.run(h, spec, b, opts, xi_d, bufs, rhs=rhs_d)
+    msg.run(h, spec, b, opts, xi_d, bufs, rhs=rhs_d, seed=seed, sample_id=sample_id)
     torch.cuda.synchronize()
     out = {k: getattr(bufs, k).cpu().numpy() for k in ("kx", "ky", "u", "q", "dq", "cycles", "status")}
     out["layout"] = bufs.layout
@@ -65,13 +67,19 @@ def compare_sample(c, P, Q, spec, xi, g, tol=1e-10, max_cycles=50, rhs=None, ome
         status = ora["status"]
         ora = oracle_solve(c, P, Q, spec, xi, forced=g["cycles"], **kw)
         ora["status"] = status
+    eu, eq, edq = errors(c, P, Q, g, ora)
+    return eu, eq, edq, ora
+
+
+def errors(c, P, Q, g, ora):
+    """(largest per-grid relative error of u, largest relative error of Q,
+    largest error of Delta Q relative to the four quantities it combines)."""
     eu = grid_errors(c, P, Q, g["u"], ora["u"])
     eq = np.max(np.abs(g["q"] - ora["q"]) / np.maximum(np.abs(ora["q"]), 1e-300))
-    # differences are compared against the size of the four quantities they combine
     qm = ora["q"].reshape(P + 1, Q + 1)
     scale = np.abs(qm).copy()
     scale[1:, :] = np.maximum(scale[1:, :], np.abs(qm[:-1, :]))
     scale[:, 1:] = np.maximum(scale[:, 1:], np.abs(qm[:, :-1]))
     scale[1:, 1:] = np.maximum(scale[1:, 1:], np.abs(qm[:-1, :-1]))
     edq = np.max(np.abs(g["dq"] - ora["dq"]) / np.maximum(scale.ravel(), 1e-300))
-    return eu, eq, edq, ora
+    return eu, eq, edq

@@ -208,6 +208,28 @@ def test_mixed_precision_against_fp64_oracle(handle):
         assert np.max(np.abs(g["q"] - ora["q"]) / np.abs(ora["q"])) <= MIXED_TOL
 
 
+def test_mixed_precision_at_the_1024x64_shape(handle):
+    """The 1024x64 preset's own shape and field ((P,Q) = (8,4), c = 4, 45
+    grids, ly = 0.01, sigma^2 = 2, face means): mixed precision refined to
+    1e-8 against the FP64 oracle run to 1e-10 on a seeded subset; per grid
+    u, Q and Delta Q within 1e-8.  Most levels cycle on the host in FP32
+    here and hand over to the FP64 on-chip solves below them."""
+    w = I.config(4)
+    ids = [1, 2, 3, 5]
+    xi = w.xi(ids)
+    opts = msg.SolveOpts(precision=msg.MIXED, tol=w.ir_tol, max_cycles=w.max_cycles)
+    out = PR.gpu_solve(w.c, [8] * 4, [4] * 4, w.field, xi, opts, handle=handle)
+    for s in range(4):
+        g = PR.per_sample(out, s)
+        print(f"sample {ids[s]}: oracle at 1e-10", flush=True)
+        ora = PR.oracle_solve(w.c, 8, 4, w.field, xi[s], tol=1e-10, max_cycles=w.max_cycles)
+        ora["dq"] = O.delta_q(8, 4, ora["q"])
+        assert g["status"] == 0 and ora["status"] == 0
+        eu, eq, edq = PR.errors(w.c, 8, 4, g, ora)
+        print(f"sample {ids[s]}: u {eu:.2e} Q {eq:.2e} dQ {edq:.2e}", flush=True)
+        assert max(eu, eq, edq) <= MIXED_TOL, (ids[s], eu, eq, edq)
+
+
 def test_delta_q_on_device(handle):
     import torch
     b = msg.Batch(4, [2, 3, 0], [3, 1, 4])
