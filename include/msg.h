@@ -335,6 +335,11 @@ typedef struct {
     int64_t launches;
     double milliseconds;          /* sum of per-launch event times */
     double bytes;                 /* algorithmic bytes of those launches */
+    double model_bytes;           /* the per-step byte model: every red-black sweep reads v, b
+                                     and the conductances and writes v as a step of its own
+                                     (5 values per cell), and so do the residual with its
+                                     restriction and the coarse-grid correction; equal to
+                                     `bytes` for kinds other than MSG_KERNEL_SMOOTH */
 } msg_kernel_stats;
 
 /* enable: 0 off, 1 an event pair around every launch, n > 1 around one

@@ -579,6 +579,7 @@ struct Profiler {
         hipEvent_t a, b;
         int kind;
         double bytes;
+        double model;      // bytes of the per-step model (msg_kernel_stats.model_bytes)
         int also;          // a second kind the launch counts towards (a subset kind), or -1
         bool always;       // outside the sampled population
     };
@@ -609,6 +610,7 @@ struct Profiler {
                     t.launches += 1;
                     t.milliseconds += ms;
                     t.bytes += r.bytes;
+                    t.model_bytes += r.model;
                 }
             }
             pool.push_back(r.a);
@@ -619,8 +621,8 @@ struct Profiler {
     void reset()
     {
         pending.clear();
-        for (auto& t : tot) t = msg_kernel_stats{0, 0.0, 0.0};
-        for (auto& t : fixed) t = msg_kernel_stats{0, 0.0, 0.0};
+        for (auto& t : tot) t = msg_kernel_stats{0, 0.0, 0.0, 0.0};
+        for (auto& t : fixed) t = msg_kernel_stats{0, 0.0, 0.0, 0.0};
         for (auto& n : seen) n = 0;
         draw = 0;
     }
@@ -1093,12 +1095,24 @@ double level_bytes(const KLevel& L, int kind_rel /*0 smooth, 1 restrict, 2 prolo
     return per * sizeof(T) * (double)K;
 }
 
+// bytes of the per-step model on a level: `values` values of type T per cell
+// (5 per red-black sweep, 5 for a residual with its restriction or for a
+// correction, 2 for a copy)
+template <typename T>
+double model_bytes(const KLevel& L, double values, int64_t K)
+{
+    double cells = 0.0;
+    for (int g = 0; g < L.ngrids; ++g) cells += (double)L.g[g].nx * L.g[g].ny;
+    return cells * values * sizeof(T) * (double)K;
+}
+
+// model < 0: the per-step model's bytes equal the algorithmic bytes
 template <typename F>
-msg_status timed(const Ctx& X, int kind, double bytes, F&& f, int also = -1, bool always = false)
+msg_status timed(const Ctx& X, int kind, double bytes, F&& f, int also = -1, bool always = false, double model = -1.0)
 {
     Profiler* P = X.prof;
     if (!P || !P->on || !P->pick(kind, also, always)) return f();
-    Profiler::Rec r{P->get(), P->get(), kind, bytes, also, always};
+    Profiler::Rec r{P->get(), P->get(), kind, bytes, model < 0.0 ? bytes : model, also, always};
     if (!r.a || !r.b) return fail(MSG_ERR_HIP, "event creation failed");
     HIPCHK(hipEventRecord(r.a, X.s));
     msg_status st = f();
@@ -1192,6 +1206,7 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, I
         // iterates the correction reads
         const double bytes = ns == 0 ? level_bytes<T>(L, 4, X.kact)
                                      : level_bytes<T>(L, 0, X.kact) + (corr ? level_bytes<T>(L, 3, X.kact) : 0.0);
+        const double model = model_bytes<T>(L, ns == 0 ? 2.0 : 5.0 * ns + (corr ? 5.0 : 0.0), X.kact);
         msg_status r = timed(
             X, MSG_KERNEL_SMOOTH, bytes,
             [&] {
@@ -1200,7 +1215,7 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, I
                                           (T)X.o->omega, X.s);
                 });
             },
-            lev == C.L ? MSG_KERNEL_SMOOTH_STAGE : -1);
+            lev == C.L ? MSG_KERNEL_SMOOTH_STAGE : -1, false, model);
         if (r != MSG_OK) return r;
         it.cur[lev] ^= 1;
         ++flips;
@@ -1232,7 +1247,7 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, I
                         return launch_rbgs_restrict<T>(L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, vc, X.s);
                     });
                 },
-                lev == C.L ? MSG_KERNEL_SMOOTH_STAGE : -1);
+                lev == C.L ? MSG_KERNEL_SMOOTH_STAGE : -1, false, model_bytes<T>(L, 15.0, X.kact));
             if (st != MSG_OK) return st;
             it.cur[lev] ^= 1;
             ++flips;
@@ -1900,12 +1915,15 @@ msg_status mg_cycle(const Ctx& X, const MgPlan& M, int k, Iter<double>& it, doub
             const int ns = (sweeps >= 2 && g_fuse == 2) ? 2 : 1;
             const double* vin = it.now(k);
             double* vout = it.v[1 - it.cur[k]];
-            msg_status r = timed(X, MSG_KERNEL_SMOOTH, level_bytes<double>(L, 0, K), [&] {
-                return chunked(L, K, [&](int k0, int kn) {
-                    return launch_rbgs<double>(ns, L, kn, X.probs + k0, X.active + k0, X.c, vin, vout, B, KX, KY,
-                                               nullptr, X.o->omega, X.s);
-                });
-            });
+            msg_status r = timed(
+                X, MSG_KERNEL_SMOOTH, level_bytes<double>(L, 0, K),
+                [&] {
+                    return chunked(L, K, [&](int k0, int kn) {
+                        return launch_rbgs<double>(ns, L, kn, X.probs + k0, X.active + k0, X.c, vin, vout, B, KX,
+                                                   KY, nullptr, X.o->omega, X.s);
+                    });
+                },
+                -1, false, model_bytes<double>(L, 5.0 * ns, K));
             if (r != MSG_OK) return r;
             it.cur[k] ^= 1;
             sweeps -= ns;
@@ -2277,17 +2295,19 @@ extern "C" msg_status msg_get_profile(msg_handle h, int kind, msg_kernel_stats* 
 {
     if (!h || !out) return fail(MSG_ERR_ARG, "handle and output are required");
     if (kind < 0 || kind >= MSG_KERNEL_KINDS) return fail(MSG_ERR_ARG, "unknown kernel kind %d", kind);
-    *out = msg_kernel_stats{0, 0.0, 0.0};
+    *out = msg_kernel_stats{0, 0.0, 0.0, 0.0};
     int64_t all = 0;
-    msg_kernel_stats fx{0, 0.0, 0.0};
+    msg_kernel_stats fx{0, 0.0, 0.0, 0.0};
     for (const Lane& ln : h->lane) {
         out->launches += ln.prof.tot[kind].launches;
         out->milliseconds += ln.prof.tot[kind].milliseconds;
         out->bytes += ln.prof.tot[kind].bytes;
+        out->model_bytes += ln.prof.tot[kind].model_bytes;
         all += ln.prof.seen[kind];
         fx.launches += ln.prof.fixed[kind].launches;
         fx.milliseconds += ln.prof.fixed[kind].milliseconds;
         fx.bytes += ln.prof.fixed[kind].bytes;
+        fx.model_bytes += ln.prof.fixed[kind].model_bytes;
     }
     // sampled timing: totals over the sampled population estimated from its
     // timed launches (zero when none was timed), plus the always-timed ones
@@ -2295,10 +2315,12 @@ extern "C" msg_status msg_get_profile(msg_handle h, int kind, msg_kernel_stats* 
         const double f = out->launches > 0 ? (double)all / (double)out->launches : 0.0;
         out->milliseconds *= f;
         out->bytes *= f;
+        out->model_bytes *= f;
         out->launches = all;
     }
     out->launches += fx.launches;
     out->milliseconds += fx.milliseconds;
     out->bytes += fx.bytes;
+    out->model_bytes += fx.model_bytes;
     return MSG_OK;
 }

@@ -62,7 +62,8 @@ class MaternSpecC(ctypes.Structure):
 
 
 class KernelStatsC(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64), ("milliseconds", ctypes.c_double), ("bytes", ctypes.c_double)]
+    _fields_ = [("launches", ctypes.c_int64), ("milliseconds", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("model_bytes", ctypes.c_double)]
 
 
 class SolveOptsC(ctypes.Structure):
@@ -251,12 +252,12 @@ class Handle:
         _check(lib().msg_set_profiling(self.h, int(every) if on else 0), "msg_set_profiling")
 
     def profile(self):
-        """{kernel name: (launches, milliseconds, algorithmic bytes)}"""
+        """{kernel name: (launches, milliseconds, algorithmic bytes, per-step model bytes)}"""
         out = {}
         for k, name in enumerate(KERNEL_NAMES):
             st = KernelStatsC()
             _check(lib().msg_get_profile(self.h, k, ctypes.byref(st)), "msg_get_profile")
-            out[name] = (st.launches, st.milliseconds, st.bytes)
+            out[name] = (st.launches, st.milliseconds, st.bytes, st.model_bytes)
         return out
 
     def sample_matern(self, spec: MaternSpec, batch: Batch, kx, ky, kx32=None, ky32=None, ratio=None, ws=None,
