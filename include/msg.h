@@ -184,6 +184,23 @@ msg_status msg_sample_field(msg_handle h, const msg_field_spec *spec, const msg_
                             const double *d_xi, double *d_kx, double *d_ky,
                             float *d_kx32, float *d_ky32, msg_stream stream);
 
+/* msg_sample_field for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops that forbid allocation).  Same
+ * arguments and results as msg_sample_field; its device staging (per
+ * sample about 32 bytes of tables plus 4 bytes per grid, and without d_xi
+ * the drawn normals, 8 bytes per term) lives in a static array of 32 MiB
+ * per device instead of memory allocated for the call; the call allocates
+ * nothing.  Errors: those of msg_sample_field, and MSG_ERR_WORKSPACE, before
+ * any device work, when a batch needs more than 32 MiB of staging (pass d_xi
+ * or split the batch).  All calls on one device share that device's array
+ * and nothing of a call survives in it that a later call needs: calls that
+ * overlap on one device (other host threads, or another stream still
+ * running one) race on it.  Returns after the work has completed on
+ * `stream`. */
+msg_status msg_sample_field_noalloc(msg_handle h, const msg_field_spec *spec, const msg_batch_desc *batch,
+                                    const double *d_xi, double *d_kx, double *d_ky,
+                                    float *d_kx32, float *d_ky32, msg_stream stream);
+
 /* Full MSG solve of every sample (Section 2, Algorithm MSG F-cycle with the
  * MSG mu-cycle, eq. restriction, eq. interpolation, eq. weight_factors),
  * returning the solution of every grid (p,q) of every sample -- the "free

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsg.so")
-SOURCES = ["msg_kernels.hip", "matern.hip", "msg_host.cpp"]
+SOURCES = ["msg_kernels.hip", "matern.hip", "noalloc.hip", "msg_host.cpp"]
 
 # packed-FP32 instructions are disabled: the compiler would otherwise form
 # v_pk_* FP32 arithmetic from scalar float code

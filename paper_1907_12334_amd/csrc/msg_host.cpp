@@ -26,6 +26,7 @@
 #include "../../include/msg.h"
 #include "matern_kernels.hpp"
 #include "msg_device.hpp"
+#include "msg_internal.hpp"
 #include "msg_kernels.hpp"
 
 using namespace msg;
@@ -806,6 +807,9 @@ msg_status msg_create(msg_handle* h, int device)
     if (device < 0 || device >= n) return fail(MSG_ERR_ARG, "device %d not present (%d devices)", device, n);
     HIPCHK(hipSetDevice(device));
     read_env();
+    // this device's copy of the no-allocation scratch (noalloc.hip)
+    msg_status st = msg::noalloc_setup(device);
+    if (st != MSG_OK) return st;
     *h = new msg_handle_s{device};
     return MSG_OK;
 }
@@ -838,9 +842,14 @@ msg_status msg_workspace_size(msg_handle, const msg_batch_desc* batch, const msg
     return MSG_OK;
 }
 
-msg_status msg_sample_field(msg_handle h, const msg_field_spec* spec, const msg_batch_desc* batch,
-                            const double* d_xi, double* d_kx, double* d_ky, float* d_kx32, float* d_ky32,
-                            msg_stream stream)
+}  // extern "C"
+
+// msg_sample_field with its device staging (the per-sample tables and, without
+// d_xi, the drawn normals) in `staging` of `cap` bytes, or, when staging is
+// null, in memory allocated on the stream for the call.
+msg_status msg::sample_field_impl(msg_handle h, const msg_field_spec* spec, const msg_batch_desc* batch,
+                                  const double* d_xi, double* d_kx, double* d_ky, float* d_kx32, float* d_ky32,
+                                  msg_stream stream, void* staging, size_t cap)
 {
     if (!h) return fail(MSG_ERR_ARG, "handle is NULL");
     msg_status st = check_batch(batch);
@@ -921,7 +930,15 @@ msg_status msg_sample_field(msg_handle h, const msg_field_spec* spec, const msg_
     const size_t o_ids = o_lists + align_up(sizeof(int32_t) * nlist);
     const size_t o_xi = o_ids + align_up(sizeof(int64_t) * ids.size());
     const size_t bytes = o_xi + (d_xi ? 0 : sizeof(double) * (size_t)BL.S * A.n_terms);
-    HIPCHK(hipMallocAsync(&dmem, bytes, s));
+    if (staging) {
+        if (bytes > cap)
+            return fail(MSG_ERR_WORKSPACE,
+                        "the batch needs %zu bytes of device staging, the no-allocation scratch holds %zu; "
+                        "pass d_xi or split the batch", bytes, cap);
+        dmem = staging;
+    } else {
+        HIPCHK(hipMallocAsync(&dmem, bytes, s));
+    }
     SampleBase* d_bases = (SampleBase*)dmem;
     int32_t* d_lists = (int32_t*)((char*)dmem + o_lists);
     std::vector<int32_t> lists;
@@ -966,9 +983,22 @@ msg_status msg_sample_field(msg_handle h, const msg_field_spec* spec, const msg_
             }
         at += n;
     }
-    HIPCHK(hipFreeAsync(dmem, s));
+    if (!staging) HIPCHK(hipFreeAsync(dmem, s));
     HIPCHK(hipStreamSynchronize(s));   // the host staging vectors die with this call
     return MSG_OK;
+}
+
+int msg::handle_device(msg_handle h) { return h->device; }
+
+msg_status msg::report(msg_status st, const char* text) { return fail(st, "%s", text); }
+
+extern "C" {
+
+msg_status msg_sample_field(msg_handle h, const msg_field_spec* spec, const msg_batch_desc* batch,
+                            const double* d_xi, double* d_kx, double* d_ky, float* d_kx32, float* d_ky32,
+                            msg_stream stream)
+{
+    return msg::sample_field_impl(h, spec, batch, d_xi, d_kx, d_ky, d_kx32, d_ky32, stream, nullptr, 0);
 }
 
 static_assert(MSG_QOI_MEAN == QOI_MEAN && MSG_QOI_POINT == QOI_POINT && MSG_QOI_SUBDOMAIN == QOI_SUBDOMAIN &&

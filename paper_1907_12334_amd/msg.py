@@ -25,7 +25,7 @@ FP64, MIXED = 0, 1
 EXPORTS = ("msg_default_opts", "msg_create", "msg_destroy", "msg_last_error", "msg_layout",
            "msg_workspace_size", "msg_sample_field", "msg_solve_batch", "msg_quantity", "mimc_delta_q",
            "msg_set_profiling", "msg_get_profile", "msg_cycles_workspace_size", "msg_cycles",
-           "msg_matern_workspace_size", "msg_sample_matern")
+           "msg_matern_workspace_size", "msg_sample_matern", "msg_sample_field_noalloc")
 CYCLES_MSG, CYCLES_MG = 0, 1
 QOI_MEAN, QOI_POINT, QOI_SUBDOMAIN, QOI_FLUX = range(4)
 (KERNEL_SMOOTH, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_TAIL, KERNEL_RESIDUAL_NORM, KERNEL_SMOOTH_STAGE,
@@ -98,6 +98,7 @@ def lib():
                                          ctypes.POINTER(ctypes.c_size_t)]
         L.msg_sample_field.argtypes = [vp, ctypes.POINTER(FieldSpecC), ctypes.POINTER(BatchDescC),
                                        vp, vp, vp, vp, vp, vp]
+        L.msg_sample_field_noalloc.argtypes = L.msg_sample_field.argtypes
         L.msg_solve_batch.argtypes = [vp, ctypes.POINTER(BatchDescC), ctypes.POINTER(SolveOptsC),
                                       vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.mimc_delta_q.argtypes = [ctypes.POINTER(BatchDescC), vp, vp, vp]
@@ -112,7 +113,8 @@ def lib():
                                                 ctypes.POINTER(ctypes.c_size_t)]
         L.msg_sample_matern.argtypes = [vp, ctypes.POINTER(MaternSpecC), ctypes.POINTER(BatchDescC),
                                         vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
-        for n in ("msg_create", "msg_layout", "msg_workspace_size", "msg_sample_field", "msg_solve_batch",
+        for n in ("msg_create", "msg_layout", "msg_workspace_size", "msg_sample_field", "msg_sample_field_noalloc",
+                  "msg_solve_batch",
                   "msg_quantity", "mimc_delta_q", "msg_set_profiling", "msg_get_profile",
                   "msg_cycles_workspace_size", "msg_cycles", "msg_matern_workspace_size", "msg_sample_matern"):
             getattr(L, n).restype = ctypes.c_int

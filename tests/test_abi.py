@@ -105,6 +105,8 @@ def test_entry_points_reject_null_handle_without_device_work():
     spec = msg.FieldSpec(type("S", (), {"kind": "cos", "a": [0], "b": [0], "amp": [1.0]})())
     code = L.msg_sample_field(None, ctypes.byref(spec.c_struct), ctypes.byref(b.c_struct), *([None] * 6))
     assert code == msg.MSG_ERR_ARG
+    code = L.msg_sample_field_noalloc(None, ctypes.byref(spec.c_struct), ctypes.byref(b.c_struct), *([None] * 6))
+    assert code == msg.MSG_ERR_ARG
     code = L.mimc_delta_q(ctypes.byref(b.c_struct), None, None, None)
     assert code == msg.MSG_ERR_ARG
 
