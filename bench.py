@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--mixed-workload-samples", type=int, default=None, help="default: the preset's 1024")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-profile", action="store_true", help="no HIP events around launches")
+    ap.add_argument("--overlap", type=int, default=None,
+                    help="overlap mode of the timed steps (msg_solve_opts.overlap; default: the library's choice)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_k_rbgs_se-256x256-s4096.md"))
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run one device copy of this many bytes (calibrates the HBM byte counters)")
@@ -135,6 +137,8 @@ def main():
         opts, tune = AT.autotune(h, w, opts, samples=S, cycles=args.tune_cycles, reps=1, log=log)
         torch.cuda.empty_cache()
         log(f"autotuned plan: {tune['params']}")
+    if args.overlap is not None:
+        opts = dataclasses.replace(opts, overlap=args.overlap)
     bufs = msg.Buffers(batch, opts)
     log(f"device buffers {sum(t.numel() * t.element_size() for t in [bufs.kx, bufs.ky, bufs.u, bufs.ws]) / 1e9:.1f} GB")
 
@@ -210,7 +214,8 @@ def main():
             f"({sm_s:.2f} s of smoother time)")
     else:
         roofline = roofline_of(prof["smooth"], SMOOTH_KERNEL, traffic)
-        roofline["measured_on"] = "the timed steps (concurrent parts share the device)"
+        roofline["measured_on"] = ("the timed steps, every launch on one stream" if args.overlap == 0 else
+                                   "the timed steps (concurrent parts share the device)")
 
     cpu_threads = cpu_share()[0]
     head = take_samples(bufs, w, range(min(S, args.cpu_samples or cpu_threads)))
