@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="no HIP events around launches")
     ap.add_argument("--overlap", type=int, default=None,
                     help="overlap mode of the timed steps (msg_solve_opts.overlap; default: the library's choice)")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_k_rbgs_se-256x256-s4096.md"))
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_k_rbgs_se-256x256-s4096_one_stream.md"))
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run one device copy of this many bytes (calibrates the HBM byte counters)")
     return ap.parse_args()
