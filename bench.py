@@ -457,6 +457,7 @@ def mimc_leg(h, msg, I):
         out[name] = {"tol": tol, "E": r.E, "rmse": r.rmse, "samples": r.N, "batches": r.batches,
                      "seconds": round(r.seconds, 3), "samples_per_s": round(r.N / r.seconds, 1),
                      "learned_rates": [round(x, 3) for x in r.rates],
+                     "fitted_work_rates_gamma": [round(x, 3) for x in r.gamma],
                      "most_drawn_indices": [[list(k), v] for k, v in top]}
         log(f"MSG-MIMC {name}: E={r.E:.6f} rmse={r.rmse:.2e} N={r.N} in {r.seconds:.1f} s")
     # the paper's own field model: Matern (lambda = 1/4, nu = 1/2) with eta and
@@ -469,7 +470,8 @@ def mimc_leg(h, msg, I):
         "field": "Matern lambda=1/4 nu=1/2, eta~U[1/16,1/4], theta~U[-30,30] deg, per-sample circulant embedding",
         "lmax": 6, "tol": 1e-3, "E": r.E, "rmse": r.rmse, "samples": r.N, "batches": r.batches,
         "seconds": round(r.seconds, 3), "samples_per_s": round(r.N / r.seconds, 1),
-        "learned_rates": [round(x, 3) for x in r.rates], "min_embedding_eig_ratio": est.min_eig_ratio,
+        "learned_rates": [round(x, 3) for x in r.rates], "fitted_work_rates_gamma": [round(x, 3) for x in r.gamma],
+        "min_embedding_eig_ratio": est.min_eig_ratio,
         "most_drawn_indices": [[list(k), v] for k, v in top]}
     log(f"MSG-MIMC Q1 Matern prior: E={r.E:.6f} rmse={r.rmse:.2e} N={r.N} in {r.seconds:.1f} s")
     return out

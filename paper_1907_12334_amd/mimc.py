@@ -16,16 +16,27 @@ mimc_delta_q, all on the device; only the per-grid Delta Q return.
 The distribution starts at the paper's GEOMETRIC(log(2)(1 + 4)/2) in each
 direction (beta = 4, gamma = 1) and is re-fitted after every batch from the
 data: per direction, beta_j from a least-squares fit of log2 of the sample
-variance of Delta Q_tau against tau, gamma_j from the work model of one solve
-(cells of the finest grid times the number of grids), and r_j = log(2)
+variance of Delta Q_tau against tau, gamma_j from a least-squares fit of log2
+of the mean measured work of a sample against its index L, and r_j = log(2)
 (beta_j + gamma_j) / 2, as in the paper's derivation of the optimal sample
-sizes.  Each sample keeps the p_tau of the distribution it was drawn from.
-Indices are capped at `lmax` per direction (tail mass exp(-r (lmax+1))).
+sizes (Section 3, rates of assumptions A2 and A3).  A sample's work is what
+its solve did: the cycles run on each grid tau <= L (returned by the library)
+times the cell visits of one W-cycle on that grid's rectangle,
+(tau1+1)(tau2+1) c^2 2^(tau1+tau2); samples of one batch share a ragged
+launch, so their times cannot be taken one by one.  Each sample keeps the
+p_tau of the distribution it was drawn from.  Indices are capped at `lmax`
+per direction (tail mass exp(-r (lmax+1))).
+
+A batch in which any sample's solve failed (cycle cap hit, non-finite
+residual) or any difference is not finite raises MIMCFailure and adds
+nothing to the estimator: dropping the sample would bias the estimate, and
+keeping an unconverged difference would add an error nobody controls.
 
 Random numbers are inputs (inputs.mimc_uniforms): L_j = floor(-log(U_j) / r_j).
 
 Two field models.  The default draws the coefficient from a truncated
-expansion (inputs.FieldSpec, normals from inputs.draw_xi).  With a Matern
+expansion (inputs.FieldSpec), its normals drawn on the device from the
+counter-based streams (estimator seed, sample counter).  With a Matern
 prior (inputs.MaternPrior) every sample is the paper's Section 5 setting: a
 lognormal field with Matern covariance whose anisotropic ratio eta and
 rotation theta are themselves uniform random hyperparameters, drawn per
@@ -66,6 +77,25 @@ def reuse_weights(P: int, Q: int, r: np.ndarray) -> np.ndarray:
     return np.exp(r[0] * t1 + r[1] * t2).ravel()
 
 
+class MIMCFailure(RuntimeError):
+    """A batch contained samples whose solve did not converge."""
+
+    def __init__(self, failed):
+        self.failed = failed          # [(sample id, (L1, L2), status)]
+        super().__init__(f"{len(failed)} sample(s) of the batch not solved to tolerance "
+                         f"(sample id, index, status): {failed[:8]}")
+
+
+def sample_work(c: int, P: int, Q: int, cycles: np.ndarray) -> float:
+    """Cell visits of one solve: cycles run on each grid times the cell
+    visits of one W-cycle on that grid's rectangle."""
+    w = 0.0
+    for a in range(P + 1):
+        for b in range(Q + 1):
+            w += float(cycles[a * (Q + 1) + b]) * (a + 1) * (b + 1) * c * c * 2.0 ** (a + b)
+    return w
+
+
 @dataclasses.dataclass
 class Estimate:
     E: float
@@ -75,6 +105,7 @@ class Estimate:
     batches: int
     seconds: float
     index_counts: Dict[Tuple[int, int], int]
+    gamma: Tuple[float, float] = (1.0, 1.0)     # work growth rates fitted from the solves
 
     @property
     def rmse(self) -> float:
@@ -97,6 +128,8 @@ class MSGMIMC:
         self.ys: List[float] = []
         self.dq: Dict[Tuple[int, int], List[float]] = {}
         self.counts: Dict[Tuple[int, int], int] = {}
+        self.work: Dict[Tuple[int, int], List[float]] = {}
+        self.gamma = np.array([1.0, 1.0])
         self.batches = 0
         self.next_sample_id = 0
 
@@ -114,8 +147,8 @@ class MSGMIMC:
         self.next_sample_id += len(P)
         bufs = msg.Buffers(batch, self.opts)
         if self.prior is None:
-            xi = torch.tensor(I.draw_xi(self.field.n_terms, ids, self.seed), dtype=torch.float64, device="cuda:0")
-            msg.run(self.h, self.field, batch, self.opts, xi, bufs)
+            # normals drawn on the device from the streams (seed, sample id)
+            msg.run(self.h, self.field, batch, self.opts, None, bufs, seed=self.seed, sample_id=ids)
         else:
             pr = self.prior
             eta, theta = self.hyperparameters(len(P), self.batches)
@@ -130,19 +163,27 @@ class MSGMIMC:
         lay = bufs.layout
         dq = bufs.dq.cpu().numpy()
         status = bufs.status.cpu().numpy()
-        return [dq[lay["grid"][k]:lay["grid"][k + 1]] for k in range(len(P))], status
+        cyc = bufs.cycles.cpu().numpy()
+        g = lay["grid"]
+        return ([dq[g[k]:g[k + 1]] for k in range(len(P))], status, [cyc[g[k]:g[k + 1]] for k in range(len(P))],
+                ids)
 
     def add_batch(self, n: int) -> None:
         u = I.mimc_uniforms(n, self.batches, self.seed)
         L = draw_indices(u, self.r, self.lmax)
-        dqs, status = self.solve_batch(L)
-        for (P, Q), d in zip(L, dqs):
+        dqs, status, cycles, ids = self.solve_batch(L)
+        failed = [(int(i), (int(l[0]), int(l[1])), int(st)) for i, l, st, d in zip(ids, L, status, dqs)
+                  if st != msg.SAMPLE_CONVERGED or not np.all(np.isfinite(d))]
+        if failed:
+            raise MIMCFailure(failed)
+        for (P, Q), d, cy in zip(L, dqs, cycles):
             w = reuse_weights(int(P), int(Q), self.r)
             self.ys.append(float(np.dot(d, w)))
             for a in range(P + 1):
                 for b in range(Q + 1):
                     self.dq.setdefault((a, b), []).append(float(d[a * (Q + 1) + b]))
             self.counts[(int(P), int(Q))] = self.counts.get((int(P), int(Q)), 0) + 1
+            self.work.setdefault((int(P), int(Q)), []).append(sample_work(self.c, int(P), int(Q), cy))
         self.batches += 1
         if self.learn:
             self.refit()
@@ -164,10 +205,22 @@ class MSGMIMC:
             return
         coef, *_ = np.linalg.lstsq(A, np.array(vals), rcond=None)
         beta = np.clip(-coef[1:], 0.5, 8.0)
-        # one solve on (L1, L2): (L1+1)(L2+1) grids of up to c^2 2^(L1+L2) cells;
-        # per direction about one doubling per level
-        gamma = np.array([1.0, 1.0])
-        self.r = LOG2 * (beta + gamma) / 2.0
+        self.gamma = self.fit_gamma(min_samples)
+        self.r = LOG2 * (beta + self.gamma) / 2.0
+
+    def fit_gamma(self, min_samples: int = 8) -> np.ndarray:
+        """gamma_j from log2 of the mean measured work of a sample at L
+        against L (least squares), or the previous value while fewer than
+        three independent indices have enough samples."""
+        rows, vals = [], []
+        for (a, b), ws in self.work.items():
+            if len(ws) >= min_samples:
+                rows.append((1.0, a, b))
+                vals.append(math.log2(float(np.mean(ws))))
+        if len(rows) < 3 or np.linalg.matrix_rank(np.array(rows)) < 3:
+            return self.gamma
+        coef, *_ = np.linalg.lstsq(np.array(rows), np.array(vals), rcond=None)
+        return np.clip(coef[1:], 0.5, 4.0)
 
     def estimate(self) -> Tuple[float, float]:
         y = np.asarray(self.ys)
@@ -185,4 +238,4 @@ class MSGMIMC:
             if math.sqrt(v) <= tol or len(self.ys) >= max_samples:
                 break
         return Estimate(e, v, len(self.ys), (float(self.r[0]), float(self.r[1])), self.batches,
-                        time.perf_counter() - t0, dict(self.counts))
+                        time.perf_counter() - t0, dict(self.counts), (float(self.gamma[0]), float(self.gamma[1])))

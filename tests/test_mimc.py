@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import mimc_oracle as MO
+from oracle import normals as NR
 from paper_1907_12334_amd import inputs as I
 from paper_1907_12334_amd import mimc as M
 
@@ -87,11 +88,70 @@ def test_product_host_arithmetic_matches_reference():
     assert abs(M.initial_rates()[0] - math.log(2) * 5 / 2) <= 1e-15
 
 
+class _FakeSolves(M.MSGMIMC):
+    """The estimator's host logic with solves replaced by given per-grid
+    differences, statuses and cycle counts (no GPU)."""
+
+    def __init__(self, make, **kw):
+        super().__init__(handle=None, **kw)
+        self.make = make
+
+    def solve_batch(self, L):
+        ids = np.arange(self.next_sample_id, self.next_sample_id + len(L))
+        self.next_sample_id += len(L)
+        out = [self.make(int(i), int(P), int(Q)) for i, (P, Q) in zip(ids, L)]
+        return [o[0] for o in out], np.array([o[1] for o in out]), [o[2] for o in out], ids
+
+
+@pytest.mark.parametrize("bad", ["maxiter", "nonfinite", "nan_difference"])
+def test_failed_samples_stop_the_estimator(bad):
+    """A sample that hit the cycle cap, went non-finite, or returned a NaN
+    difference raises MIMCFailure naming it, and its batch adds nothing."""
+    def make(i, P, Q):
+        n = (P + 1) * (Q + 1)
+        d, st = np.full(n, 1e-3), 0
+        if i == 5:
+            st = {"maxiter": 1, "nonfinite": 2, "nan_difference": 0}[bad]
+            if bad != "maxiter":
+                d[-1] = np.nan
+        return d, st, np.full(n, 3, dtype=np.int32)
+    est = _FakeSolves(make, lmax=3, r0=np.array([0.7, 0.7]), learn=False)
+    with pytest.raises(M.MIMCFailure) as err:
+        est.add_batch(16)
+    assert err.value.failed[0][0] == 5 and len(est.ys) == 0 and est.batches == 0
+
+
+def test_work_rates_are_fitted_from_the_cycle_counts():
+    """With the same cycle count on every grid, the work of a sample at L is
+    sum_tau (tau1+1)(tau2+1) c^2 2^(tau1+tau2); the fitted gamma follows the
+    growth of that sum (between 1 and 2 per direction over small indices)
+    and changes when the cycle counts grow with the index."""
+    def flat(i, P, Q):
+        n = (P + 1) * (Q + 1)
+        return np.full(n, 2.0 ** -(P + Q)), 0, np.full(n, 4, dtype=np.int32)
+    est = _FakeSolves(flat, lmax=4, r0=np.array([0.4, 0.4]), learn=True)
+    for _ in range(6):
+        est.add_batch(256)
+    g1 = est.gamma.copy()
+    assert np.all(g1 > 1.0) and np.all(g1 < 2.0)
+    assert abs(M.sample_work(4, 1, 0, np.array([2, 3])) - (2 * 16 + 3 * 2 * 32)) < 1e-12
+
+    def growing(i, P, Q):
+        n = (P + 1) * (Q + 1)
+        cyc = np.array([[4 * 2 ** a for b in range(Q + 1)] for a in range(P + 1)], dtype=np.int32).ravel()
+        return np.full(n, 2.0 ** -(P + Q)), 0, cyc
+    est2 = _FakeSolves(growing, lmax=4, r0=np.array([0.4, 0.4]), learn=True)
+    for _ in range(6):
+        est2.add_batch(256)
+    assert est2.gamma[0] > g1[0] + 0.5 and abs(est2.gamma[1] - g1[1]) < 0.3
+
+
 @pytest.mark.gpu
 def test_batched_estimator_matches_reference_on_oracle_solutions():
     """Two batches of 24 samples, fixed rates, indices capped at 3: the GPU
     estimator's E and V equal the reference estimator's on oracle solutions
-    of the same samples (same uniforms, same xi) to the FP64 bar."""
+    of the same samples (same uniforms, the same normal streams) to the
+    FP64 bar."""
     import torch
     from oracle import binding as O
     from paper_1907_12334_amd import msg
@@ -109,7 +169,7 @@ def test_batched_estimator_matches_reference_on_oracle_solutions():
         for x in u:
             L = MO.draw_index((0.6, 0.8), tuple(x))
             L = (min(L[0], 3), min(L[1], 3))
-            xi = I.draw_xi(I.KL10.n_terms, [sid], est.seed)[0]
+            xi = NR.kl_normals(I.KL10.n_terms, [sid], est.seed)[0]
             sid += 1
             kx, ky = O.hierarchy_field(4, L[0], L[1], I.KL10.as_dict(), xi)
             r = O.fmsg_solve(4, L[0], L[1], kx, ky, O.opts(tol=1e-10))
