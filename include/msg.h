@@ -203,8 +203,9 @@ msg_status msg_sample_field_noalloc(msg_handle h, const msg_field_spec *spec, co
 
 /* Full MSG solve of every sample (Section 2, Algorithm MSG F-cycle with the
  * MSG mu-cycle, eq. restriction, eq. interpolation, eq. weight_factors),
- * returning the solution of every grid (p,q) of every sample -- the "free
- * solutions on all coarser grids" of Section 3 -- and Q = mean of u per grid.
+ * returning the solution of every grid (p,q) of every sample -- the coarse
+ * solutions that Section 3 reuses at no extra cost in the multi-index
+ * differences -- and Q = mean of u per grid.
  *   d_kx, d_ky      device FP64 face coefficients (msg_sample_field layout)
  *   d_kx32, d_ky32  device FP32 copies, required for MSG_MIXED, else ignored
  *   d_rhs           NULL for h = 1, else device FP64 right-hand side at the

@@ -25,8 +25,10 @@
  * grid); each is listed with its reason in the design notes:
  *   - grid (p,q) has nx = c*2^p by ny = c*2^q cells, hx = 1/nx, hy = 1/ny;
  *     index (0,0) is the coarsest c-by-c grid, level L = p + q;
- *   - the diffusion coefficient is evaluated directly at every face midpoint
- *     of every grid (direct discretisation on each grid, Section 2);
+ *   - the diffusion coefficient is evaluated at every face midpoint of
+ *     every grid (direct discretisation on each grid, Section 2), or, under
+ *     the face-mean rule, at the finest grid's face midpoints, every coarser
+ *     face taking the mean of those lying on it (oracle_face_mean);
  *   - 5-point cell-centred finite volumes; a wall face carries twice the
  *     face conductance (half-cell distance to the Dirichlet wall, u = 0);
  *   - restriction in one direction averages the two fine cells covered by a
@@ -133,7 +135,7 @@ static void apply_grid(const ogrid *g, const double *u, double *out)
             out[(size_t)j * g->nx + i] = apply_cell(g, u, i, j);
 }
 
-/* r = b - A v (Algorithm MSG mu-cycle, residual step) */
+/* r = b - A v on one grid */
 static void residual_grid(const ogrid *g, const double *b, const double *v, double *r)
 {
     for (int j = 0; j < g->ny; ++j)
@@ -352,42 +354,79 @@ static int coarse_factor(ohier *H) { return dense_factor(grid_at(H, 0, 0), H->ch
 static void coarse_solve(ohier *H) { dense_solve(grid_at(H, 0, 0), H->chol); }
 
 /* ------------------------------------------------------------------------ */
-/* Algorithm MSG mu-cycle (recursive definition)                             */
+/* The mu-cycle (Algorithm 1 of Section 2) as a correction scheme over the   */
+/* levels of the semi-coarsened family: a level is the set of grids (p,q)    */
+/* with p + q = L inside the rectangle, and each operation below acts on all */
+/* of them, one grid at a time.                                              */
 /* ------------------------------------------------------------------------ */
-static void mu_cycle(ohier *H, int L, const oracle_opts *o)
+
+/* the grids of level L, in order of increasing p; returns their count */
+static int level_grids(const ohier *H, int L, int *ps)
 {
-    if (L == 0) { coarse_solve(H); return; }
-    for (int p = 0; p <= H->P; ++p) {                    /* pre-smoothing on level L */
-        int q = L - p;
-        if (!in_rect(H, p, q)) continue;
-        ogrid *g = grid_at(H, p, q);
-        for (int s = 0; s < o->nu1; ++s) rbgs_sweep(g, g->b, g->v);
+    int n = 0;
+    for (int p = 0; p <= H->P; ++p)
+        if (in_rect(H, p, L - p)) ps[n++] = p;
+    return n;
+}
+
+/* nu red-black sweeps on every grid of level L */
+static void smooth_level(ohier *H, int L, int nu)
+{
+    int ps[64], n = level_grids(H, L, ps);
+    for (int k = 0; k < n; ++k) {
+        ogrid *g = grid_at(H, ps[k], L - ps[k]);
+        for (int s = 0; s < nu; ++s) rbgs_sweep(g, g->b, g->v);
     }
-    for (int p = 0; p <= H->P; ++p) {                    /* residuals on level L */
-        int q = L - p;
-        if (!in_rect(H, p, q)) continue;
-        ogrid *g = grid_at(H, p, q);
+}
+
+/* the coarse problems of level L - 1: every grid of level L stores its
+ * defect r = b - A v; every grid of level L - 1 takes the combination of its
+ * parents' defects given by eq. restriction as right-hand side, and zero as
+ * initial guess */
+static void coarse_problems(ohier *H, int L)
+{
+    int ps[64], n = level_grids(H, L, ps);
+    for (int k = 0; k < n; ++k) {
+        ogrid *g = grid_at(H, ps[k], L - ps[k]);
         residual_grid(g, g->b, g->v, g->r);
     }
-    for (int p = 0; p <= H->P; ++p) {                    /* restrict to level L-1, zero iterate */
-        int q = L - 1 - p;
-        if (!in_rect(H, p, q)) continue;
-        ogrid *g = grid_at(H, p, q);
-        restrict_combine(H, p, q, 0);
-        memset(g->v, 0, (size_t)g->nx * g->ny * sizeof(double));
+    n = level_grids(H, L - 1, ps);
+    for (int k = 0; k < n; ++k) {
+        ogrid *h = grid_at(H, ps[k], L - 1 - ps[k]);
+        restrict_combine(H, ps[k], L - 1 - ps[k], 0);
+        memset(h->v, 0, (size_t)h->nx * h->ny * sizeof(double));
     }
-    for (int m = 0; m < o->mu; ++m) mu_cycle(H, L - 1, o);
-    for (int p = 0; p <= H->P; ++p) {                    /* correction and post-smoothing */
-        int q = L - p;
-        if (!in_rect(H, p, q)) continue;
-        ogrid *g = grid_at(H, p, q);
-        size_t n = (size_t)g->nx * g->ny;
-        double *corr = malloc(n * sizeof(double));
-        interp_combine(H, p, q, 0, corr);
-        for (size_t k = 0; k < n; ++k) g->v[k] += o->omega * corr[k];
+}
+
+/* every grid of level L adds omega times the weighted interpolation of its
+ * children's iterates (eq. interpolation with eq. weight_factors) */
+static void correct_level(ohier *H, int L, double omega)
+{
+    int ps[64], n = level_grids(H, L, ps);
+    for (int k = 0; k < n; ++k) {
+        ogrid *g = grid_at(H, ps[k], L - ps[k]);
+        size_t cells = (size_t)g->nx * g->ny;
+        double *corr = malloc(cells * sizeof(double));
+        interp_combine(H, ps[k], L - ps[k], 0, corr);
+        for (size_t t = 0; t < cells; ++t) g->v[t] += omega * corr[t];
         free(corr);
-        for (int s = 0; s < o->nu2; ++s) rbgs_sweep(g, g->b, g->v);
     }
+}
+
+/* one mu-cycle on level L: the coarsest level is solved directly; above it,
+ * pre-smoothing, mu cycles on the coarse problems, correction and
+ * post-smoothing */
+static void mu_cycle(ohier *H, int L, const oracle_opts *o)
+{
+    if (L == 0) {
+        coarse_solve(H);
+        return;
+    }
+    smooth_level(H, L, o->nu1);
+    coarse_problems(H, L);
+    for (int m = 0; m < o->mu; ++m) mu_cycle(H, L - 1, o);
+    correct_level(H, L, o->omega);
+    smooth_level(H, L, o->nu2);
 }
 
 static double norm2(const double *x, size_t n)
