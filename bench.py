@@ -57,7 +57,11 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="library default plan instead of the autotuner's")
     ap.add_argument("--tune-cycles", type=int, default=1, help="cycles per stage in each autotuner trial")
     ap.add_argument("--mixed-workload-samples", type=int, default=None, help="default: the preset's 1024")
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=20000,
+                    help="window of the 200000-request trace replayed per offered rate")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[5000.0, 2000.0, 1000.0, 500.0])
+    ap.add_argument("--serve-oracle-requests", type=int, default=12,
+                    help="served answers compared with the oracle in the CPU leg")
     ap.add_argument("--no-profile", action="store_true", help="no HIP events around launches")
     ap.add_argument("--overlap", type=int, default=None,
                     help="overlap mode of the timed steps (msg_solve_opts.overlap; default: the library's choice)")
@@ -250,8 +254,9 @@ def main():
     if not args.skip_ragged:
         extra["ragged"] = ragged_leg(h, msg, I, torch)
 
+    served = None
     if not args.skip_serve:
-        extra["serving"] = serve_leg(msg, I, args)
+        extra["serving"], served = serve_leg(msg, I, args)
 
     if not args.skip_mimc:
         extra["msg_mimc"] = mimc_leg(h, msg, I)
@@ -261,7 +266,7 @@ def main():
 
     cpu = None
     if not args.skip_cpu:
-        cpu = cpu_baseline(w, head, I.config(4), mixed_head)
+        cpu = cpu_baseline(w, head, I.config(4), mixed_head, served)
         log(f"cpu oracle: {cpu}")
 
     out = {
@@ -515,25 +520,46 @@ def factors_leg(h):
 
 
 def serve_leg(msg, I, args):
-    """Request loop: the Poisson trace at its rate (bounded to the first
-    requests) and the same requests at a rate below capacity."""
+    """Request loop on a window of the 200 000-request Poisson trace (5000/s):
+    its first `serve_requests` requests at the trace's rate, and the same
+    requests at lower offered rates (arrival times scaled), to find the
+    sustained capacity and the load at which latency degrades.  Returns
+    (summary, served answers of small requests for the oracle check of the
+    CPU leg)."""
     from paper_1907_12334_amd.serve import Engine, replay, summarize
     opts = msg.SolveOpts(tol=1e-8, max_cycles=200, precision=msg.MIXED)
-    out = {"field": "KL-10", "c": 4, "precision": "mixed, refined to 1e-8",
-           "admission": "80% of free HBM, 3 small-request workers + 1 large-request worker"}
-    for name, n, rate in (("offered_5000_per_s", args.serve_requests, 5000.0),
-                          ("offered_400_per_s", max(1, args.serve_requests // 2), 400.0)):
-        t, P, Q, ids = I.request_trace(n, rate)
+    t, P, Q, ids = I.request_trace(200000, 5000.0)
+    n = min(args.serve_requests, len(t))
+    t, P, Q, ids = t[:n] - t[0], P[:n], Q[:n], ids[:n]
+    out = {"field": "KL-10, normals drawn on the device per request", "c": 4,
+           "precision": "mixed, refined to 1e-8", "trace": f"first {n} of 200000 requests, Poisson at 5000/s",
+           "admission": "80% of free HBM in one arena per worker, 3 small-request workers + 1 large-request worker",
+           "runs": {}}
+    kept = []
+    for rate in args.serve_rates:
         eng = Engine(I.KL10, 4, opts, workers=3, big_workers=1)
         try:
-            reqs = replay(eng, t, P, Q, ids, timeout=600)
+            reqs = replay(eng, t * (5000.0 / rate), P, Q, ids, timeout=900)
         finally:
             eng.close()
         s = summarize(reqs, rate)
         s["max_batches_in_flight"] = eng.max_inflight
-        out[name] = s
-        log(f"serving {name}: {s}")
-    return out
+        s["batches"] = len(eng.batches)
+        out["runs"][f"{rate:g}_per_s"] = s
+        log(f"serving at {rate:g}/s: {s}")
+        if rate == 5000.0:
+            kept = [{"sample": r.sample_id, "P": r.P, "Q": r.Q, "q": r.q, "dq": r.dq, "status": r.status}
+                    for r in reqs if r.P + r.Q <= 6][:args.serve_oracle_requests]
+        del eng
+        import torch
+        torch.cuda.empty_cache()
+    sat = [float(k.split("_")[0]) for k, v in out["runs"].items() if v.get("saturated")]
+    out["capacity_samples_per_s"] = max((v["samples_per_s"] for v in out["runs"].values() if v.get("saturated")),
+                                        default=None)
+    out["lowest_saturating_offered_per_s"] = min(sat) if sat else None
+    out["highest_kept_up_offered_per_s"] = max((float(k.split("_")[0]) for k, v in out["runs"].items()
+                                                if not v.get("saturated")), default=None)
+    return out, kept
 
 
 def cpu_share():
@@ -546,7 +572,7 @@ def cpu_share():
     return threads, aff
 
 
-def cpu_baseline(w, head, w4=None, mixed_head=None):
+def cpu_baseline(w, head, w4=None, mixed_head=None, served=None):
     """The oracle (field + full-MSG solve + differences) on host cores, one
     sample per thread, on the first samples of the same workload (as many as
     threads): its rate is the CPU baseline.  Its results are also compared
@@ -599,6 +625,26 @@ def cpu_baseline(w, head, w4=None, mixed_head=None):
         out["gpu_mixed_vs_fp64_oracle_1024x64"] = {
             "note": "mixed precision refined to 1e-8 on the GPU against the FP64 oracle run to 1e-10",
             "samples": len(per), "max_err": worst4, "per_sample": per}
+    if served:
+        from oracle import normals as N
+        from paper_1907_12334_amd import inputs as I
+        seed = I.BASE_SEED + 5
+
+        def ora(r):
+            xi = N.kl_normals(I.KL10.n_terms, [r["sample"]], seed)[0]
+            kx, ky = O.hierarchy_field(4, r["P"], r["Q"], I.KL10.as_dict(), xi)
+            res = O.fmsg_solve(4, r["P"], r["Q"], kx, ky, O.opts(tol=1e-10, max_cycles=200))
+            return res["status"], res["q"], O.delta_q(r["P"], r["Q"], res["q"])
+        with ThreadPoolExecutor(threads) as ex:
+            res5 = list(ex.map(ora, served))
+        eq = edq = 0.0
+        for r, (st, q, dq) in zip(served, res5):
+            eq = max(eq, float(np.max(np.abs(r["q"] - q) / np.abs(q))))
+            edq = max(edq, float(np.max(np.abs(r["dq"] - dq)) / np.max(np.abs(q))))
+        out["served_vs_fp64_oracle"] = {
+            "note": "requests served at 5000/s (mixed precision, refined to 1e-8) against the FP64 oracle at 1e-10",
+            "requests": len(served), "all_converged": all(r["status"] == 0 for r in served) and
+            all(st == 0 for st, _, _ in res5), "max_err": {"Q": eq, "dQ_over_max_Q": edq}}
     return out
 
 

@@ -140,7 +140,12 @@ typedef struct {
     /* Plan tuning (0 = the library's defaults; see paper_1907_12334_amd/autotune.py).
      * None changes results beyond rounding; all change the workspace size. */
     int32_t tail_budget;        /* LDS bytes per problem of the on-chip cycle tail (sets its
-                                   depth): 0 or 1024..65536; default 20480 */
+                                   depth): 0 or 1024..153600; default 20480, set for
+                                   thousands of resident problems.  Above 40960 the tail runs
+                                   on four wavefronts, and rectangles within the budget are
+                                   solved whole in one kernel: for batches of few large
+                                   samples, where each level kept on chip halves the host
+                                   level visits of a cycle */
     int32_t tile_width;         /* smoother tile width cap: 0 or a power of two 4..256; default 64 */
     int32_t tile_cells;         /* smoother tile cell cap: 0 or 64..4096; default 1024 */
     int32_t tile_lds;           /* smoother tile LDS elements with halo: 0 or 256..8192;

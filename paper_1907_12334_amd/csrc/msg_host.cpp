@@ -85,8 +85,8 @@ msg_status check_opts(const msg_solve_opts* o)
     if (o->tail_levels < -1 || o->tail_levels > 8) return fail(MSG_ERR_ARG, "tail_levels must be -1..8");
     if (o->handoff < -1) return fail(MSG_ERR_ARG, "handoff must be >= -1");
     if (o->overlap < -1 || o->overlap > 2) return fail(MSG_ERR_ARG, "overlap must be -1..2");
-    if (o->tail_budget != 0 && (o->tail_budget < 1024 || o->tail_budget > 65536))
-        return fail(MSG_ERR_ARG, "tail_budget must be 0 or 1024..65536 bytes");
+    if (o->tail_budget != 0 && (o->tail_budget < 1024 || o->tail_budget > 153600))
+        return fail(MSG_ERR_ARG, "tail_budget must be 0 or 1024..153600 bytes");
     if (o->tile_width != 0 && (o->tile_width < 4 || o->tile_width > 256 || (o->tile_width & (o->tile_width - 1))))
         return fail(MSG_ERR_ARG, "tile_width must be 0 or a power of two in 4..256");
     if (o->tile_cells != 0 && (o->tile_cells < 64 || o->tile_cells > 4096))
@@ -143,6 +143,8 @@ int g_solve_lds = 65536;     // LDS budget under which a class is solved entirel
 bool g_tail_table = true;    // tails smooth from a red-black slot table (false: decode every slot)
 bool g_fuse_restrict = true; // pre-smoothing passes of nu1 = 2 also restrict their residual
 bool g_debug_stages = false; // per-level timing on stderr
+constexpr size_t kWideTailLds = (size_t)40 * 1024;      // tails above this run on four wavefronts
+constexpr int kMaxGroups = kMaxIndex + 1;               // lockstep groups of one stage (at most its classes)
 
 // LDS elements of a smoother tile tw x th with halo H: its iterate with H
 // cells of halo towards a neighbouring tile and one wall cell where the tile
@@ -199,6 +201,7 @@ struct ClassPlan {
     int tail_top = 0;
     KTail tail;
     size_t tail_lds = 0;
+    int tail_threads = 64;         // workgroup of the cycle tail (one wavefront, or four for large tails)
     bool solve_in_tail = false;    // the whole adaptive level runs in one kernel (FP64)
     KTail tail64;
     size_t tail64_lds = 0;
@@ -420,20 +423,31 @@ ClassPlan plan_class(int c, int pc, int qc, std::vector<int> samples, const msg_
             off += grid_cells(c, a, b);
         }
     C.stride = off;
+    // The default LDS budget per problem is set for thousands of resident
+    // problems.  A caller solving few large problems (the request loop's
+    // large-request lane) passes a larger one: the tail then holds more
+    // levels (each level on chip halves the host level visits of a cycle),
+    // runs on four wavefronts, and rectangles up to that budget are solved
+    // whole in one kernel.  The plan depends on the options and the class
+    // rectangle only, never on how many problems share the class, so a
+    // sample's result does not depend on its batch.
+    const size_t tail_budget = (size_t)tu.tail_budget;
+    const size_t solve_budget = std::max((size_t)g_solve_lds, tail_budget);
     // classes whose whole rectangle fits in LDS run their adaptive
     // cycles inside one FP64 kernel; the others cycle on the host
     // down to a tail of levels 0..tail_top < L
     const size_t b64 = L < kMaxTailLevels ? tail_layout<double>(c, pc, qc, L, C.goff, C.tail64) : 0;
     C.tail64_lds = b64;
     if (o.tail_levels >= 0) C.solve_in_tail = L <= o.tail_levels && b64 > 0;
-    else C.solve_in_tail = b64 > 0 && b64 <= (size_t)g_solve_lds;
+    else C.solve_in_tail = b64 > 0 && b64 <= solve_budget;
     if (L == 0) C.solve_in_tail = b64 > 0;
     if (host_cycles) C.solve_in_tail = false;
     const int mcap = std::max(0, L - 1);
-    C.tail_top = o.precision == MSG_MIXED ? choose_tail<float>(c, pc, qc, mcap, o.tail_levels, tu.tail_budget, C.goff)
-                                           : choose_tail<double>(c, pc, qc, mcap, o.tail_levels, tu.tail_budget, C.goff);
+    C.tail_top = o.precision == MSG_MIXED ? choose_tail<float>(c, pc, qc, mcap, o.tail_levels, tail_budget, C.goff)
+                                           : choose_tail<double>(c, pc, qc, mcap, o.tail_levels, tail_budget, C.goff);
     C.tail_lds = o.precision == MSG_MIXED ? tail_layout<float>(c, pc, qc, C.tail_top, C.goff, C.tail)
                                            : tail_layout<double>(c, pc, qc, C.tail_top, C.goff, C.tail);
+    C.tail_threads = C.tail_lds > kWideTailLds ? 256 : 64;
     C.top1d = level_1d(c, pc, qc, L, C.goff, 1, qc);
     C.rb.resize(L + 1);
     C.rbc.resize(L + 1);
@@ -491,6 +505,7 @@ std::vector<StagePlan> make_plans(const BatchLayout& BL, const msg_solve_opts& o
 
 // ---------------------------------------------------------------- workspace
 struct Ws {
+    size_t gcls;
     size_t bpyr, chol, a64v, a64v2, a64b, a32v, a32v2, a32b, part, active, pcycles, dead, nactive, sbase, gbase, rbase, probs,
         pyrprobs, tails, cls, tpack, slots, total;
 };
@@ -529,6 +544,7 @@ Ws ws_layout(const BatchLayout& BL, const std::vector<StagePlan>& plans, bool mi
     w.pyrprobs = take(sizeof(KProb) * BL.S);
     w.tails = take(sizeof(KTail) * 2 * (kMaxIndex + 1));
     w.cls = take(sizeof(int32_t) * std::max<int64_t>(probs, 1));
+    w.gcls = take(sizeof(int32_t) * kMaxGroups * std::max<int64_t>(probs, 1));
     w.tpack = take((mixed ? sizeof(float) : sizeof(double)) * std::max<int64_t>(tpack, 1));
     w.slots = take(sizeof(int4) * std::max<int64_t>(slots, 1));
     w.total = off;
@@ -1202,51 +1218,103 @@ struct Span {
 
 
 
-template <typename T>
-msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, Iter<T>& it, T* B, const T* KX,
-                    const T* KY)
+// One class of a lockstep group: its plan, the problems [k0, k0 + kn) of the
+// class it cycles, and how many of them still cycle (byte counts).
+struct Member {
+    const ClassPlan* C;
+    Span sp;
+    int64_t kact;
+};
+
+// Classes of one F-cycle stage that share the tail level and the tail's
+// workgroup size issue the same sequence of passes in their W-cycles, so
+// they recurse in lockstep: each pass is launched per class, but every visit
+// of the on-chip tail is one launch for all of them (block b is stage problem
+// gfirst + b, with its class's tail descriptor from the table gcls), so that
+// the latency-bound tails of the classes run side by side on the chip.  The
+// buffer states of their iterates move together (one Iter for the group).
+// gcls null: a single class, launched as before.
+struct Group {
+    std::vector<Member> m;
+    int tail_top = 0, tail_threads = 64;
+    size_t tail_lds = 0;
+    const int32_t* gcls = nullptr;
+    int gfirst = 0, gend = 0;
+};
+
+Group single_group(const ClassPlan& C, const Span& sp, int64_t kact)
 {
-    const KProb* pr = X.probs + C.first + sp.k0;
-    const int32_t* act = X.active + C.first + sp.k0;
+    Group G;
+    G.m.push_back(Member{&C, sp, kact});
+    G.tail_top = C.tail_top;
+    G.tail_threads = C.tail_threads;
+    G.tail_lds = C.tail_lds;
+    return G;
+}
+
+template <typename T>
+msg_status mu_cycle(const Ctx& X, const Group& G, int lev, Iter<T>& it, T* B, const T* KX, const T* KY)
+{
     msg_status st;
-    auto tail = [&](int count, int combine) {
-        T* V = it.now(C.tail_top);
-        const T* pack = C.tpack >= 0 ? (const T*)X.tpack + C.tpack + (int64_t)sp.k0 * C.tail.nstat : nullptr;
-        const double bytes = tail_bytes(C.tail, sizeof(T)) * (double)X.kact;
-        return timed(X, MSG_KERNEL_TAIL, bytes, [&] {
-            return chunked(C.top1d, sp.kn, [&](int k0, int kn) {
-                return launch_tail<T>(X.tails, nullptr, 2 * C.ci, 64, C.tail_lds, kn, pr + k0, act + k0, X.c, X.o->mu,
-                                      X.o->nu1, X.o->nu2, (T)X.o->omega, count, combine, V, B, KX, KY,
-                                      pack ? pack + (int64_t)k0 * C.tail.nstat : nullptr, X.chol, TailSolve{}, X.s);
+    const int M = G.tail_top, Lstage = G.m[0].C->L;
+    auto tail = [&](int count, int combine) -> msg_status {
+        T* V = it.now(M);
+        double bytes = 0.0;
+        for (const Member& e : G.m) bytes += tail_bytes(e.C->tail, sizeof(T)) * (double)e.kact;
+        if (!G.gcls) {
+            const Member& e = G.m[0];
+            const ClassPlan& C = *e.C;
+            const T* pack = C.tpack >= 0 ? (const T*)X.tpack : nullptr;
+            return timed(X, MSG_KERNEL_TAIL, bytes, [&] {
+                return chunked(C.top1d, e.sp.kn, [&](int k0, int kn) {
+                    const int kb = C.first + e.sp.k0 + k0;
+                    return launch_tail<T>(X.tails, nullptr, 2 * C.ci, kb, C.tail_threads, C.tail_lds, kn,
+                                          X.probs + kb, X.active + kb, X.c, X.o->mu, X.o->nu1, X.o->nu2,
+                                          (T)X.o->omega, count, combine, V, B, KX, KY, pack, X.chol, TailSolve{},
+                                          X.s);
+                });
             });
+        }
+        return timed(X, MSG_KERNEL_TAIL, bytes, [&]() -> msg_status {
+            hipError_t e = launch_tail<T>(X.tails, G.gcls + G.gfirst, 0, G.gfirst, G.tail_threads, G.tail_lds,
+                                          G.gend - G.gfirst, X.probs + G.gfirst, X.active + G.gfirst, X.c, X.o->mu,
+                                          X.o->nu1, X.o->nu2, (T)X.o->omega, count, combine, V, B, KX, KY,
+                                          (const T*)X.tpack, X.chol, TailSolve{}, X.s);
+            if (e != hipSuccess) return fail(MSG_ERR_HIP, "tail launch: %s", hipGetErrorString(e));
+            return MSG_OK;
         });
     };
-    if (lev <= C.tail_top) return tail(1, 0);
+    if (lev <= M) return tail(1, 0);
     // sweeps red-black sweeps on level lev, two fused per pass; with `corr`
     // the first pass also applies the coarse-grid correction (eq. interpolation).
     // ns = 0 is a copy pass (no sweep).
     int flips = 0;
     int combine_in_tail = 0;        // the restriction into the tail's top level left two halves to average
     auto pass = [&](int ns, bool corr) -> msg_status {
-        const KLevel& L = corr ? C.rbc[lev] : C.rb[lev];
         const T* vin = it.now(lev);
         T* vout = it.v[1 - it.cur[lev]];
         const T* vc = corr ? it.now(lev - 1) : nullptr;
-        // smoother bytes (a copy: read and write the iterate), plus the coarse
-        // iterates the correction reads
-        const double bytes = ns == 0 ? level_bytes<T>(L, 4, X.kact)
-                                     : level_bytes<T>(L, 0, X.kact) + (corr ? level_bytes<T>(L, 3, X.kact) : 0.0);
-        const double model = model_bytes<T>(L, ns == 0 ? 2.0 : 5.0 * ns + (corr ? 5.0 : 0.0), X.kact);
-        msg_status r = timed(
-            X, MSG_KERNEL_SMOOTH, bytes,
-            [&] {
-                return chunked(L, sp.kn, [&](int k0, int kn) {
-                    return launch_rbgs<T>(ns, L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, vc,
-                                          (T)X.o->omega, X.s);
-                });
-            },
-            lev == C.L ? MSG_KERNEL_SMOOTH_STAGE : -1, false, model);
-        if (r != MSG_OK) return r;
+        for (const Member& e : G.m) {
+            const ClassPlan& C = *e.C;
+            const KLevel& L = corr ? C.rbc[lev] : C.rb[lev];
+            const KProb* pr = X.probs + C.first + e.sp.k0;
+            const int32_t* act = X.active + C.first + e.sp.k0;
+            // smoother bytes (a copy: read and write the iterate), plus the coarse
+            // iterates the correction reads
+            const double bytes = ns == 0 ? level_bytes<T>(L, 4, e.kact)
+                                         : level_bytes<T>(L, 0, e.kact) + (corr ? level_bytes<T>(L, 3, e.kact) : 0.0);
+            const double model = model_bytes<T>(L, ns == 0 ? 2.0 : 5.0 * ns + (corr ? 5.0 : 0.0), e.kact);
+            msg_status r = timed(
+                X, MSG_KERNEL_SMOOTH, bytes,
+                [&] {
+                    return chunked(L, e.sp.kn, [&](int k0, int kn) {
+                        return launch_rbgs<T>(ns, L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, vc,
+                                              (T)X.o->omega, X.s);
+                    });
+                },
+                lev == Lstage ? MSG_KERNEL_SMOOTH_STAGE : -1, false, model);
+            if (r != MSG_OK) return r;
+        }
         it.cur[lev] ^= 1;
         ++flips;
         return MSG_OK;
@@ -1266,82 +1334,101 @@ msg_status mu_cycle(const Ctx& X, const ClassPlan& C, const Span& sp, int lev, I
         // pre-smoothing and the restriction of its residual in one pass, then
         // the coarse grids with two parents combine their halves
         {
-            const KLevel& L = C.rbr[lev];
             const T* vin = it.now(lev);
             T* vout = it.v[1 - it.cur[lev]];
             T* vc = it.v[0];
-            st = timed(
-                X, MSG_KERNEL_SMOOTH, level_bytes<T>(L, 0, X.kact) + level_bytes<T>(L, 5, X.kact),
-                [&] {
-                    return chunked(L, sp.kn, [&](int k0, int kn) {
-                        return launch_rbgs_restrict<T>(L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, vc, X.s);
-                    });
-                },
-                lev == C.L ? MSG_KERNEL_SMOOTH_STAGE : -1, false, model_bytes<T>(L, 15.0, X.kact));
-            if (st != MSG_OK) return st;
+            for (const Member& e : G.m) {
+                const ClassPlan& C = *e.C;
+                const KLevel& L = C.rbr[lev];
+                const KProb* pr = X.probs + C.first + e.sp.k0;
+                const int32_t* act = X.active + C.first + e.sp.k0;
+                st = timed(
+                    X, MSG_KERNEL_SMOOTH, level_bytes<T>(L, 0, e.kact) + level_bytes<T>(L, 5, e.kact),
+                    [&] {
+                        return chunked(L, e.sp.kn, [&](int k0, int kn) {
+                            return launch_rbgs_restrict<T>(L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, vc,
+                                                           X.s);
+                        });
+                    },
+                    lev == Lstage ? MSG_KERNEL_SMOOTH_STAGE : -1, false, model_bytes<T>(L, 15.0, e.kact));
+                if (st != MSG_OK) return st;
+            }
             it.cur[lev] ^= 1;
             ++flips;
         }
         // into the tail's top level, the tail's load averages the two
         // halves instead
-        if (lev - 1 <= C.tail_top) {
+        if (lev - 1 <= M) {
             combine_in_tail = 1;
             it.cur[lev - 1] = 0;
         } else {
-            const KLevel& R = C.res[lev];
             T* vc = it.v[0];
-            st = timed(
-                X, MSG_KERNEL_RESTRICT, level_bytes<T>(R, 6, X.kact),
-                [&] {
-                    return chunked(R, sp.kn, [&](int k0, int kn) {
-                        return launch_restrict_combine<T>(R, kn, pr + k0, act + k0, vc, B, X.s);
-                    });
-                },
-                lev == C.L ? MSG_KERNEL_RESTRICT_STAGE : -1);
-            if (st != MSG_OK) return st;
+            for (const Member& e : G.m) {
+                const ClassPlan& C = *e.C;
+                const KLevel& R = C.res[lev];
+                const KProb* pr = X.probs + C.first + e.sp.k0;
+                const int32_t* act = X.active + C.first + e.sp.k0;
+                st = timed(
+                    X, MSG_KERNEL_RESTRICT, level_bytes<T>(R, 6, e.kact),
+                    [&] {
+                        return chunked(R, e.sp.kn, [&](int k0, int kn) {
+                            return launch_restrict_combine<T>(R, kn, pr + k0, act + k0, vc, B, X.s);
+                        });
+                    },
+                    lev == Lstage ? MSG_KERNEL_RESTRICT_STAGE : -1);
+                if (st != MSG_OK) return st;
+            }
             it.cur[lev - 1] = 0;
         }
     } else {
-    if ((st = smooth(X.o->nu1, false)) != MSG_OK) return st;
-    {
-        const KLevel& L = C.res[lev];
+        if ((st = smooth(X.o->nu1, false)) != MSG_OK) return st;
         const T* vf = it.now(lev);
         T* vc = it.v[0];
-        st = timed(
-            X, MSG_KERNEL_RESTRICT, level_bytes<T>(L, 1, X.kact),
-            [&] {
-                return chunked(L, sp.kn, [&](int k0, int kn) {
-                    return launch_restrict<T>(false, L, kn, pr + k0, act + k0, X.c, vf, vc, B, KX, KY, X.s);
-                });
-            },
-            lev == C.L ? MSG_KERNEL_RESTRICT_STAGE : -1);
-        if (st != MSG_OK) return st;
+        for (const Member& e : G.m) {
+            const ClassPlan& C = *e.C;
+            const KLevel& L = C.res[lev];
+            const KProb* pr = X.probs + C.first + e.sp.k0;
+            const int32_t* act = X.active + C.first + e.sp.k0;
+            st = timed(
+                X, MSG_KERNEL_RESTRICT, level_bytes<T>(L, 1, e.kact),
+                [&] {
+                    return chunked(L, e.sp.kn, [&](int k0, int kn) {
+                        return launch_restrict<T>(false, L, kn, pr + k0, act + k0, X.c, vf, vc, B, KX, KY, X.s);
+                    });
+                },
+                lev == Lstage ? MSG_KERNEL_RESTRICT_STAGE : -1);
+            if (st != MSG_OK) return st;
+        }
         it.cur[lev - 1] = 0;
     }
-    }
-    if (lev - 1 <= C.tail_top) {
+    if (lev - 1 <= M) {
         if ((st = tail(X.o->mu, combine_in_tail)) != MSG_OK) return st;
     } else {
         for (int m = 0; m < X.o->mu; ++m)
-            if ((st = mu_cycle<T>(X, C, sp, lev - 1, it, B, KX, KY)) != MSG_OK) return st;
+            if ((st = mu_cycle<T>(X, G, lev - 1, it, B, KX, KY)) != MSG_OK) return st;
     }
     if (X.o->nu2 > 0) {
         if ((st = smooth(X.o->nu2, true)) != MSG_OK) return st;      // correction fused into the first pass
     } else {
-        const KLevel& L = C.pro[lev];
         const T* vc = it.now(lev - 1);
         T* vf = it.now(lev);
-        st = timed(X, MSG_KERNEL_PROLONG, level_bytes<T>(L, 2, X.kact), [&] {
-            return chunked(L, sp.kn, [&](int k0, int kn) {
-                return launch_prolong<T>(L, kn, pr + k0, act + k0, X.c, (T)X.o->omega, vc, vf, KX, KY, X.s);
+        for (const Member& e : G.m) {
+            const ClassPlan& C = *e.C;
+            const KLevel& L = C.pro[lev];
+            const KProb* pr = X.probs + C.first + e.sp.k0;
+            const int32_t* act = X.active + C.first + e.sp.k0;
+            st = timed(X, MSG_KERNEL_PROLONG, level_bytes<T>(L, 2, e.kact), [&] {
+                return chunked(L, e.sp.kn, [&](int k0, int kn) {
+                    return launch_prolong<T>(L, kn, pr + k0, act + k0, X.c, (T)X.o->omega, vc, vf, KX, KY, X.s);
+                });
             });
-        });
-        if (st != MSG_OK) return st;
+            if (st != MSG_OK) return st;
+        }
     }
     // The stage's own level keeps its iterate across cycles, and problems that
     // have stopped are skipped by every pass: an odd number of buffer swaps
     // per cycle would leave theirs behind, so a copy pass evens it out.
-    if (lev == C.L && (flips & 1)) return pass(0, false);
+    if (lev == Lstage && (flips & 1)) return pass(0, false);
     return MSG_OK;
 }
 
@@ -1468,6 +1555,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
     std::vector<KProb> probs;
     std::vector<KTail> tails;
     std::vector<int32_t> cls;
+    std::vector<std::vector<int32_t>> gcls_host;     // per lockstep group: class descriptor per stage problem
     X.tails = (const KTail*)(ws + W.tails);
     X.tpack = ws + W.tpack;
     for (const StagePlan& SP : plans) {
@@ -1496,6 +1584,8 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
             int64_t so = 0;
             for (const ClassPlan& C : SP.classes) {
                 tails[2 * C.ci] = C.tail;
+                tails[2 * C.ci].first = C.first;
+                tails[2 * C.ci].pack_off = std::max<int64_t>(C.tpack, 0);
                 tails[2 * C.ci + 1] = C.tail64;
                 for (int t = 0; t < 2; ++t) {
                     KTail& TL = tails[2 * C.ci + t];
@@ -1563,7 +1653,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                     for (int64_t k0 = 0; k0 < SP.K; k0 += per) {
                         const int kn = (int)std::min<int64_t>(per, SP.K - k0);
                         TailSolve ad{opts->tol, opts->max_cycles, SP.L, pcycles + k0, d_status, dead};
-                        hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls) + k0, 0, threads, lds,
+                        hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls) + k0, 0, (int)k0, threads, lds,
                                                            kn, X.probs + k0, X.active + k0, c, opts->mu, opts->nu1,
                                                            opts->nu2, opts->omega, -1, 0, it64.v[0], a64b, d_kx, d_ky,
                                                            nullptr, chol, ad, s);
@@ -1608,7 +1698,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                     HIPCHK(hipMemcpyAsync(ws + W.cls, cls.data(), sizeof(int32_t) * SP.K, hipMemcpyHostToDevice, s));
                     TailSolve ad{opts->tol, opts->max_cycles, SP.L, pcycles, d_status, dead};
                     st = timed(X, MSG_KERNEL_TAIL, 0.0, [&]() -> msg_status {
-                        hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls), 0,
+                        hipError_t e = launch_tail<double>(X.tails, (const int32_t*)(ws + W.cls), 0, 0,
                                                            lds >= 24576 ? 256 : 64, lds, SP.K, X.probs, X.active, c,
                                                            opts->mu, opts->nu1, opts->nu2, opts->omega, -1, 0,
                                                            it64.v[buf], a64b, d_kx, d_ky, nullptr, chol, ad, s);
@@ -1658,6 +1748,75 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
             // the classes then run on the lane's own stream, forked from and
             // joined back to the part's stream.
             const bool fork = ov > 0 || use_graphs;
+            int rr = 0;
+            if (!use_graphs) {
+                // the classes still cycling, in lockstep groups of equal tail
+                // level and tail workgroup: one tail launch per group visit
+                std::vector<Group> groups;
+                std::vector<std::vector<int>> gci;
+                for (int ci = 0; ci < ncls; ++ci) {
+                    const ClassPlan& C = SP.classes[ci];
+                    if (host_active[ci] == 0) continue;
+                    size_t g = 0;
+                    while (g < groups.size() &&
+                           (groups[g].tail_top != C.tail_top || groups[g].tail_threads != C.tail_threads))
+                        ++g;
+                    if (g == groups.size()) {
+                        groups.push_back(single_group(C, Span{0, C.K}, host_active[ci]));
+                        gci.push_back({ci});
+                        continue;
+                    }
+                    groups[g].m.push_back(Member{&C, Span{0, C.K}, host_active[ci]});
+                    groups[g].tail_lds = std::max(groups[g].tail_lds, C.tail_lds);
+                    gci[g].push_back(ci);
+                }
+                gcls_host.resize(groups.size());
+                for (size_t g = 0; g < groups.size(); ++g) {
+                    Group& G = groups[g];
+                    if (G.m.size() < 2) continue;
+                    G.gfirst = INT_MAX;
+                    G.gend = 0;
+                    gcls_host[g].assign(SP.K, -1);
+                    for (const Member& e : G.m) {
+                        G.gfirst = std::min(G.gfirst, e.C->first);
+                        G.gend = std::max(G.gend, e.C->first + e.C->K);
+                        for (int k = 0; k < e.C->K; ++k) gcls_host[g][e.C->first + k] = 2 * e.C->ci;
+                    }
+                    int32_t* d = (int32_t*)(ws + W.gcls) + (int64_t)g * SP.K;
+                    HIPCHK(hipMemcpyAsync(d, gcls_host[g].data(), sizeof(int32_t) * SP.K, hipMemcpyHostToDevice, s));
+                    G.gcls = d;
+                }
+                if (fork) {
+                    HIPCHK(hipEventRecord(ln.fork, s));
+                    for (int k = 0; k < kSideStreams; ++k) HIPCHK(hipStreamWaitEvent(ln.side[k], ln.fork, 0));
+                }
+                for (size_t g = 0; g < groups.size(); ++g) {
+                    const Group& G = groups[g];
+                    Ctx Y = X;
+                    Y.s = ov > 0 ? ln.side[rr++ % kSideStreams] : s;
+                    // the members' buffer states are equal: they have cycled together
+                    // since the stage began
+                    const int c0 = gci[g][0];
+                    if (!mixed) {
+                        Iter<double> it = i64[c0];
+                        if ((st = mu_cycle<double>(Y, G, SP.L, it, a64b, d_kx, d_ky)) != MSG_OK) return st;
+                        for (int ci : gci[g]) i64[ci] = it;
+                        continue;
+                    }
+                    Iter<float> it = i32[c0];
+                    if ((st = mu_cycle<float>(Y, G, SP.L, it, a32b, d_kx32, d_ky32)) != MSG_OK) return st;
+                    for (int ci : gci[g]) i32[ci] = it;
+                    for (int ci : gci[g]) {
+                        const ClassPlan& C = SP.classes[ci];
+                        const float* e32 = i32[ci].now(SP.L);
+                        st = chunked(C.top1d, C.K, [&](int k0, int kn) {
+                            const int a = C.first + k0;
+                            return launch_ir_update(C.top1d, kn, X.probs + a, X.active + a, it64.v[0], e32, Y.s);
+                        });
+                        if (st != MSG_OK) return st;
+                    }
+                }
+            } else {
             if (fork) {
                 HIPCHK(hipEventRecord(ln.fork, s));
                 for (int k = 0; k < kSideStreams; ++k) HIPCHK(hipStreamWaitEvent(ln.side[k], ln.fork, 0));
@@ -1672,8 +1831,9 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                 const Span span{0, C.K};
                 // one W-cycle of the class (and its refinement update)
                 auto cycle = [&]() -> msg_status {
-                    if (!mixed) return mu_cycle<double>(Y, C, span, SP.L, i64[ci], a64b, d_kx, d_ky);
-                    msg_status r = mu_cycle<float>(Y, C, span, SP.L, i32[ci], a32b, d_kx32, d_ky32);
+                    const Group G1 = single_group(C, span, Y.kact);
+                    if (!mixed) return mu_cycle<double>(Y, G1, SP.L, i64[ci], a64b, d_kx, d_ky);
+                    msg_status r = mu_cycle<float>(Y, G1, SP.L, i32[ci], a32b, d_kx32, d_ky32);
                     if (r != MSG_OK) return r;
                     const float* e32 = i32[ci].now(SP.L);
                     return chunked(C.top1d, C.K, [&](int k0, int kn) {
@@ -1713,6 +1873,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                     i32[ci] = G.after32;
                 }
                 HIPCHK(hipGraphLaunch(G.exec, Y.s));
+            }
             }
             for (int k = 0; fork && k < kSideStreams; ++k) {
                 HIPCHK(hipEventRecord(ln.join[k], ln.side[k]));
@@ -2108,7 +2269,8 @@ extern "C" msg_status msg_cycles(msg_handle h, const msg_batch_desc* batch, cons
         hipError_t e = launch_ratio(S, top.ntiles, X.probs, part, d_ratios, k, ncycles + 1, s);
         if (e != hipSuccess) return fail(MSG_ERR_HIP, "ratio: %s", hipGetErrorString(e));
         if (k == ncycles) break;
-        st = mg ? mg_cycle(X, M, 0, it, B, d_kx, d_ky) : mu_cycle<double>(X, C, Span{0, S}, P + Q, it, B, d_kx, d_ky);
+        st = mg ? mg_cycle(X, M, 0, it, B, d_kx, d_ky)
+                : mu_cycle<double>(X, single_group(C, Span{0, S}, S), P + Q, it, B, d_kx, d_ky);
         if (st != MSG_OK) return st;
     }
     const int64_t ntop = grid_cells(c, P, Q);

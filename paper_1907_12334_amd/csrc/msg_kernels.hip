@@ -1288,12 +1288,13 @@ __device__ __forceinline__ void tail_norms(const KTail& TL, T* sm, double& rr, d
 // adaptive loop of one F-cycle level (Section 2: cycle until ||r|| <= tol ||b||,
 // checked before every cycle) for problems whose rectangle fits in LDS,
 // updating cycle counts, status and the non-finite level like k_converge.
-// Block b works on problem b of the launch with class descriptor
-// tables[cls[b]] (cls given: several classes in one launch, -1 = skip) or
-// tables[tidx].
+// Block b works on problem b of the launch, problem kbase + b of the stage's
+// table, with class descriptor tables[cls[b]] (cls given: several classes in
+// one launch, -1 = skip) or tables[tidx]; with `pack`, its conductance image
+// is image (kbase + b - first) of its class, at the class's pack_off.
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
-k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int tidx,
+k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int tidx, int kbase,
        const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c, int mu, int nu1,
        int nu2, T omega, int count, int combine, T* __restrict__ V, T* __restrict__ B, const T* __restrict__ KX,
        const T* __restrict__ KY, const T* __restrict__ pack, const double* __restrict__ chol, TailSolve ad)
@@ -1311,7 +1312,8 @@ k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int ti
     // computed here from the coefficients), the top level's iterates and
     // right-hand sides, the coarsest inverse
     if (pack) {
-        const uint4* src = reinterpret_cast<const uint4*>(pack + (int64_t)k * TL.nstat);
+        const uint4* src =
+            reinterpret_cast<const uint4*>(pack + TL.pack_off + (int64_t)(kbase + k - TL.first) * TL.nstat);
         uint4* dst = reinterpret_cast<uint4*>(sm);
         const int n16 = TL.nstat * (int)sizeof(T) / 16;
         for (int idx = threadIdx.x; idx < n16; idx += NT) dst[idx] = src[idx];
@@ -1710,8 +1712,8 @@ hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int3
 }
 
 template <typename T>
-hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int threads, size_t lds_bytes, int K,
-                       const KProb* probs, const int32_t* active, int c, int mu, int nu1, int nu2, T omega,
+hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int kbase, int threads, size_t lds_bytes,
+                       int K, const KProb* probs, const int32_t* active, int c, int mu, int nu1, int nu2, T omega,
                        int count, int combine, T* V, T* B, const T* KX, const T* KY, const T* pack,
                        const double* chol, const TailSolve& ad, hipStream_t st)
 {
@@ -1721,11 +1723,11 @@ hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int th
         if (e != hipSuccess) return e;
     }
     if (threads == 256)
-        hipLaunchKernelGGL((k_tail<T, 256>), dim3(K), dim3(256), lds_bytes, st, tables, cls, tidx, probs, active, c,
-                           mu, nu1, nu2, omega, count, combine, V, B, KX, KY, pack, chol, ad);
+        hipLaunchKernelGGL((k_tail<T, 256>), dim3(K), dim3(256), lds_bytes, st, tables, cls, tidx, kbase, probs,
+                           active, c, mu, nu1, nu2, omega, count, combine, V, B, KX, KY, pack, chol, ad);
     else
-        hipLaunchKernelGGL((k_tail<T, 64>), dim3(K), dim3(64), lds_bytes, st, tables, cls, tidx, probs, active, c,
-                           mu, nu1, nu2, omega, count, combine, V, B, KX, KY, pack, chol, ad);
+        hipLaunchKernelGGL((k_tail<T, 64>), dim3(K), dim3(64), lds_bytes, st, tables, cls, tidx, kbase, probs,
+                           active, c, mu, nu1, nu2, omega, count, combine, V, B, KX, KY, pack, chol, ad);
     return LAUNCH_CHECK();
 }
 
@@ -1882,11 +1884,11 @@ template hipError_t launch_prolong<double>(const KLevel&, int, const KProb*, con
                                            const double*, double*, const double*, const double*, hipStream_t);
 template hipError_t launch_prolong<float>(const KLevel&, int, const KProb*, const int32_t*, int, float, const float*,
                                           float*, const float*, const float*, hipStream_t);
-template hipError_t launch_tail<double>(const KTail*, const int32_t*, int, int, size_t, int, const KProb*,
+template hipError_t launch_tail<double>(const KTail*, const int32_t*, int, int, int, size_t, int, const KProb*,
                                         const int32_t*, int, int, int, int, double, int, int, double*, double*,
                                         const double*, const double*, const double*, const double*,
                                         const TailSolve&, hipStream_t);
-template hipError_t launch_tail<float>(const KTail*, const int32_t*, int, int, size_t, int, const KProb*,
+template hipError_t launch_tail<float>(const KTail*, const int32_t*, int, int, int, size_t, int, const KProb*,
                                        const int32_t*, int, int, int, int, float, int, int, float*, float*, const float*,
                                        const float*, const float*, const double*, const TailSolve&, hipStream_t);
 template hipError_t launch_tail_pack<double>(const KTail*, int, const KProb*, int, const double*, const double*,

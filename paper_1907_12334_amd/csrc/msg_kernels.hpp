@@ -70,12 +70,14 @@ template <typename T>
 hipError_t launch_prolong(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, T omega,
                           const T* Vc, T* Vf, const T* KX, const T* KY, hipStream_t st);
 // block b uses class descriptor tables[cls[b]] (cls given, -1 skips the
-// block) or tables[tidx]; threads is 64 or 256; combine != 0 when the top
+// block) or tables[tidx] and is problem kbase + b of the stage (which picks
+// its conductance image in `pack`); threads is 64 or 256; combine != 0 when the top
 // level was just filled by the restricting pre-smoothing pass, whose two
 // halves of a grid with two parents the tail averages as it loads them
 hipError_t launch_tail_slots(const KTail* table, int4* out, hipStream_t st);
 template <typename T>
-hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int threads, size_t lds_bytes, int K,
+hipError_t launch_tail(const KTail* tables, const int32_t* cls, int tidx, int kbase, int threads, size_t lds_bytes,
+                       int K,
                        const KProb* probs, const int32_t* active, int c, int mu, int nu1, int nu2, T omega,
                        int count, int combine, T* V, T* B, const T* KX, const T* KY, const T* pack,
                        const double* chol, const TailSolve& ad, hipStream_t st);

@@ -342,25 +342,58 @@ def delta_q(batch: Batch, q, dq, stream=None):
 
 # ---------------------------------------------------------------- convenience
 class Buffers:
-    """Device buffers of one batch: fields, outputs and workspace (torch)."""
+    """Device buffers of one batch: fields, outputs and workspace (torch).
+    With `arena` (a uint8 device tensor), every buffer is a 256-byte aligned
+    view into it instead of an allocation of its own (Buffers.bytes_needed
+    says how much it must hold)."""
 
-    def __init__(self, batch: Batch, opts: SolveOpts, device="cuda:0", mixed_fields=None):
+    def __init__(self, batch: Batch, opts: SolveOpts, device="cuda:0", mixed_fields=None, arena=None):
         import torch
         lay = batch.layout()
         self.layout = lay
-        dev = torch.device(device)
+        dev = torch.device(device) if arena is None else arena.device
         mixed = opts.precision == MIXED if mixed_fields is None else mixed_fields
-        self.kx = torch.empty(int(lay["xface"][-1]), dtype=torch.float64, device=dev)
-        self.ky = torch.empty(int(lay["yface"][-1]), dtype=torch.float64, device=dev)
-        self.kx32 = torch.empty(int(lay["xface"][-1]), dtype=torch.float32, device=dev) if mixed else None
-        self.ky32 = torch.empty(int(lay["yface"][-1]), dtype=torch.float32, device=dev) if mixed else None
-        self.u = torch.empty(int(lay["cell"][-1]), dtype=torch.float64, device=dev)
-        self.q = torch.empty(int(lay["grid"][-1]), dtype=torch.float64, device=dev)
-        self.dq = torch.empty(int(lay["grid"][-1]), dtype=torch.float64, device=dev)
-        self.cycles = torch.empty(int(lay["grid"][-1]), dtype=torch.int32, device=dev)
-        self.status = torch.empty(batch.n, dtype=torch.int32, device=dev)
         nbytes = workspace_size(batch, opts)
-        self.ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=dev)
+        plan = self._plan(lay, batch.n, mixed, nbytes)
+        if arena is not None:
+            arena = arena[(-arena.data_ptr()) % 256:]            # views start on 256-byte boundaries
+            if plan[-1][1] > arena.numel():
+                raise ValueError(f"arena of {arena.numel()} bytes cannot hold the batch ({plan[-1][1]} bytes)")
+        for name, end, dtype, n in plan[:-1]:
+            if dtype is None:
+                setattr(self, name, None)
+            elif arena is None:
+                setattr(self, name, torch.empty(n, dtype=dtype, device=dev))
+            else:
+                size = n * torch.empty((), dtype=dtype).element_size()
+                setattr(self, name, arena[end - size:end].view(dtype))
+
+    @staticmethod
+    def _plan(lay, S, mixed, ws_bytes):
+        """[(name, end byte in the arena, dtype or None, elements)] plus the total."""
+        import torch
+        items = [("kx", torch.float64, int(lay["xface"][-1])), ("ky", torch.float64, int(lay["yface"][-1])),
+                 ("kx32", torch.float32 if mixed else None, int(lay["xface"][-1])),
+                 ("ky32", torch.float32 if mixed else None, int(lay["yface"][-1])),
+                 ("u", torch.float64, int(lay["cell"][-1])), ("q", torch.float64, int(lay["grid"][-1])),
+                 ("dq", torch.float64, int(lay["grid"][-1])), ("cycles", torch.int32, int(lay["grid"][-1])),
+                 ("status", torch.int32, S), ("ws", torch.float64, (ws_bytes + 7) // 8)]
+        out, off = [], 0
+        for name, dt, n in items:
+            if dt is None:
+                out.append((name, off, None, 0))
+                continue
+            size = n * torch.empty((), dtype=dt).element_size()
+            off = (off + 255) // 256 * 256 + size
+            out.append((name, off, dt, n))
+        out.append(("total", (off + 255) // 256 * 256, None, 0))
+        return out
+
+    @staticmethod
+    def bytes_needed(batch: Batch, opts: SolveOpts, mixed_fields=None) -> int:
+        """Arena bytes that hold every buffer of the batch."""
+        mixed = opts.precision == MIXED if mixed_fields is None else mixed_fields
+        return Buffers._plan(batch.layout(), batch.n, mixed, workspace_size(batch, opts))[-1][1] + 256
 
 
 def run(handle: Handle, spec, batch: Batch, opts: SolveOpts, xi, bufs: Optional[Buffers] = None, rhs=None,

@@ -14,14 +14,19 @@ Scheduling:
     a HIP stream (default priority) and, whenever it is free, takes the
     waiting requests of its lane in arrival order into one ragged batch, up to
     a request count, a work cap and the free HBM budget;
-  * the budget (a fraction of the free device memory at start) is reserved per
-    request from its exact footprint (fields, solution, outputs and its share
-    of the solver workspace) and released when its batch completes, so a
-    request that arrives while other batches are on the device is admitted as
-    soon as a worker and memory are free, and its batch runs concurrently
-    with theirs on another stream;
-  * fields, iterates and solutions stay on the device during a solve; only
-    Q, Delta Q, status and cycle counts (and u on request) come back.
+  * the budget (a fraction of the free device memory at start) is split into
+    one device arena per worker, allocated once when the engine starts; a
+    batch's buffers (fields, solutions, outputs, solver workspace) are views
+    into its worker's arena, so serving allocates no device memory per
+    batch.  Each request reserves its exact footprint from the budget until
+    its batch completes, and a worker takes requests while their footprints
+    fit its arena, so a request that arrives while other batches are on the
+    device is admitted as soon as a worker is free, and its batch runs
+    concurrently with theirs on another stream;
+  * the standard normals of a request's field are drawn on the device from
+    its stream (engine seed, sample id); fields, iterates and solutions stay
+    on the device during a solve; only Q, Delta Q, status and cycle counts
+    (and u on request) come back.
 
 The library calls release the interpreter lock, so workers overlap on the
 device.  Nothing here computes any part of the method.
@@ -51,6 +56,7 @@ class Request:
     t_admit: float = float("nan")
     t_done: float = float("nan")
     batch_size: int = 0
+    lane: str = ""
     q: Optional[np.ndarray] = None
     dq: Optional[np.ndarray] = None
     u: Optional[np.ndarray] = None
@@ -62,6 +68,9 @@ class Request:
     @property
     def latency(self) -> float:
         return self.t_done - self.t_arrival
+
+
+BIG_TAIL_LDS = 150 * 1024     # LDS bytes per problem of the large-request lane's tails
 
 
 def work_estimate(c: int, P: int, Q: int) -> float:
@@ -85,7 +94,11 @@ class Footprints:
             cells, xf, yf, grids = (int(lay[k][-1]) for k in ("cell", "xface", "yface", "grid"))
             field = (8 + (4 if self.mixed else 0)) * (xf + yf)
             outs = 8 * cells + grids * (8 + 8 + 4) + 4
-            self._cache[key] = field + outs + msg.workspace_size(b, self.opts) + 4096
+            # the larger of the two lanes' plans (the large-request lane's
+            # wider tails need larger tail images)
+            ws = max(msg.workspace_size(b, self.opts),
+                     msg.workspace_size(b, dataclasses.replace(self.opts, tail_budget=BIG_TAIL_LDS)))
+            self._cache[key] = field + outs + ws + 4096
         return self._cache[key]
 
 
@@ -118,10 +131,11 @@ class Admission:
             self.cv.notify_all()
         return req
 
-    def take(self, lane: str):
+    def take(self, lane: str, cap: Optional[int] = None):
         """Pop the next batch of `lane` without waiting: arrival order, up to
-        max_batch requests and the work cap, while the budget allows.  Returns
-        (requests, reserved bytes); ([], 0) if the head does not fit yet."""
+        max_batch requests and the work cap, while the budget (and the
+        worker's capacity `cap`, if given) allows.  Returns (requests, reserved
+        bytes); ([], 0) if the head does not fit yet."""
         with self.cv:
             q = self.lanes[lane]
             batch, work, need = [], 0.0, 0
@@ -131,7 +145,7 @@ class Admission:
                 w = self.work(r.P, r.Q)
                 if batch and work + w > self.max_batch_work:
                     break
-                if self.reserved + need + b > self.budget:
+                if self.reserved + need + b > self.budget or (cap is not None and need + b > cap):
                     break
                 q.popleft()
                 batch.append(r)
@@ -140,14 +154,14 @@ class Admission:
             self.reserved += need
             return batch, need
 
-    def wait_batch(self, lane: str):
+    def wait_batch(self, lane: str, cap: Optional[int] = None):
         """Block until a batch of `lane` can start; None once stopping and empty."""
         with self.cv:
             while True:
                 if self.stopping and not self.lanes[lane]:
                     return None
                 if self.lanes[lane]:
-                    batch, need = self.take(lane)
+                    batch, need = self.take(lane, cap)
                     if batch:
                         return batch, need
                 self.cv.wait(timeout=0.05)
@@ -183,13 +197,18 @@ class Engine:
         self.foot = Footprints(c, opts, opts.precision == msg.MIXED)
         self.adm = Admission(budget_bytes, self.foot, lambda P, Q: work_estimate(c, P, Q), max_batch,
                              max_batch_work, big_work)
+        # one arena per worker, carved once: a share of the budget each
+        n_workers = workers + big_workers
+        self.arena_bytes = budget_bytes // n_workers // 256 * 256
+        self.arenas = [torch.empty(self.arena_bytes, dtype=torch.uint8, device=self.dev) for _ in range(n_workers)]
         self.t0 = time.perf_counter()
         self.batches: List[dict] = []
         self.lock = threading.Lock()
         self.inflight = 0
         self.max_inflight = 0
-        self.threads = [threading.Thread(target=self._worker, args=("small",), daemon=True) for _ in range(workers)]
-        self.threads += [threading.Thread(target=self._worker, args=("big",), daemon=True) for _ in range(big_workers)]
+        lanes = ["small"] * workers + ["big"] * big_workers
+        self.threads = [threading.Thread(target=self._worker, args=(lane, self.arenas[k]), daemon=True)
+                        for k, lane in enumerate(lanes)]
         for t in self.threads:
             t.start()
 
@@ -198,21 +217,30 @@ class Engine:
         return time.perf_counter() - self.t0
 
     def submit(self, req: Request) -> Request:
+        if self.foot(req.P, req.Q) > self.arena_bytes - self.arena_bytes // 16:
+            raise ValueError(f"request ({req.P},{req.Q}) needs more than a worker's arena")
         return self.adm.submit(req)
 
     def close(self):
         self.adm.stop()
         for t in self.threads:
             t.join()
+        self.arenas = []
 
-    def _worker(self, lane: str):
+    def _worker(self, lane: str, arena):
         torch = self.torch
+        # large requests come in batches of a few samples: their tails take a
+        # CU's worth of LDS each (deeper on-chip tails, fewer launches)
+        opts = dataclasses.replace(self.opts, tail_budget=BIG_TAIL_LDS) if lane == "big" else self.opts
         torch.cuda.set_device(self.dev)
         handle = msg.Handle(self.device)
         stream = torch.cuda.Stream(device=self.dev)      # default priority
+        # footprints are estimates from single requests: keep 1/16 of the
+        # arena for what a batch needs beyond their sum
+        cap = self.arena_bytes - self.arena_bytes // 16
         try:
             while True:
-                got = self.adm.wait_batch(lane)
+                got = self.adm.wait_batch(lane, cap)
                 if got is None:
                     return
                 batch, need = got
@@ -223,7 +251,7 @@ class Engine:
                 for r in batch:
                     r.t_admit = t_admit
                 try:
-                    self._run(handle, stream, batch)
+                    self._run(handle, stream, batch, arena, opts)
                 except Exception as e:                  # report per request, keep serving
                     for r in batch:
                         r.error = f"{type(e).__name__}: {e}"
@@ -231,24 +259,25 @@ class Engine:
                 self.adm.release(need)
                 with self.lock:
                     self.inflight -= 1
-                    self.batches.append({"lane": lane, "size": len(batch), "t_admit": t_admit, "t_done": t_done})
+                    self.batches.append({"lane": lane, "size": len(batch), "t_admit": t_admit, "t_done": t_done,
+                                         "work": float(sum(work_estimate(self.c, r.P, r.Q) for r in batch))})
                 for r in batch:
                     r.t_done = t_done
                     r.batch_size = len(batch)
+                    r.lane = lane
                     r.done.set()
         finally:
             handle.close()
 
-    def _run(self, handle: msg.Handle, stream, reqs: Sequence[Request]):
+    def _run(self, handle: msg.Handle, stream, reqs: Sequence[Request], arena, opts: msg.SolveOpts):
         torch = self.torch
         P = [r.P for r in reqs]
         Q = [r.Q for r in reqs]
         batch = msg.Batch(self.c, P, Q)
-        xi_h = I.draw_xi(self.field.n_terms, [r.sample_id for r in reqs], self.seed)
+        ids = np.array([r.sample_id for r in reqs], dtype=np.int64)
         with torch.cuda.stream(stream):
-            xi = torch.from_numpy(xi_h).to(self.dev, non_blocking=False)
-            bufs = msg.Buffers(batch, self.opts, device=self.dev)
-            msg.run(handle, self.field, batch, self.opts, xi, bufs, stream=stream)
+            bufs = msg.Buffers(batch, opts, arena=arena)
+            msg.run(handle, self.field, batch, opts, None, bufs, stream=stream, seed=self.seed, sample_id=ids)
             q = bufs.q.cpu().numpy()
             dq = bufs.dq.cpu().numpy()
             st = bufs.status.cpu().numpy()
@@ -306,6 +335,11 @@ def summarize(reqs: Sequence[Request], offered_rate: Optional[float] = None) -> 
         "errors": int(sum(r.error is not None for r in reqs)),
         "span_s": round(span, 3),
     }
+    for lane in ("small", "big"):
+        lt = np.array([r.latency for r in reqs if r.lane == lane])
+        if len(lt):
+            out[f"{lane}_lane"] = {"requests": int(len(lt)), "p50_ms": round(float(np.percentile(lt, 50)) * 1e3, 2),
+                                   "p99_ms": round(float(np.percentile(lt, 99)) * 1e3, 2)}
     out["drain_s"] = round(t_last - t_arr, 3)
     if offered_rate:
         out["offered_per_s"] = offered_rate

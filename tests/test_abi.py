@@ -87,7 +87,7 @@ def test_workspace_size_and_options():
     for bad in (-2, 3):
         with pytest.raises(msg.MsgError):
             msg.workspace_size(b, msg.SolveOpts(overlap=bad))
-    for bad in (dict(tail_budget=512), dict(tail_budget=70000), dict(tile_width=48), dict(tile_width=512),
+    for bad in (dict(tail_budget=512), dict(tail_budget=160000), dict(tile_width=48), dict(tile_width=512),
                 dict(tile_cells=32), dict(tile_lds=9000)):
         with pytest.raises(msg.MsgError):
             msg.workspace_size(b, msg.SolveOpts(**bad))

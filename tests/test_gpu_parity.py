@@ -97,6 +97,33 @@ def test_tail_depth_does_not_change_results(handle, tail):
     _check_batch(handle, c, [P] * 2, [Q] * 2, spec, opts, tol=1e-12)
 
 
+@pytest.mark.parametrize("precision", [msg.FP64, msg.MIXED])
+@pytest.mark.parametrize("max_cycles", [1, 2, 400])
+def test_wide_tails_for_few_large_samples(handle, precision, max_cycles):
+    """A tail budget of 150 KB per problem (the request loop's large-request
+    lane): deeper tails on four wavefronts and larger rectangles solved whole
+    in one kernel.  Unconverged iterates match the oracle step by step, and
+    converged ones within the bar (FP64: 1e-10; mixed: 1e-8 against the FP64
+    oracle)."""
+    c, P, Q = 4, [6, 5, 7], [5, 6, 1]
+    spec = I.separable(0.3, 0.03, 1.0, m=20, face_rule=1)
+    xi = I.draw_xi(spec.n_terms, range(3), base_seed=31)
+    if precision == msg.FP64:
+        opts = msg.SolveOpts(max_cycles=max_cycles, tail_budget=150 * 1024)
+        _check_batch(handle, c, P, Q, spec, opts, xi=xi, tol=1e-12 if max_cycles < 400 else FP64_TOL)
+        return
+    if max_cycles < 400:
+        pytest.skip("mixed precision is compared converged")
+    opts = msg.SolveOpts(precision=msg.MIXED, tol=1e-8, max_cycles=max_cycles, tail_budget=150 * 1024)
+    out = PR.gpu_solve(c, P, Q, spec, xi, opts, handle=handle)
+    for s in range(3):
+        g = PR.per_sample(out, s)
+        ora = PR.oracle_solve(c, P[s], Q[s], spec, xi[s], tol=1e-10, max_cycles=max_cycles)
+        assert g["status"] == 0 and ora["status"] == 0
+        eu, eq, edq = PR.errors(c, P[s], Q[s], g, ora)
+        assert max(eu, eq, edq) <= MIXED_TOL, (s, eu, eq, edq)
+
+
 @pytest.mark.parametrize("handoff", [0, 1, -1])
 def test_converged_with_and_without_handoff(handle, handoff):
     """Converged solves through the host loop only, with a handoff once a

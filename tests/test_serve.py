@@ -105,7 +105,8 @@ def test_served_in_mix_equals_alone():
     P = rng.integers(1, 5, size=n)
     Q = rng.integers(1, 5, size=n)
     ids = np.arange(1000, 1000 + n)
-    eng = Engine(I.KL10, c, opts, workers=3, big_workers=1, max_batch=8, big_work=work_estimate(c, 4, 4))
+    eng = Engine(I.KL10, c, opts, workers=3, big_workers=1, max_batch=8, big_work=work_estimate(c, 4, 4),
+                 budget_bytes=8 << 30)
     try:
         reqs = replay(eng, np.zeros(n), P, Q, ids, want_u=True, timeout=300)
     finally:
@@ -113,12 +114,12 @@ def test_served_in_mix_equals_alone():
     s = summarize(reqs)
     assert s["errors"] == 0 and s["requests"] == n
     assert eng.max_inflight >= 2                 # batches overlapped on the device
+    assert all(r.lane in ("small", "big") for r in reqs) and "small_lane" in s
     h = msg.Handle(0)
     worst = 0.0
     for r in reqs[::3]:
         b = msg.Batch(c, [r.P], [r.Q])
-        xi = torch.tensor(I.draw_xi(I.KL10.n_terms, [r.sample_id], I.BASE_SEED + 5), device="cuda:0")
-        bufs = msg.run(h, I.KL10, b, opts, xi)
+        bufs = msg.run(h, I.KL10, b, opts, None, seed=I.BASE_SEED + 5, sample_id=[r.sample_id])
         u = bufs.u.cpu().numpy()
         q = bufs.q.cpu().numpy()
         dq = bufs.dq.cpu().numpy()
@@ -126,4 +127,38 @@ def test_served_in_mix_equals_alone():
         assert np.array_equal(bufs.cycles.cpu().numpy(), r.cycles)
         for a, m in ((u, r.u), (q, r.q), (dq, r.dq)):
             worst = max(worst, float(np.max(np.abs(a - m)) / max(np.max(np.abs(a)), 1e-300)))
+    assert worst <= 1e-8, worst
+
+
+@pytest.mark.gpu
+def test_served_answers_match_the_oracle():
+    """Requests served from a mix (mixed precision refined to 1e-8, normals
+    drawn on the device from the engine's streams): Q and Delta Q on every
+    grid within 1e-8 of the FP64 oracle run to 1e-10 on the oracle's own
+    normals of the same streams."""
+    from oracle import binding as O
+    from oracle import normals as N
+    from paper_1907_12334_amd import msg
+    from paper_1907_12334_amd.serve import Engine, replay
+
+    c, seed = 4, I.BASE_SEED + 5
+    opts = msg.SolveOpts(tol=1e-8, max_cycles=200, precision=msg.MIXED)
+    t, P, Q, ids = I.request_trace(64, 5000.0)
+    keep = (P + Q) <= 7                                   # the oracle stays quick
+    P, Q, ids, t = P[keep], Q[keep], ids[keep], t[keep] - t[keep][0]
+    eng = Engine(I.KL10, c, opts, workers=3, big_workers=1, budget_bytes=8 << 30, seed=seed)
+    try:
+        reqs = replay(eng, t, P, Q, ids, timeout=300)
+    finally:
+        eng.close()
+    worst = 0.0
+    for r in reqs[::2]:
+        xi = N.kl_normals(I.KL10.n_terms, [r.sample_id], seed)[0]
+        kx, ky = O.hierarchy_field(c, r.P, r.Q, I.KL10.as_dict(), xi)
+        ora = O.fmsg_solve(c, r.P, r.Q, kx, ky, O.opts(tol=1e-10, max_cycles=200))
+        assert r.status == 0 and ora["status"] == 0
+        dq = O.delta_q(r.P, r.Q, ora["q"])
+        worst = max(worst, float(np.max(np.abs(r.q - ora["q"]) / np.abs(ora["q"]))),
+                    float(np.max(np.abs(r.dq - dq)) / np.max(np.abs(ora["q"]))))
+    print(f"served vs oracle: {len(reqs[::2])} requests, worst {worst:.2e}", flush=True)
     assert worst <= 1e-8, worst
