@@ -456,11 +456,18 @@ def mimc_leg(h, msg, I):
     flux (KL-10, c = 4, mixed precision to 1e-8), batches of 512 samples."""
     from paper_1907_12334_amd import mimc as M
     out = {"field": "KL-10", "c": 4, "precision": "mixed, refined to 1e-8", "batch": 512}
-    for name, kind, tol in (("Q1_point", msg.QOI_POINT, 3e-4), ("Q3_flux", msg.QOI_FLUX, 3e-3)):
-        r = M.MSGMIMC(h, I.KL10, c=4, kind=kind).run(tol=tol, batch=512)
+    # the geometric pmf re-fitted from the rates, and the learned pmf of the
+    # paper's experiments (sample sizes ~ sqrt(V/C) per index)
+    for name, kind, tol, pmf in (("Q1_point", msg.QOI_POINT, 3e-4, "geometric"),
+                                 ("Q1_point_learned_pmf", msg.QOI_POINT, 3e-4, "learned"),
+                                 ("Q3_flux", msg.QOI_FLUX, 3e-3, "geometric"),
+                                 ("Q3_flux_learned_pmf", msg.QOI_FLUX, 3e-3, "learned")):
+        est = M.MSGMIMC(h, I.KL10, c=4, kind=kind, pmf=pmf)
+        r = est.run(tol=tol, batch=512)
         top = sorted(r.index_counts.items(), key=lambda kv: -kv[1])[:6]
-        out[name] = {"tol": tol, "E": r.E, "rmse": r.rmse, "samples": r.N, "batches": r.batches,
+        out[name] = {"pmf": pmf, "tol": tol, "E": r.E, "rmse": r.rmse, "samples": r.N, "batches": r.batches,
                      "seconds": round(r.seconds, 3), "samples_per_s": round(r.N / r.seconds, 1),
+                     "cell_visits": float(sum(t for _, t in est.work.values())),
                      "learned_rates": [round(x, 3) for x in r.rates],
                      "fitted_work_rates_gamma": [round(x, 3) for x in r.gamma],
                      "most_drawn_indices": [[list(k), v] for k, v in top]}

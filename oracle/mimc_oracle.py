@@ -13,7 +13,17 @@ Readings:
   * GEOMETRIC(r) in a direction has P(L >= l) = exp(-r l), drawn by inverse
     transform from a uniform U in (0,1]: L = floor(-log(U) / r);
   * Y^(n) = sum over tau <= L^(n) of Delta Q_tau^(n) / p_tau, with p from the
-    distribution L^(n) was drawn from.
+    distribution L^(n) was drawn from;
+  * the learned (empirical) distribution of the experiments (Section 3, eq.
+    Nell): N_tau proportional to sqrt(V_tau / C_tau), normalised so that the
+    coarsest index is always reached, p_tau = min(1, N_tau / N_0).  Such a p
+    need not be the tail of any distribution, so the pmf pi(l) = P(L = l) is
+    taken from it by inclusion-exclusion, negative masses are set to zero,
+    the result is renormalised and mixed with weight eps with the geometric
+    pmf (so that every index of the box keeps a positive probability and the
+    estimator stays unbiased), and the weights use the tail of that pmf.
+    Indices live in the box [0..lmax]^2: draws beyond it are capped, so the
+    tail of an index inside the box is unchanged.
 """
 import math
 
@@ -60,3 +70,72 @@ def cost_ratio(beta, gamma):
             term *= 2.0 ** (-(gamma[j] + beta[j]) / 2.0)
         total += (-1) ** (len(members) + 1) * term
     return 1.0 - total
+
+
+# ---------------------------------------------------------------- learned pmf
+def geometric_tail(r, lmax):
+    """p_tau = prod_j exp(-r_j tau_j) on the box [0..lmax]^2 (draws capped at lmax)."""
+    return {(a, b): tail_probability(r, (a, b)) for a in range(lmax + 1) for b in range(lmax + 1)}
+
+
+def pmf_from_tail(p, lmax):
+    """pi(l) = P(L = l) from the tail p(tau) = P(L >= tau) by inclusion-exclusion
+    in the two directions; the tail is zero outside the box."""
+    def P(a, b):
+        return p[(a, b)] if a <= lmax and b <= lmax else 0.0
+    return {(a, b): P(a, b) - P(a + 1, b) - P(a, b + 1) + P(a + 1, b + 1)
+            for a in range(lmax + 1) for b in range(lmax + 1)}
+
+
+def tail_from_pmf(pi, lmax):
+    """p(tau) = sum over l >= tau (both directions) of pi(l)."""
+    out = {}
+    for t1 in range(lmax + 1):
+        for t2 in range(lmax + 1):
+            s = 0.0
+            for a in range(t1, lmax + 1):
+                for b in range(t2, lmax + 1):
+                    s += pi[(a, b)]
+            out[(t1, t2)] = s
+    return out
+
+
+def empirical_tail(V, C, lmax):
+    """p_tau = min(1, N_tau / N_0), N_tau = sqrt(V_tau / C_tau) (eq. Nell)."""
+    n0 = math.sqrt(V[(0, 0)] / C[(0, 0)])
+    return {(a, b): min(1.0, math.sqrt(V[(a, b)] / C[(a, b)]) / n0)
+            for a in range(lmax + 1) for b in range(lmax + 1)}
+
+
+def learned_distribution(V, C, r, lmax, eps):
+    """(pi, p) of the learned distribution: the pmf of the empirical tail with
+    negative masses dropped and renormalised, mixed with weight eps with the
+    geometric pmf of rates r; p is the tail of the mixture."""
+    raw = pmf_from_tail(empirical_tail(V, C, lmax), lmax)
+    raw = {k: max(0.0, x) for k, x in raw.items()}
+    total = sum(raw.values())
+    geo = pmf_from_tail(geometric_tail(r, lmax), lmax)
+    pi = {k: (1.0 - eps) * raw[k] / total + eps * geo[k] for k in raw}
+    return pi, tail_from_pmf(pi, lmax)
+
+
+def draw_index_pmf(pi, lmax, u):
+    """Inverse transform over the indices in p-major order: the first l whose
+    cumulative mass reaches u in (0,1]; the last index if rounding leaves the
+    total just below u."""
+    acc = 0.0
+    for a in range(lmax + 1):
+        for b in range(lmax + 1):
+            acc += pi[(a, b)]
+            if u <= acc:
+                return (a, b)
+    return (lmax, lmax)
+
+
+def sample_y_tail(dq, L, p):
+    """Y = sum_{0 <= tau <= L} dq[tau] / p[tau] for a tail given as a table."""
+    y = 0.0
+    for t1 in range(L[0] + 1):
+        for t2 in range(L[1] + 1):
+            y += dq[(t1, t2)] / p[(t1, t2)]
+    return y

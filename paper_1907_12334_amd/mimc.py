@@ -27,6 +27,19 @@ launch, so their times cannot be taken one by one.  Each sample keeps the
 p_tau of the distribution it was drawn from.  Indices are capped at `lmax`
 per direction (tail mass exp(-r (lmax+1))).
 
+With pmf="learned" the indices come instead from the learned distribution
+of the paper's experiments (Section 3, eq. Nell): sample sizes N_tau
+proportional to sqrt(V_tau / C_tau), with V_tau the sample variance of
+Delta Q_tau and C_tau the mean measured work of a solve on rectangle tau where
+an index has enough samples, and the fitted laws 2^(v0 - beta.tau) and
+2^(w0 + gamma.tau) elsewhere.  The tail p_tau = min(1, N_tau / N_0) becomes a
+pmf on the box [0..lmax]^2 by inclusion-exclusion, its negative masses are
+dropped, and it is renormalised and mixed with weight eps with the geometric
+pmf of the current rates, so that every index of the box keeps a positive
+probability and the estimator stays unbiased; the weights 1/p_tau use the
+tail of that mixture.  A draw takes one uniform and inverts the cumulative
+mass over the indices in p-major order.
+
 A batch in which any sample's solve failed (cycle cap hit, non-finite
 residual) or any difference is not finite raises MIMCFailure and adds
 nothing to the estimator: dropping the sample would bias the estimate, and
@@ -77,6 +90,42 @@ def reuse_weights(P: int, Q: int, r: np.ndarray) -> np.ndarray:
     return np.exp(r[0] * t1 + r[1] * t2).ravel()
 
 
+def geometric_tail(r: np.ndarray, lmax: int) -> np.ndarray:
+    """p_tau = exp(-r_1 tau_1) exp(-r_2 tau_2) on the box [0..lmax]^2."""
+    t = np.arange(lmax + 1, dtype=float)
+    return np.exp(-r[0] * t)[:, None] * np.exp(-r[1] * t)[None, :]
+
+
+def pmf_from_tail(p: np.ndarray) -> np.ndarray:
+    """pi(l) = P(L = l) from p(tau) = P(L >= tau) on a box (zero outside)."""
+    n = p.shape[0]
+    z = np.zeros((n + 1, n + 1))
+    z[:n, :n] = p
+    return z[:-1, :-1] - z[1:, :-1] - z[:-1, 1:] + z[1:, 1:]
+
+
+def tail_from_pmf(pi: np.ndarray) -> np.ndarray:
+    """p(tau) = sum of pi over l >= tau in both directions."""
+    return pi[::-1, ::-1].cumsum(0).cumsum(1)[::-1, ::-1].copy()
+
+
+def learned_distribution(V: np.ndarray, C: np.ndarray, r: np.ndarray, eps: float) -> Tuple[np.ndarray, np.ndarray]:
+    """(pi, p) on the box from per-index variances V and costs C (eq. Nell)."""
+    n0 = math.sqrt(V[0, 0] / C[0, 0])
+    raw = np.maximum(pmf_from_tail(np.minimum(1.0, np.sqrt(V / C) / n0)), 0.0)
+    raw /= raw.sum()
+    pi = (1.0 - eps) * raw + eps * pmf_from_tail(geometric_tail(r, V.shape[0] - 1))
+    return pi, tail_from_pmf(pi)
+
+
+def draw_indices_pmf(u: np.ndarray, pi: np.ndarray) -> np.ndarray:
+    """Indices from uniforms in (0,1]: the first index, in p-major order,
+    whose cumulative mass reaches u."""
+    n = pi.shape[0]
+    k = np.minimum(np.searchsorted(np.cumsum(pi.ravel()), u, side="left"), n * n - 1)
+    return np.stack([k // n, k % n], axis=1).astype(np.int64)
+
+
 class MIMCFailure(RuntimeError):
     """A batch contained samples whose solve did not converge."""
 
@@ -106,6 +155,7 @@ class Estimate:
     seconds: float
     index_counts: Dict[Tuple[int, int], int]
     gamma: Tuple[float, float] = (1.0, 1.0)     # work growth rates fitted from the solves
+    pmf: str = "geometric"                       # index distribution: geometric or learned
 
     @property
     def rmse(self) -> float:
@@ -118,7 +168,9 @@ class MSGMIMC:
     def __init__(self, handle: msg.Handle, field: I.FieldSpec = I.KL10, c: int = 4,
                  kind: int = msg.QOI_POINT, opts: Optional[msg.SolveOpts] = None, lmax: int = 9,
                  r0: Optional[np.ndarray] = None, seed: int = I.BASE_SEED + 6, learn: bool = True,
-                 prior: Optional[I.MaternPrior] = None):
+                 prior: Optional[I.MaternPrior] = None, pmf: str = "geometric", eps: float = 0.1):
+        if pmf not in ("geometric", "learned"):
+            raise ValueError(f"pmf must be 'geometric' or 'learned', not {pmf!r}")
         self.h, self.field, self.c, self.kind = handle, field, c, kind
         self.prior = prior
         self.min_eig_ratio = math.inf
@@ -126,10 +178,16 @@ class MSGMIMC:
         self.lmax, self.seed, self.learn = lmax, seed, learn
         self.r = np.array(initial_rates() if r0 is None else r0, dtype=float)
         self.ys: List[float] = []
-        self.dq: Dict[Tuple[int, int], List[float]] = {}
+        self.ystat: Tuple[int, float, float] = (0, 0.0, 0.0)         # count, mean, M2 of the Y's
+        self.dq: Dict[Tuple[int, int], Tuple[int, float, float]] = {}     # index -> (count, mean, M2)
         self.counts: Dict[Tuple[int, int], int] = {}
-        self.work: Dict[Tuple[int, int], List[float]] = {}
+        self.work: Dict[Tuple[int, int], Tuple[int, float]] = {}          # L -> (count, summed work)
         self.gamma = np.array([1.0, 1.0])
+        self.pmf, self.eps = pmf, eps
+        self.vfit: Optional[Tuple[float, np.ndarray]] = None     # (v0, beta): log2 V = v0 - beta.tau
+        self.wfit: Optional[Tuple[float, np.ndarray]] = None     # (w0, gamma): log2 C = w0 + gamma.tau
+        self.tail = geometric_tail(self.r, lmax)
+        self.pi = pmf_from_tail(self.tail)
         self.batches = 0
         self.next_sample_id = 0
 
@@ -170,34 +228,68 @@ class MSGMIMC:
 
     def add_batch(self, n: int) -> None:
         u = I.mimc_uniforms(n, self.batches, self.seed)
-        L = draw_indices(u, self.r, self.lmax)
+        if self.pmf == "learned":
+            L = draw_indices_pmf(u[:, 0], self.pi)
+            tail = self.tail
+        else:
+            L = draw_indices(u, self.r, self.lmax)
+            tail = None
         dqs, status, cycles, ids = self.solve_batch(L)
         failed = [(int(i), (int(l[0]), int(l[1])), int(st)) for i, l, st, d in zip(ids, L, status, dqs)
                   if st != msg.SAMPLE_CONVERGED or not np.all(np.isfinite(d))]
         if failed:
             raise MIMCFailure(failed)
-        for (P, Q), d, cy in zip(L, dqs, cycles):
-            w = reuse_weights(int(P), int(Q), self.r)
-            self.ys.append(float(np.dot(d, w)))
-            for a in range(P + 1):
-                for b in range(Q + 1):
-                    self.dq.setdefault((a, b), []).append(float(d[a * (Q + 1) + b]))
-            self.counts[(int(P), int(Q))] = self.counts.get((int(P), int(Q)), 0) + 1
-            self.work.setdefault((int(P), int(Q)), []).append(sample_work(self.c, int(P), int(Q), cy))
+        ybatch = np.empty(len(L))
+        groups: Dict[Tuple[int, int], List[int]] = {}
+        for k, (P, Q) in enumerate(L):
+            groups.setdefault((int(P), int(Q)), []).append(k)
+        for (P, Q), ks in groups.items():
+            D = np.stack([dqs[k] for k in ks])                    # samples x grids of rectangle (P, Q)
+            w = reuse_weights(P, Q, self.r) if tail is None else 1.0 / tail[:P + 1, :Q + 1].ravel()
+            ybatch[ks] = D @ w
+            self.merge_stats(P, Q, D)
+            work = np.array([sample_work(self.c, P, Q, cycles[k]) for k in ks])
+            n0, s0 = self.work.get((P, Q), (0, 0.0))
+            self.work[(P, Q)] = (n0 + len(ks), s0 + float(work.sum()))
+            self.counts[(P, Q)] = self.counts.get((P, Q), 0) + len(ks)
+        self.ys.extend(ybatch.tolist())
+        n0, m0, s0 = self.ystat
+        nb, mb = len(ybatch), float(ybatch.mean())
+        n1, delta = n0 + nb, mb - m0
+        self.ystat = (n1, m0 + delta * nb / n1, s0 + float(((ybatch - mb) ** 2).sum()) + delta * delta * n0 * nb / n1)
         self.batches += 1
         if self.learn:
             self.refit()
 
     # -------------------------------------------------------------- learning
+    def merge_stats(self, P: int, Q: int, D: np.ndarray) -> None:
+        """Fold the columns of D (Delta Q of a group of samples on rectangle
+        (P, Q)) into the per-index count, mean and sum of squared deviations
+        (pairwise merge of two samples' statistics)."""
+        nb = D.shape[0]
+        mb = D.mean(axis=0)
+        m2b = ((D - mb) ** 2).sum(axis=0)
+        for a in range(P + 1):
+            for b in range(Q + 1):
+                j = a * (Q + 1) + b
+                n0, m0, s0 = self.dq.get((a, b), (0, 0.0, 0.0))
+                n1 = n0 + nb
+                delta = float(mb[j]) - m0
+                self.dq[(a, b)] = (n1, m0 + delta * nb / n1, s0 + float(m2b[j]) + delta * delta * n0 * nb / n1)
+
+    def variance(self, key: Tuple[int, int], min_samples: int) -> float:
+        """Sample variance of Delta Q at an index, or 0 with fewer than min_samples samples."""
+        n, _, m2 = self.dq.get(key, (0, 0.0, 0.0))
+        return m2 / (n - 1) if n >= min_samples else 0.0
+
     def refit(self, min_samples: int = 8) -> None:
         """Re-fit the geometric rates from the sample variances of Delta Q."""
         rows, vals = [], []
-        for (a, b), xs in self.dq.items():
-            if len(xs) >= min_samples:
-                v = float(np.var(xs, ddof=1))
-                if v > 0.0:
-                    rows.append((1.0, a, b))
-                    vals.append(math.log2(v))
+        for (a, b) in self.dq:
+            v = self.variance((a, b), min_samples)
+            if v > 0.0:
+                rows.append((1.0, a, b))
+                vals.append(math.log2(v))
         if len(rows) < 4:
             return
         A = np.array(rows)
@@ -205,29 +297,56 @@ class MSGMIMC:
             return
         coef, *_ = np.linalg.lstsq(A, np.array(vals), rcond=None)
         beta = np.clip(-coef[1:], 0.5, 8.0)
+        self.vfit = (float(coef[0]), beta)
         self.gamma = self.fit_gamma(min_samples)
         self.r = LOG2 * (beta + self.gamma) / 2.0
+        if self.pmf == "learned" and self.wfit is not None:
+            V, C = self.index_tables(min_samples)
+            self.pi, self.tail = learned_distribution(V, C, self.r, self.eps)
+        else:
+            self.tail = geometric_tail(self.r, self.lmax)
+            self.pi = pmf_from_tail(self.tail)
+
+    def index_tables(self, min_samples: int = 8) -> Tuple[np.ndarray, np.ndarray]:
+        """V_tau and C_tau on the box: sample variance of Delta Q_tau and mean
+        measured work of a solve on rectangle tau where an index has at least
+        min_samples samples, the fitted laws elsewhere."""
+        n = self.lmax + 1
+        t = np.arange(n, dtype=float)
+        v0, beta = self.vfit
+        w0, gamma = self.wfit
+        V = 2.0 ** (v0 - beta[0] * t[:, None] - beta[1] * t[None, :])
+        C = 2.0 ** (w0 + gamma[0] * t[:, None] + gamma[1] * t[None, :])
+        for (a, b) in self.dq:
+            v = self.variance((a, b), min_samples)
+            if a < n and b < n and v > 0.0:
+                V[a, b] = v
+        for (a, b), (cnt, total) in self.work.items():
+            if a < n and b < n and cnt >= min_samples:
+                C[a, b] = total / cnt
+        return V, C
 
     def fit_gamma(self, min_samples: int = 8) -> np.ndarray:
         """gamma_j from log2 of the mean measured work of a sample at L
         against L (least squares), or the previous value while fewer than
         three independent indices have enough samples."""
         rows, vals = [], []
-        for (a, b), ws in self.work.items():
-            if len(ws) >= min_samples:
+        for (a, b), (cnt, total) in self.work.items():
+            if cnt >= min_samples:
                 rows.append((1.0, a, b))
-                vals.append(math.log2(float(np.mean(ws))))
+                vals.append(math.log2(total / cnt))
         if len(rows) < 3 or np.linalg.matrix_rank(np.array(rows)) < 3:
             return self.gamma
         coef, *_ = np.linalg.lstsq(np.array(rows), np.array(vals), rcond=None)
-        return np.clip(coef[1:], 0.5, 4.0)
+        gamma = np.clip(coef[1:], 0.5, 4.0)
+        self.wfit = (float(coef[0]), gamma)
+        return gamma
 
     def estimate(self) -> Tuple[float, float]:
-        y = np.asarray(self.ys)
-        n = len(y)
-        e = float(y.mean())
-        v = float(((y - e) ** 2).sum() / (n * (n - 1))) if n > 1 else float("inf")
-        return e, v
+        """E = mean of Y and V = sum (Y - E)^2 / (N (N - 1)), from the running
+        count, mean and sum of squared deviations of the Y's."""
+        n, e, m2 = self.ystat
+        return e, (m2 / (n * (n - 1)) if n > 1 else float("inf"))
 
     def run(self, tol: float, batch: int = 256, max_samples: int = 1 << 20) -> Estimate:
         """Draw batches until sqrt(V) <= tol (Algorithm MSG-MIMC)."""
@@ -238,4 +357,5 @@ class MSGMIMC:
             if math.sqrt(v) <= tol or len(self.ys) >= max_samples:
                 break
         return Estimate(e, v, len(self.ys), (float(self.r[0]), float(self.r[1])), self.batches,
-                        time.perf_counter() - t0, dict(self.counts), (float(self.gamma[0]), float(self.gamma[1])))
+                        time.perf_counter() - t0, dict(self.counts), (float(self.gamma[0]), float(self.gamma[1])),
+                        self.pmf)

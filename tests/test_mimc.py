@@ -146,6 +146,138 @@ def test_work_rates_are_fitted_from_the_cycle_counts():
     assert est2.gamma[0] > g1[0] + 0.5 and abs(est2.gamma[1] - g1[1]) < 0.3
 
 
+def _noisy_tables(seed, lmax):
+    rng = np.random.default_rng(seed)
+    t = np.arange(lmax + 1)
+    V = 2.0 ** (-3.1 * t[:, None] - 1.7 * t[None, :]) * np.exp(0.8 * rng.standard_normal((lmax + 1, lmax + 1)))
+    C = 2.0 ** (1.2 * t[:, None] + 1.4 * t[None, :]) * np.exp(0.3 * rng.standard_normal((lmax + 1, lmax + 1)))
+    return V, C
+
+
+def test_learned_pmf_is_geometric_under_product_laws():
+    """With V_tau = 2^(-beta.tau) and C_tau = 2^(gamma.tau) exactly, N_tau of
+    eq. Nell is prod exp(-r_j tau_j) with r_j = log(2)(beta_j + gamma_j)/2, so
+    the learned tail is the geometric one (the paper's derivation of the
+    geometric choice), whatever the mixing weight."""
+    beta, gamma, lmax = (3.3, 2.1), (1.3, 1.1), 6
+    r = [math.log(2) * (b + g) / 2 for b, g in zip(beta, gamma)]
+    V = {(a, b): 2.0 ** (-beta[0] * a - beta[1] * b) for a in range(lmax + 1) for b in range(lmax + 1)}
+    C = {(a, b): 2.0 ** (gamma[0] * a + gamma[1] * b) for a in range(lmax + 1) for b in range(lmax + 1)}
+    for eps in (0.0, 0.3):
+        pi, p = MO.learned_distribution(V, C, (0.5, 0.5) if eps == 0 else r, lmax, eps)
+        for k, x in MO.geometric_tail(r, lmax).items():
+            assert abs(p[k] - x) <= 1e-13
+        assert abs(pi[(0, 0)] - (1 - math.exp(-r[0])) * (1 - math.exp(-r[1]))) <= 1e-13
+        # capped at the box edge: P(L = (lmax, 0)) holds the mass beyond it
+        assert abs(pi[(lmax, 0)] - math.exp(-r[0] * lmax) * (1 - math.exp(-r[1]))) <= 1e-13
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_learned_pmf_is_a_distribution_with_its_own_tail(seed):
+    """On noisy tables (tails that are not those of any distribution): the
+    pmf is non-negative and sums to one, every index of the box has positive
+    probability (the geometric floor), p_0 = 1, p decreases in each
+    direction, and p is the tail of pi (inclusion-exclusion gives pi back)."""
+    lmax = 5
+    Va, Ca = _noisy_tables(seed, lmax)
+    V = {(a, b): Va[a, b] for a in range(lmax + 1) for b in range(lmax + 1)}
+    C = {(a, b): Ca[a, b] for a in range(lmax + 1) for b in range(lmax + 1)}
+    raw = MO.pmf_from_tail(MO.empirical_tail(V, C, lmax), lmax)
+    assert min(raw.values()) < 0           # the case the clipping is for
+    pi, p = MO.learned_distribution(V, C, (1.0, 1.0), lmax, 0.1)
+    assert min(pi.values()) > 0 and abs(sum(pi.values()) - 1) <= 1e-14
+    assert abs(p[(0, 0)] - 1) <= 1e-14
+    for (a, b), x in p.items():
+        if a > 0:
+            assert x <= p[(a - 1, b)] + 1e-15
+        if b > 0:
+            assert x <= p[(a, b - 1)] + 1e-15
+    back = MO.pmf_from_tail(p, lmax)
+    assert max(abs(back[k] - pi[k]) for k in pi) <= 1e-14
+
+
+def test_learned_pmf_unbiased_by_exact_enumeration():
+    """E[Y] = sum over L of pi(L) Y(L) equals the sum of the differences over
+    the box, for any valid pmf and its tail (the telescoping identity)."""
+    lmax = 5
+    Va, Ca = _noisy_tables(7, lmax)
+    V = {(a, b): Va[a, b] for a in range(lmax + 1) for b in range(lmax + 1)}
+    C = {(a, b): Ca[a, b] for a in range(lmax + 1) for b in range(lmax + 1)}
+    pi, p = MO.learned_distribution(V, C, (0.8, 1.9), lmax, 0.05)
+    rng = np.random.default_rng(4)
+    dq = {k: float(rng.standard_normal()) for k in pi}
+    ey = sum(pi[L] * MO.sample_y_tail(dq, L, p) for L in pi)
+    assert abs(ey - sum(dq.values())) <= 1e-12 * (1 + sum(abs(x) for x in dq.values()))
+
+
+def test_learned_pmf_host_arithmetic_matches_reference():
+    """The driver's vectorised pmf, tail and draws equal the reference's loops."""
+    lmax = 6
+    Va, Ca = _noisy_tables(11, lmax)
+    V = {(a, b): Va[a, b] for a in range(lmax + 1) for b in range(lmax + 1)}
+    C = {(a, b): Ca[a, b] for a in range(lmax + 1) for b in range(lmax + 1)}
+    r = np.array([1.1, 0.7])
+    pi_ref, p_ref = MO.learned_distribution(V, C, tuple(r), lmax, 0.1)
+    pi, p = M.learned_distribution(Va, Ca, r, 0.1)
+    for (a, b) in pi_ref:
+        assert abs(pi[a, b] - pi_ref[(a, b)]) <= 1e-15 and abs(p[a, b] - p_ref[(a, b)]) <= 1e-14
+    u = I.mimc_uniforms(3000, 5)[:, 0]
+    L = M.draw_indices_pmf(u, pi)
+    ref = np.array([MO.draw_index_pmf(pi_ref, lmax, float(x)) for x in u])
+    assert np.array_equal(L, ref)
+
+
+def test_learned_pmf_estimator_is_unbiased_with_fake_solves():
+    """The estimator with the learned pmf on fake solves whose differences
+    have known means (2^-(2a+b) times a unit-mean normal factor): the learned
+    distribution leaves the geometric one, and the estimate is within four
+    RMSE of the exact sum over the box."""
+    lmax = 5
+
+    def make(i, P, Q):
+        rng = np.random.default_rng(1000 + i)
+        n = (P + 1) * (Q + 1)
+        a = np.repeat(np.arange(P + 1), Q + 1)
+        b = np.tile(np.arange(Q + 1), P + 1)
+        d = 2.0 ** -(2 * a + b) * (1 + rng.standard_normal(n))
+        return d, 0, np.full(n, 4, dtype=np.int32)
+    est = _FakeSolves(make, lmax=lmax, r0=np.array([0.5, 0.5]), learn=True, pmf="learned")
+    res = est.run(tol=3e-2, batch=512)
+    exact = sum(2.0 ** -(2 * a + b) for a in range(lmax + 1) for b in range(lmax + 1))
+    assert res.pmf == "learned" and abs(res.E - exact) <= 4 * res.rmse
+    assert np.max(np.abs(est.tail - M.geometric_tail(est.r, lmax))) > 1e-3
+    assert abs(est.pi.sum() - 1) <= 1e-12 and est.pi.min() > 0
+
+
+def test_running_statistics_match_direct_ones():
+    """Per-index variances merged batch by batch, and E and V of the Y's,
+    equal the direct sample statistics of every value seen."""
+    seen = {}
+
+    def make(i, P, Q):
+        rng = np.random.default_rng(i)
+        n = (P + 1) * (Q + 1)
+        d = 3.0 + rng.standard_normal(n) * 0.1
+        for a in range(P + 1):
+            for b in range(Q + 1):
+                seen.setdefault((a, b), []).append(d[a * (Q + 1) + b])
+        return d, 0, np.full(n, 2, dtype=np.int32)
+    est = _FakeSolves(make, lmax=3, r0=np.array([0.6, 0.9]), learn=False)
+    for n in (17, 64, 5):
+        est.add_batch(n)
+    for k, xs in seen.items():
+        if len(xs) >= 2:
+            assert abs(est.variance(k, 2) - np.var(xs, ddof=1)) <= 1e-12 * np.var(xs, ddof=1)
+    e, v = est.estimate()
+    e_ref, v_ref = MO.estimate(est.ys)
+    assert abs(e - e_ref) <= 1e-13 * abs(e_ref) and abs(v - v_ref) <= 1e-10 * v_ref
+
+
+def test_pmf_option_is_checked():
+    with pytest.raises(ValueError):
+        _FakeSolves(lambda *a: None, pmf="uniform")
+
+
 @pytest.mark.gpu
 def test_batched_estimator_matches_reference_on_oracle_solutions():
     """Two batches of 24 samples, fixed rates, indices capped at 3: the GPU
