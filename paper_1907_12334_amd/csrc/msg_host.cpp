@@ -765,6 +765,17 @@ Split split_batch(const msg_batch_desc* batch, const msg_solve_opts* opts)
 
 namespace {
 
+// Debug switch read at every solve: MSG_DEBUG_SPLIT_SWEEPS=1 runs each
+// smoothing pass as its separate steps (correction, copy, one launch per
+// colour of every half-sweep) and restricts with k_restrict instead of the
+// fused restricting pass, so a test can compare the fused kernels with
+// their unfused definition bit for bit.  The on-chip tail is unchanged.
+bool split_sweeps()
+{
+    const char* t = std::getenv("MSG_DEBUG_SPLIT_SWEEPS");
+    return t && std::atoi(t) != 0;
+}
+
 // tuning overrides from the environment, read once per process (handles may
 // be created from several threads; sizes may be asked for before any handle)
 void read_env()
@@ -1103,6 +1114,7 @@ struct Ctx {
     int64_t kact;       // problems of the current class still cycling
     const KTail* tails; // device: per class of the level, [2 ci] cycle tail, [2 ci + 1] whole-class tail
     void* tpack;        // device: tail conductance images of the stage (type of the cycles)
+    bool split = false; // debug: smoothing passes as one launch per colour, no fused transfers
 };
 
 // algorithmic bytes: data a kernel must touch at least once per active problem
@@ -1290,7 +1302,39 @@ msg_status mu_cycle(const Ctx& X, const Group& G, int lev, Iter<T>& it, T* B, co
     // ns = 0 is a copy pass (no sweep).
     int flips = 0;
     int combine_in_tail = 0;        // the restriction into the tail's top level left two halves to average
+    // split-sweep debug mode: the correction (k_prolong) on the input
+    // buffer, a copy into the output buffer, then each half-sweep as one
+    // in-place launch per colour over whole grids
+    auto split_pass = [&](int ns, bool corr) -> msg_status {
+        T* vin = it.v[it.cur[lev]];
+        T* vout = it.v[1 - it.cur[lev]];
+        const T* vc = corr ? it.now(lev - 1) : nullptr;
+        for (const Member& e : G.m) {
+            const ClassPlan& C = *e.C;
+            const KLevel& P1 = C.pro[lev];
+            const KProb* pr = X.probs + C.first + e.sp.k0;
+            const int32_t* act = X.active + C.first + e.sp.k0;
+            msg_status r = timed(X, MSG_KERNEL_SMOOTH, level_bytes<T>(P1, 0, e.kact) * ns, [&] {
+                return chunked(P1, e.sp.kn, [&](int k0, int kn) -> hipError_t {
+                    hipError_t h = hipSuccess;
+                    if (corr)
+                        h = launch_prolong<T>(P1, kn, pr + k0, act + k0, X.c, (T)X.o->omega, vc, vin, KX, KY, X.s);
+                    if (h == hipSuccess)
+                        h = launch_rbgs<T>(0, C.rb[lev], kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, nullptr,
+                                           (T)X.o->omega, X.s);
+                    for (int sw = 0; sw < 2 * ns && h == hipSuccess; ++sw)
+                        h = launch_rb_colour<T>(P1, kn, pr + k0, act + k0, X.c, sw & 1, vout, B, KX, KY, X.s);
+                    return h;
+                });
+            });
+            if (r != MSG_OK) return r;
+        }
+        it.cur[lev] ^= 1;
+        ++flips;
+        return MSG_OK;
+    };
     auto pass = [&](int ns, bool corr) -> msg_status {
+        if (X.split && ns > 0) return split_pass(ns, corr);
         const T* vin = it.now(lev);
         T* vout = it.v[1 - it.cur[lev]];
         const T* vc = corr ? it.now(lev - 1) : nullptr;
@@ -1330,7 +1374,7 @@ msg_status mu_cycle(const Ctx& X, const Group& G, int lev, Iter<T>& it, T* B, co
         }
         return MSG_OK;
     };
-    if (g_fuse_restrict && g_fuse == 2 && X.o->nu1 == 2) {
+    if (g_fuse_restrict && g_fuse == 2 && X.o->nu1 == 2 && !X.split) {
         // pre-smoothing and the restriction of its residual in one pass, then
         // the coarse grids with two parents combine their halves
         {
@@ -1538,6 +1582,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
     X.chol = chol;
     X.prof = &ln.prof;
     X.kact = 0;
+    X.split = split_sweeps();
     double* a64b = (double*)(ws + W.a64b);
     float* a32b = mixed ? (float*)(ws + W.a32b) : nullptr;
     Iter<double> it64;

@@ -60,6 +60,16 @@ __device__ __forceinline__ T residual_at(const T* __restrict__ v, const T* __res
     return b[c] - (s.wW * (u - uW) + s.wE * (u - uE) + s.wS * (u - uS) + s.wN * (u - uN));
 }
 
+// One Gauss-Seidel update of a cell from its neighbours (zero beyond a wall):
+// the fused smoother and the one-colour kernel share this arithmetic, so the
+// two agree bit for bit.
+template <typename T>
+__device__ __forceinline__ T gs_update(const Stencil<T>& s, T b, T vW, T vE, T vS, T vN)
+{
+    const T num = b + s.wW * vW + s.wE * vE + s.wS * vS + s.wN * vN;
+    return num / (s.wW + s.wE + s.wS + s.wN);
+}
+
 // Weight factors (eq. weight_factors) in closed form: with f = (-1)^i,
 // (A f)_ij = (-1)^i [2 (kW + kE)/hx^2 + 2 k_wall/hy^2 on cells touching a
 // y-wall]; symmetrically for g = (-1)^j.  kappa_x = lx^2 / (lx^2 + ly^2).
@@ -475,9 +485,7 @@ k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ ac
                 const int i = xa + li;
                 const Stencil<T> st = stencil_at(kx, ky, nx, ny, i, j, ihx2, ihy2);
                 const int r = (j - j0 + Hy) * RW + (i - i0 + Hx);
-                const T num = b[(int64_t)j * nx + i] + st.wW * sv[r - 1] + st.wE * sv[r + 1] + st.wS * sv[r - RW] +
-                              st.wN * sv[r + RW];
-                sv[r] = num / (st.wW + st.wE + st.wS + st.wN);
+                sv[r] = gs_update(st, b[(int64_t)j * nx + i], sv[r - 1], sv[r + 1], sv[r - RW], sv[r + RW]);
             }
             __syncthreads();
         }
@@ -542,6 +550,35 @@ k_rbgs(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ ac
             }
         }
     }
+}
+
+// One colour of a red-black half-sweep over whole grids in global memory,
+// in place (cells of one colour have no neighbour of that colour), one
+// thread per cell.  Used only by the split-sweep debug mode, which runs the
+// fused passes as their separate steps to check them bit for bit.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_rb_colour(KLevel L, const KProb* __restrict__ probs, const int32_t* __restrict__ active, int c, int colour,
+            T* __restrict__ V, const T* __restrict__ B, const T* __restrict__ KX, const T* __restrict__ KY)
+{
+    const Where w = locate(L);
+    if (w.k < 0 || !active[w.k]) return;
+    const KGrid& G = L.g[w.gi];
+    const KProb pr = probs[w.k];
+    const int64_t cell = (int64_t)w.t * blockDim.x + threadIdx.x;
+    const int nx = G.nx, ny = G.ny;
+    if (cell >= (int64_t)nx * ny) return;
+    const int i = (int)(cell % nx), j = (int)(cell / nx);
+    if (((i + j) & 1) != colour) return;
+    T* v = V + pr.arena_base + G.aoff;
+    const T* kx = KX + pr.fx_base + xface_off(c, pr.Qs, G.p, G.q);
+    const T* ky = KY + pr.fy_base + yface_off(c, pr.Qs, G.p, G.q);
+    const Stencil<T> st = stencil_at(kx, ky, nx, ny, i, j, T(nx) * T(nx), T(ny) * T(ny));
+    const T vW = i > 0 ? v[cell - 1] : T(0);
+    const T vE = i < nx - 1 ? v[cell + 1] : T(0);
+    const T vS = j > 0 ? v[cell - nx] : T(0);
+    const T vN = j < ny - 1 ? v[cell + nx] : T(0);
+    v[cell] = gs_update(st, B[pr.arena_base + G.aoff + cell], vW, vE, vS, vN);
 }
 
 // The coarse grids with two parents after a restricting pass: b = average
@@ -1684,6 +1721,15 @@ hipError_t launch_rbgs_restrict(const KLevel& L, int K, const KProb* probs, cons
 }
 
 template <typename T>
+hipError_t launch_rb_colour(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, int colour,
+                            T* V, const T* B, const T* KX, const T* KY, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_rb_colour<T>), level_grid(L, K), dim3(threads_of(L)), 0, st, with_blocks(L, K), probs,
+                       active, c, colour, V, B, KX, KY);
+    return LAUNCH_CHECK();
+}
+
+template <typename T>
 hipError_t launch_restrict_combine(const KLevel& L, int K, const KProb* probs, const int32_t* active, T* Vc, T* B,
                                    hipStream_t st)
 {
@@ -1871,6 +1917,10 @@ template hipError_t launch_rbgs_restrict<double>(const KLevel&, int, const KProb
                                                 double*, double*, const double*, const double*, double*, hipStream_t);
 template hipError_t launch_rbgs_restrict<float>(const KLevel&, int, const KProb*, const int32_t*, int, const float*,
                                                float*, float*, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_rb_colour<double>(const KLevel&, int, const KProb*, const int32_t*, int, int, double*,
+                                             const double*, const double*, const double*, hipStream_t);
+template hipError_t launch_rb_colour<float>(const KLevel&, int, const KProb*, const int32_t*, int, int, float*,
+                                            const float*, const float*, const float*, hipStream_t);
 template hipError_t launch_restrict_combine<double>(const KLevel&, int, const KProb*, const int32_t*, double*, double*,
                                                     hipStream_t);
 template hipError_t launch_restrict_combine<float>(const KLevel&, int, const KProb*, const int32_t*, float*, float*,

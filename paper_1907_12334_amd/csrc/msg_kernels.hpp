@@ -63,6 +63,11 @@ hipError_t launch_rbgs_restrict(const KLevel& L, int K, const KProb* probs, cons
 template <typename T>
 hipError_t launch_restrict_combine(const KLevel& L, int K, const KProb* probs, const int32_t* active, T* Vc, T* B,
                                    hipStream_t st);
+// one colour of a red-black half-sweep in place in global memory (L: one
+// thread per cell; the split-sweep debug mode)
+template <typename T>
+hipError_t launch_rb_colour(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, int colour,
+                            T* V, const T* B, const T* KX, const T* KY, hipStream_t st);
 template <typename T>
 hipError_t launch_restrict(bool rhs, const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
                            const T* Vf, T* Vc, T* B, const T* KX, const T* KY, hipStream_t st);

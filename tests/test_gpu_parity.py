@@ -201,6 +201,31 @@ def test_graph_replay_matches_launches(handle, precision, overlap):
         assert np.array_equal(out[k], ref[k]), k
 
 
+@pytest.mark.parametrize("precision,cycle", [(msg.FP64, (2, 2, 2)), (msg.FP64, (1, 1, 3)), (msg.MIXED, (2, 2, 2))])
+def test_fused_passes_match_split_sweeps_bitwise(handle, monkeypatch, precision, cycle):
+    """The fused smoothing passes (tiles with recomputed halos in LDS, the
+    correction applied in the load, the residual restricted in the
+    pre-smoothing pass) against the debug mode that runs every step on its
+    own: the correction kernel, then one in-place launch per colour of every
+    half-sweep over whole grids, then the plain restriction kernel.  Same
+    bits, on a batch whose levels above the tail are several tiles wide."""
+    mu, nu1, nu2 = cycle
+    c, spec = 2, I.separable(0.3, 0.03, 1.0, m=20)
+    P, Q = [6] * 3 + [5] * 3 + [3] * 2, [5] * 3 + [6] * 3 + [3] * 2
+    xi = I.draw_xi(spec.n_terms, range(len(P)))
+    tol = 1e-10 if precision == msg.FP64 else 1e-8
+    opts = msg.SolveOpts(mu=mu, nu1=nu1, nu2=nu2, tol=tol, max_cycles=400, precision=precision, handoff=0,
+                         tail_levels=2)
+    monkeypatch.delenv("MSG_DEBUG_SPLIT_SWEEPS", raising=False)
+    ref = PR.gpu_solve(c, P, Q, spec, xi, opts, handle=handle)
+    monkeypatch.setenv("MSG_DEBUG_SPLIT_SWEEPS", "1")
+    out = PR.gpu_solve(c, P, Q, spec, xi, opts, handle=handle)
+    monkeypatch.delenv("MSG_DEBUG_SPLIT_SWEEPS")
+    assert np.all(ref["status"] == 0) and ref["cycles"].max() >= 3
+    for k in ("u", "q", "dq", "cycles", "status"):
+        assert np.array_equal(out[k], ref[k]), k
+
+
 def test_ragged_batch_and_batch_invariance(handle):
     rng = np.random.default_rng(5)
     P = rng.integers(0, 5, size=12)
