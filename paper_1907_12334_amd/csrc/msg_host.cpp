@@ -142,6 +142,7 @@ int g_handoff = 1024;        // hand a class's last cycling problems to one kern
 int g_solve_lds = 65536;     // LDS budget under which a class is solved entirely in one kernel
 bool g_tail_table = true;    // tails smooth from a red-black slot table (false: decode every slot)
 bool g_fuse_restrict = true; // pre-smoothing passes of nu1 = 2 also restrict their residual
+bool g_fuse_visits = true;   // consecutive W-cycle visits of a level share one pass (see mu_cycle)
 bool g_debug_stages = false; // per-level timing on stderr
 constexpr size_t kWideTailLds = (size_t)40 * 1024;      // tails above this run on four wavefronts
 constexpr int kMaxGroups = kMaxIndex + 1;               // lockstep groups of one stage (at most its classes)
@@ -209,6 +210,8 @@ struct ClassPlan {
     std::vector<KLevel> rb, rbc, pro, res;   // per level: smoother tiles (rbc: with the correction's
                                              // children), prolongation, restriction into level-1
     std::vector<KLevel> rbr;                 // per level: the restricting pre-smoothing pass
+    std::vector<KLevel> rbcr;                // per level: post-smoothing of one W-cycle visit and the
+                                             // restricting pre-smoothing of the next, fused (may be empty)
     int64_t part0 = 0;             // first partial-sum slot
     int64_t tpack = -1;            // element offset of the class's tail conductance images, -1 if none
     std::vector<int> samples;
@@ -454,6 +457,11 @@ ClassPlan plan_class(int c, int pc, int qc, std::vector<int> samples, const msg_
     C.pro.resize(L + 1);
     C.res.resize(L + 1);
     C.rbr.resize(L + 1);
+    // the fused pair of passes has a halo of 2 (2 + 2) + 1 cells: tiles of
+    // up to twice the LDS of the plain passes keep its halo share moderate
+    Tuning tu2 = tu;
+    tu2.tile_lds = std::min(kRbgsLdsMax, std::max(2 * tu.tile_lds, 4096));
+    if (g_fuse == 2) C.rbcr.resize(L + 1);
     for (int lev = 1; lev <= L; ++lev) {
         C.rb[lev] = level_rbgs(c, pc, qc, lev, C.goff, H, tu);
         C.rbr[lev] = level_rbgs_restrict(c, pc, qc, lev, C.goff, H, tu);
@@ -465,6 +473,7 @@ ClassPlan plan_class(int c, int pc, int qc, std::vector<int> samples, const msg_
         }
         C.pro[lev] = level_1d(c, pc, qc, lev, C.goff, 1, qc, -1);
         C.res[lev] = level_1d(c, pc, qc, lev - 1, C.goff, 2, qc, -1);
+        if (g_fuse == 2) C.rbcr[lev] = level_rbgs_restrict(c, pc, qc, lev, C.goff, 2 * H, tu2);
     }
     return C;
 }
@@ -794,6 +803,7 @@ void read_env()
         if (const char* t = std::getenv("MSG_PARTS")) g_parts = std::max(2, std::min(kMaxParts, std::atoi(t)));
         if (const char* t = std::getenv("MSG_TAIL_TABLE")) g_tail_table = std::atoi(t) != 0;
         if (const char* t = std::getenv("MSG_FUSE_RESTRICT")) g_fuse_restrict = std::atoi(t) != 0;
+        if (const char* t = std::getenv("MSG_FUSE_VISITS")) g_fuse_visits = std::atoi(t) != 0;
     });
 }
 
@@ -1264,8 +1274,17 @@ Group single_group(const ClassPlan& C, const Span& sp, int64_t kact)
     return G;
 }
 
+// Flags of one W-cycle visit of a level (mu_cycle below).  In a W-cycle the
+// post-smoothing pass of one visit of a level and the pre-smoothing pass of
+// the next visit follow each other with nothing in between (the parent level
+// calls its coarse cycle mu times in a row); such a pair runs as one pass.
+constexpr int kLeavePost = 1;   // end without the correction and post-smoothing (the next visit applies them)
+constexpr int kFusedPre = 2;    // start with the previous visit's correction and post-smoothing, fused
+                                // with this visit's pre-smoothing and restriction
+
 template <typename T>
-msg_status mu_cycle(const Ctx& X, const Group& G, int lev, Iter<T>& it, T* B, const T* KX, const T* KY)
+msg_status mu_cycle(const Ctx& X, const Group& G, int lev, Iter<T>& it, T* B, const T* KX, const T* KY,
+                    int flags = 0)
 {
     msg_status st;
     const int M = G.tail_top, Lstage = G.m[0].C->L;
@@ -1374,27 +1393,39 @@ msg_status mu_cycle(const Ctx& X, const Group& G, int lev, Iter<T>& it, T* B, co
         }
         return MSG_OK;
     };
+    const bool fused_pre = (flags & kFusedPre) != 0;
     if (g_fuse_restrict && g_fuse == 2 && X.o->nu1 == 2 && !X.split) {
         // pre-smoothing and the restriction of its residual in one pass, then
-        // the coarse grids with two parents combine their halves
+        // the coarse grids with two parents combine their halves.  Fused with
+        // the previous visit's correction and post-smoothing, the restricted
+        // values go to the coarse buffer that does not hold the correction
+        // being read (other tiles of the same launch still read it).
+        const int tb = fused_pre ? 1 - it.cur[lev - 1] : 0;
         {
             const T* vin = it.now(lev);
             T* vout = it.v[1 - it.cur[lev]];
-            T* vc = it.v[0];
+            T* vco = it.v[tb];
+            const T* ve = fused_pre ? it.now(lev - 1) : nullptr;
             for (const Member& e : G.m) {
                 const ClassPlan& C = *e.C;
-                const KLevel& L = C.rbr[lev];
+                const KLevel& L = fused_pre ? C.rbcr[lev] : C.rbr[lev];
                 const KProb* pr = X.probs + C.first + e.sp.k0;
                 const int32_t* act = X.active + C.first + e.sp.k0;
+                const double bytes = level_bytes<T>(L, 0, e.kact) + level_bytes<T>(L, 5, e.kact) +
+                                     (fused_pre ? level_bytes<T>(L, 3, e.kact) : 0.0);
                 st = timed(
-                    X, MSG_KERNEL_SMOOTH, level_bytes<T>(L, 0, e.kact) + level_bytes<T>(L, 5, e.kact),
+                    X, MSG_KERNEL_SMOOTH, bytes,
                     [&] {
                         return chunked(L, e.sp.kn, [&](int k0, int kn) {
-                            return launch_rbgs_restrict<T>(L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, vc,
+                            if (fused_pre)
+                                return launch_rbgs_corr_restrict<T>(L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX,
+                                                                    KY, ve, (T)X.o->omega, vco, X.s);
+                            return launch_rbgs_restrict<T>(L, kn, pr + k0, act + k0, X.c, vin, vout, B, KX, KY, vco,
                                                            X.s);
                         });
                     },
-                    lev == Lstage ? MSG_KERNEL_SMOOTH_STAGE : -1, false, model_bytes<T>(L, 15.0, e.kact));
+                    lev == Lstage ? MSG_KERNEL_SMOOTH_STAGE : -1, false,
+                    model_bytes<T>(L, fused_pre ? 30.0 : 15.0, e.kact));
                 if (st != MSG_OK) return st;
             }
             it.cur[lev] ^= 1;
@@ -1404,9 +1435,9 @@ msg_status mu_cycle(const Ctx& X, const Group& G, int lev, Iter<T>& it, T* B, co
         // halves instead
         if (lev - 1 <= M) {
             combine_in_tail = 1;
-            it.cur[lev - 1] = 0;
+            it.cur[lev - 1] = tb;
         } else {
-            T* vc = it.v[0];
+            T* vc = it.v[tb];
             for (const Member& e : G.m) {
                 const ClassPlan& C = *e.C;
                 const KLevel& R = C.res[lev];
@@ -1422,7 +1453,7 @@ msg_status mu_cycle(const Ctx& X, const Group& G, int lev, Iter<T>& it, T* B, co
                     lev == Lstage ? MSG_KERNEL_RESTRICT_STAGE : -1);
                 if (st != MSG_OK) return st;
             }
-            it.cur[lev - 1] = 0;
+            it.cur[lev - 1] = tb;
         }
     } else {
         if ((st = smooth(X.o->nu1, false)) != MSG_OK) return st;
@@ -1448,9 +1479,18 @@ msg_status mu_cycle(const Ctx& X, const Group& G, int lev, Iter<T>& it, T* B, co
     if (lev - 1 <= M) {
         if ((st = tail(X.o->mu, combine_in_tail)) != MSG_OK) return st;
     } else {
-        for (int m = 0; m < X.o->mu; ++m)
-            if ((st = mu_cycle<T>(X, G, lev - 1, it, B, KX, KY)) != MSG_OK) return st;
+        // consecutive visits of level lev-1 share their boundary pass when
+        // it is a two-sweep post-smoothing followed by a two-sweep restricting
+        // pre-smoothing and every member planned the fused tiles
+        bool pair = g_fuse_visits && g_fuse_restrict && g_fuse == 2 && X.o->nu1 == 2 && X.o->nu2 == 2 && !X.split;
+        for (const Member& e : G.m)
+            pair = pair && (int)e.C->rbcr.size() > lev - 1 && e.C->rbcr[lev - 1].ngrids > 0;
+        for (int m = 0; m < X.o->mu; ++m) {
+            const int f = pair ? ((m > 0 ? kFusedPre : 0) | (m + 1 < X.o->mu ? kLeavePost : 0)) : 0;
+            if ((st = mu_cycle<T>(X, G, lev - 1, it, B, KX, KY, f)) != MSG_OK) return st;
+        }
     }
+    if (flags & kLeavePost) return MSG_OK;         // the next visit applies them, fused
     if (X.o->nu2 > 0) {
         if ((st = smooth(X.o->nu2, true)) != MSG_OK) return st;      // correction fused into the first pass
     } else {

@@ -428,6 +428,11 @@ __device__ __forceinline__ T correction_at(const KGrid& G, const KProb& pr, int 
 }
 
 //
+// CORR and RS with NS = 4: the post-smoothing pass of one W-cycle visit of a
+// level and the pre-smoothing pass of the next visit, which follow each
+// other with nothing in between, as one pass (the restricted values go to
+// the coarse iterate buffer that does not hold the correction being read).
+//
 // RS (with NS = 2, no correction): the pre-smoothing pass also forms the
 // residual of its tile's cells and restricts it into level l-1 (eq.
 // restriction), so the iterate, right-hand side and conductances are not read
@@ -1721,6 +1726,23 @@ hipError_t launch_rbgs_restrict(const KLevel& L, int K, const KProb* probs, cons
 }
 
 template <typename T>
+hipError_t launch_rbgs_corr_restrict(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
+                                     const T* Vin, T* Vout, T* B, const T* KX, const T* KY, const T* Vc, T omega,
+                                     T* Vco, hipStream_t st)
+{
+    const dim3 grid = level_grid(L, K);
+    const KLevel Lb = with_blocks(L, K);
+    const size_t lds = sizeof(T) * (size_t)L.lds;
+    if (L.bs == 64)
+        hipLaunchKernelGGL((k_rbgs<T, 4, true, 64, true>), grid, dim3(64), lds, st, Lb, probs, active, c, Vin, Vout, B,
+                           KX, KY, Vc, omega, B, Vco);
+    else
+        hipLaunchKernelGGL((k_rbgs<T, 4, true, kBlock, true>), grid, dim3(kBlock), lds, st, Lb, probs, active, c, Vin,
+                           Vout, B, KX, KY, Vc, omega, B, Vco);
+    return LAUNCH_CHECK();
+}
+
+template <typename T>
 hipError_t launch_rb_colour(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c, int colour,
                             T* V, const T* B, const T* KX, const T* KY, hipStream_t st)
 {
@@ -1917,6 +1939,12 @@ template hipError_t launch_rbgs_restrict<double>(const KLevel&, int, const KProb
                                                 double*, double*, const double*, const double*, double*, hipStream_t);
 template hipError_t launch_rbgs_restrict<float>(const KLevel&, int, const KProb*, const int32_t*, int, const float*,
                                                float*, float*, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_rbgs_corr_restrict<double>(const KLevel&, int, const KProb*, const int32_t*, int,
+                                                      const double*, double*, double*, const double*, const double*,
+                                                      const double*, double, double*, hipStream_t);
+template hipError_t launch_rbgs_corr_restrict<float>(const KLevel&, int, const KProb*, const int32_t*, int,
+                                                     const float*, float*, float*, const float*, const float*,
+                                                     const float*, float, float*, hipStream_t);
 template hipError_t launch_rb_colour<double>(const KLevel&, int, const KProb*, const int32_t*, int, int, double*,
                                              const double*, const double*, const double*, hipStream_t);
 template hipError_t launch_rb_colour<float>(const KLevel&, int, const KProb*, const int32_t*, int, int, float*,

@@ -63,6 +63,13 @@ hipError_t launch_rbgs_restrict(const KLevel& L, int K, const KProb* probs, cons
 template <typename T>
 hipError_t launch_restrict_combine(const KLevel& L, int K, const KProb* probs, const int32_t* active, T* Vc, T* B,
                                    hipStream_t st);
+// the post-smoothing pass of one W-cycle visit (correction from Vc, two
+// sweeps) and the restricting pre-smoothing pass of the next visit (two
+// sweeps, residual restricted into Vco and B) as one pass
+template <typename T>
+hipError_t launch_rbgs_corr_restrict(const KLevel& L, int K, const KProb* probs, const int32_t* active, int c,
+                                     const T* Vin, T* Vout, T* B, const T* KX, const T* KY, const T* Vc, T omega,
+                                     T* Vco, hipStream_t st);
 // one colour of a red-black half-sweep in place in global memory (L: one
 // thread per cell; the split-sweep debug mode)
 template <typename T>
