@@ -143,6 +143,7 @@ int g_solve_lds = 65536;     // LDS budget under which a class is solved entirel
 bool g_tail_table = true;    // tails smooth from a red-black slot table (false: decode every slot)
 bool g_fuse_restrict = true; // pre-smoothing passes of nu1 = 2 also restrict their residual
 bool g_fuse_visits = true;   // consecutive W-cycle visits of a level share one pass (see mu_cycle)
+int g_cr_tw = 0, g_cr_cells = 0, g_cr_lds = 0;   // tiles of that shared pass (0: derived from the plain ones)
 bool g_debug_stages = false; // per-level timing on stderr
 constexpr size_t kWideTailLds = (size_t)40 * 1024;      // tails above this run on four wavefronts
 constexpr int kMaxGroups = kMaxIndex + 1;               // lockstep groups of one stage (at most its classes)
@@ -457,10 +458,13 @@ ClassPlan plan_class(int c, int pc, int qc, std::vector<int> samples, const msg_
     C.pro.resize(L + 1);
     C.res.resize(L + 1);
     C.rbr.resize(L + 1);
-    // the fused pair of passes has a halo of 2 (2 + 2) + 1 cells: tiles of
-    // up to twice the LDS of the plain passes keep its halo share moderate
+    // the fused pair of passes has a halo of 2 (2 + 2) + 1 cells: tiles twice
+    // as wide and twice as large as the plain passes' keep its halo share
+    // moderate (128 x 16 cells and 39 KB of LDS at the default plan)
     Tuning tu2 = tu;
-    tu2.tile_lds = std::min(kRbgsLdsMax, std::max(2 * tu.tile_lds, 4096));
+    tu2.tile_w = g_cr_tw > 0 ? g_cr_tw : std::min(256, 2 * tu.tile_w);
+    tu2.tile_cells = g_cr_cells > 0 ? g_cr_cells : std::min(4096, 2 * tu.tile_cells);
+    tu2.tile_lds = std::min(kRbgsLdsMax, g_cr_lds > 0 ? g_cr_lds : std::max(4 * tu.tile_lds, 4096));
     if (g_fuse == 2) C.rbcr.resize(L + 1);
     for (int lev = 1; lev <= L; ++lev) {
         C.rb[lev] = level_rbgs(c, pc, qc, lev, C.goff, H, tu);
@@ -804,6 +808,9 @@ void read_env()
         if (const char* t = std::getenv("MSG_TAIL_TABLE")) g_tail_table = std::atoi(t) != 0;
         if (const char* t = std::getenv("MSG_FUSE_RESTRICT")) g_fuse_restrict = std::atoi(t) != 0;
         if (const char* t = std::getenv("MSG_FUSE_VISITS")) g_fuse_visits = std::atoi(t) != 0;
+        if (const char* t = std::getenv("MSG_CR_TW")) g_cr_tw = std::max(4, std::min(256, std::atoi(t)));
+        if (const char* t = std::getenv("MSG_CR_CELLS")) g_cr_cells = std::max(64, std::min(4096, std::atoi(t)));
+        if (const char* t = std::getenv("MSG_CR_LDS")) g_cr_lds = std::max(1024, std::min(kRbgsLdsMax, std::atoi(t)));
     });
 }
 
