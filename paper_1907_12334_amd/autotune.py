@@ -29,6 +29,11 @@ TILES: Tuple[Tuple[int, int, int], ...] = ((64, 1024, 2048), (32, 512, 2048), (6
 TAIL_BUDGETS: Tuple[int, ...] = (20480, 12288, 28672, 40960)
 
 
+# wider tail budgets, for batches of few problems per class (ragged batches,
+# the request loop), where each level kept on chip saves host level visits
+WIDE_TAIL_BUDGETS: Tuple[int, ...] = (20480, 40960, 65536, 102400, 153600)
+
+
 def shape_key(w: I.Workload, samples: int, precision: int) -> str:
     return (f"c{w.c}-P{min(w.P)}..{max(w.P)}-Q{min(w.Q)}..{max(w.Q)}-S{samples}-"
             f"{'mixed' if precision == msg.MIXED else 'fp64'}")
@@ -52,10 +57,14 @@ def _trial(h, w: I.Workload, opts: msg.SolveOpts, xi, reps: int) -> float:
 
 
 def autotune(h: msg.Handle, w: I.Workload, opts: msg.SolveOpts, samples: int = 1024, cycles: int = 2,
-             reps: int = 2, cache: Optional[str] = None, log=None, margin: float = 0.02) -> Tuple[msg.SolveOpts, dict]:
+             reps: int = 2, cache: Optional[str] = None, log=None, margin: float = 0.02,
+             budgets: Sequence[int] = TAIL_BUDGETS, overlaps: Sequence[int] = ()) -> Tuple[msg.SolveOpts, dict]:
     """Returns (opts with the fastest plan parameters, report).  A candidate
     replaces the current choice only when it is faster by more than `margin`
-    (relative), so timing noise does not move the plan off the defaults."""
+    (relative), so timing noise does not move the plan off the defaults.
+    `budgets` are the tail budgets tried (the first is the starting point);
+    `overlaps`, if given, the overlap modes tried last (results do not depend
+    on them either)."""
     import torch
     sub = w.subset(min(samples, w.n_samples))
     key = shape_key(w, sub.n_samples, opts.precision)
@@ -77,7 +86,7 @@ def autotune(h: msg.Handle, w: I.Workload, opts: msg.SolveOpts, samples: int = 1
             log(f"autotune {params}: {t:.3f} s")
         return t
 
-    best_params = {"tail_budget": TAIL_BUDGETS[0], "tile_width": TILES[0][0], "tile_cells": TILES[0][1],
+    best_params = {"tail_budget": budgets[0], "tile_width": TILES[0][0], "tile_cells": TILES[0][1],
                    "tile_lds": TILES[0][2]}
     best = run(best_params)
     for tw, cells, lds in TILES[1:]:
@@ -85,11 +94,19 @@ def autotune(h: msg.Handle, w: I.Workload, opts: msg.SolveOpts, samples: int = 1
         t = run(p)
         if t < best * (1.0 - margin):
             best, best_params = t, p
-    for tb in TAIL_BUDGETS[1:]:
+    for tb in budgets[1:]:
         p = dict(best_params, tail_budget=tb)
         t = run(p)
         if t < best * (1.0 - margin):
             best, best_params = t, p
+    if overlaps:
+        best_params = dict(best_params, overlap=overlaps[0])
+        best = run(best_params)
+        for ov in overlaps[1:]:
+            p = dict(best_params, overlap=ov)
+            t = run(p)
+            if t < best * (1.0 - margin):
+                best, best_params = t, p
     report = {"key": key, "params": best_params, "seconds": round(best, 4), "samples": sub.n_samples,
               "cycles_per_trial": cycles, "margin": margin, "trials": trials, "cached": False}
     if cache:
