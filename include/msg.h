@@ -266,7 +266,8 @@ msg_status mimc_delta_q(const msg_batch_desc *batch, const double *d_q, double *
  * (which holds every face midpoint of every grid (p,q) <= (P,Q), so all grids
  * of a sample see one realisation) from a periodic embedding enlarged by
  * m = 1 + 2 ceil(sqrt(nu) log2(max(c 2^P, c 2^Q))) per direction (or `pad`),
- * rounded up to a power of two of at most 8192 points per direction.  The
+ * rounded up to a power of two of at most 32768 points per direction (rows
+ * above 8192 points, beyond one workgroup's LDS, run as the four-step FFT).  The
  * normals come from Philox4x64-10 with counter (frequency pair, sample id,
  * 0, 0) and key (seed, 0x6D617465726E), through u = ((w >> 12) + 1/2) 2^-52
  * and the Box-Muller transform.
@@ -280,7 +281,7 @@ msg_status mimc_delta_q(const msg_batch_desc *batch, const double *d_q, double *
  * Workspace: msg_matern_workspace_size bytes hold chunks of up to 8 samples;
  * any size that holds one sample of the largest embedding works, in more
  * chunks.  Errors: MSG_ERR_ARG, MSG_ERR_LAYOUT, MSG_ERR_UNSUPPORTED (an
- * embedding above 8192 points per direction), MSG_ERR_WORKSPACE.  Enqueued
+ * embedding above 32768 points per direction), MSG_ERR_WORKSPACE.  Enqueued
  * on `stream`. */
 typedef struct {
     double lambda;             /* length scale, > 0 */

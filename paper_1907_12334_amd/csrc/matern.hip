@@ -25,6 +25,8 @@
 
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "matern_kernels.hpp"
 #include "msg_device.hpp"
 #include "philox.hpp"
@@ -134,6 +136,28 @@ k_fft_rows(int64_t rows, int logn, int tw_stride, const double2* __restrict__ tw
         __syncthreads();
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x) x[i] = buf[i];
+}
+
+// Rows longer than one workgroup's LDS holds (four-step FFT, Bailey 1990):
+// a row of N = N1 N2 points, x[N2 n1 + n2], is an N1 x N2 matrix; after the
+// transpose to [n2][n1] and length-N1 FFTs of its rows, entry [n2][k1] is
+// multiplied by exp(-2 pi i n2 k1 / N); after the transpose to [k1][n2] and
+// length-N2 FFTs, entry [k1][k2] holds X[k1 + N1 k2], and a last transpose
+// puts it in natural order.  This kernel is the twiddle step, over
+// rows x N2 x N1 entries.
+__global__ void __launch_bounds__(256)
+k_fft_twiddle(int64_t total, int logn, int h1, double2* __restrict__ X)
+{
+    const int64_t N = (int64_t)1 << logn;
+    const int64_t n1mask = ((int64_t)1 << h1) - 1;
+    const int64_t n2mask = (N >> h1) - 1;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k1 = e & n1mask, n2 = (e >> h1) & n2mask;
+        const int64_t m = (n2 * k1) & (N - 1);
+        double s, c;
+        sincospi(-2.0 * (double)m / (double)N, &s, &c);
+        X[e] = cmul(X[e], make_double2(c, s));
+    }
 }
 
 // out[s][c][r] = in[s][r][c] for R x C complex matrices, 32 x 32 tiles
@@ -291,6 +315,36 @@ hipError_t launch_transpose(int K, int R, int C, const double2* in, double2* out
 {
     hipLaunchKernelGGL(k_transpose, dim3((C + 31) / 32, (R + 31) / 32, K), dim3(32, 8), 0, st, R, C, in, out);
     return LAUNCH_CHECK();
+}
+
+// K matrices of R x C, in slices of at most 32768 (the grid's z limit)
+static hipError_t transpose_many(int64_t K, int R, int C, const double2* in, double2* out, hipStream_t st)
+{
+    const int64_t per = (int64_t)R * C;
+    for (int64_t k0 = 0; k0 < K; k0 += 32768) {
+        const int kn = (int)std::min<int64_t>(32768, K - k0);
+        hipError_t e = launch_transpose(kn, R, C, in + k0 * per, out + k0 * per, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_fft_rows_long(int64_t rows, int logn, int h1, int tw_log, const double2* tw, double2* X,
+                                double2* S, hipStream_t st)
+{
+    const int h2 = logn - h1;
+    const int N1 = 1 << h1, N2 = 1 << h2;
+    const int64_t total = rows << logn;
+    hipError_t e;
+    if ((e = transpose_many(rows, N1, N2, X, S, st)) != hipSuccess) return e;               // [n2][n1]
+    if ((e = launch_fft_rows(rows * N2, h1, (1 << tw_log) >> h1, tw, S, st)) != hipSuccess) return e;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, (int64_t)1 << 20);
+    hipLaunchKernelGGL(k_fft_twiddle, dim3((unsigned)blocks), dim3(256), 0, st, total, logn, h1, S);
+    if ((e = LAUNCH_CHECK()) != hipSuccess) return e;
+    if ((e = transpose_many(rows, N2, N1, S, X, st)) != hipSuccess) return e;               // [k1][n2]
+    if ((e = launch_fft_rows(rows * N1, h2, (1 << tw_log) >> h2, tw, X, st)) != hipSuccess) return e;
+    if ((e = transpose_many(rows, N1, N2, X, S, st)) != hipSuccess) return e;               // [k2][k1]
+    return hipMemcpyAsync(X, S, sizeof(double2) * (size_t)total, hipMemcpyDeviceToDevice, st);
 }
 
 hipError_t launch_eig_ratio(int K, int64_t M, int nb, const double2* L, double2* part, const int32_t* out_index,

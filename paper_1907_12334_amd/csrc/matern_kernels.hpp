@@ -18,6 +18,10 @@ hipError_t launch_mat_row(int K, int Mx, int My, double hx, double hy, double nu
                           const MaternSample* smp, double2* A, hipStream_t st);
 hipError_t launch_fft_rows(int64_t rows, int logn, int tw_stride, const double2* tw, double2* X, hipStream_t st);
 hipError_t launch_transpose(int K, int R, int C, const double2* in, double2* out, hipStream_t st);
+// FFTs of rows of 2^logn points as 2^h1 x 2^(logn-h1) (four-step; both
+// factors at most one workgroup's row length); S: scratch of the same size
+hipError_t launch_fft_rows_long(int64_t rows, int logn, int h1, int tw_log, const double2* tw, double2* X,
+                                double2* S, hipStream_t st);
 hipError_t launch_eig_ratio(int K, int64_t M, int nb, const double2* L, double2* part, const int32_t* out_index,
                             double* ratio, hipStream_t st);
 hipError_t launch_mat_xi(int K, int Mx, int My, uint64_t seed, uint64_t key1, const MaternSample* smp, double2* LT,

@@ -2377,7 +2377,8 @@ extern "C" msg_status msg_cycles(msg_handle h, const msg_batch_desc* batch, cons
 namespace {
 
 constexpr uint64_t kMaternKey1 = 0x6D617465726Eull;
-constexpr int kMaternMaxLog = 13;        // rows of up to 8192 points: one row in 128 KB of LDS
+constexpr int kMaternRowLog = 13;        // rows of up to 8192 points in one workgroup (128 KB of LDS)
+constexpr int kMaternMaxLog = 15;        // longer rows (up to 32768 points) by the four-step FFT
 constexpr int kMaternChunk = 8;          // samples per chunk at the suggested workspace size
 constexpr int kMaternBlocks = 256;       // partial min/max blocks per sample
 
@@ -2412,8 +2413,8 @@ msg_status check_matern(const msg_batch_desc* batch, const msg_matern_spec* sp)
         int lx, ly;
         matern_shape(batch->c, batch->P[s], batch->Q[s], sp->nu, sp->pad, lx, ly);
         if (lx > kMaternMaxLog || ly > kMaternMaxLog)
-            return fail(MSG_ERR_UNSUPPORTED, "sample %d: embedding of 2^%d x 2^%d points exceeds 8192 per direction", s,
-                        lx, ly);
+            return fail(MSG_ERR_UNSUPPORTED, "sample %d: embedding of 2^%d x 2^%d points exceeds 32768 per direction",
+                        s, lx, ly);
     }
     return MSG_OK;
 }
@@ -2526,7 +2527,18 @@ extern "C" msg_status msg_sample_matern(msg_handle h, const msg_matern_spec* sp,
     auto chk = [&](hipError_t e, const char* what) -> msg_status {
         return e == hipSuccess ? MSG_OK : fail(MSG_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
     };
-    if ((st = chk(launch_mat_twiddles(1 << lmax, tw, s), "twiddles")) != MSG_OK) return st;
+    // rows longer than one workgroup holds run as the four-step FFT
+    // (MSG_MATERN_ROW_LOG lowers that length, for tests of the long-row path)
+    int row_log = kMaternRowLog;
+    // (at least half the longest row's log, so that both factors fit one workgroup)
+    if (const char* t = std::getenv("MSG_MATERN_ROW_LOG"))
+        row_log = std::max((kMaternMaxLog + 1) / 2, std::min(kMaternRowLog, std::atoi(t)));
+    const int tw_log = std::min(lmax, row_log);
+    auto fft = [&](int64_t rows, int logn, double2* X, double2* scratch) -> hipError_t {
+        if (logn <= row_log) return launch_fft_rows(rows, logn, (1 << tw_log) >> logn, tw, X, s);
+        return launch_fft_rows_long(rows, logn, (logn + 1) / 2, tw_log, tw, X, scratch, s);
+    };
+    if ((st = chk(launch_mat_twiddles(1 << tw_log, tw, s), "twiddles")) != MSG_OK) return st;
     const double coef = std::pow(2.0, 1.0 - sp->nu) / std::tgamma(sp->nu);
     int first = 0;
     for (auto& kv : rects) {
@@ -2540,18 +2552,18 @@ extern "C" msg_status msg_sample_matern(msg_handle h, const msg_matern_spec* sp,
             const int K = std::min(chunk, n - k0);
             const MaternSample* t = d_tab + first + k0;
             if ((st = chk(launch_mat_row(K, Mx, My, hx, hy, sp->nu, coef, t, A, s), "embedding row")) != MSG_OK ||
-                (st = chk(launch_fft_rows((int64_t)K * My, lx, (1 << lmax) >> lx, tw, A, s), "fft")) != MSG_OK ||
+                (st = chk(fft((int64_t)K * My, lx, A, B), "fft")) != MSG_OK ||
                 (st = chk(launch_transpose(K, My, Mx, A, B, s), "transpose")) != MSG_OK ||
-                (st = chk(launch_fft_rows((int64_t)K * Mx, ly, (1 << lmax) >> ly, tw, B, s), "fft")) != MSG_OK)
+                (st = chk(fft((int64_t)K * Mx, ly, B, A), "fft")) != MSG_OK)
                 return st;
             if (d_ratio &&
                 (st = chk(launch_eig_ratio(K, M, kMaternBlocks, B, part, d_idx + first + k0, d_ratio, s),
                           "eigenvalue check")) != MSG_OK)
                 return st;
             if ((st = chk(launch_mat_xi(K, Mx, My, sp->seed, kMaternKey1, t, B, s), "normals")) != MSG_OK ||
-                (st = chk(launch_fft_rows((int64_t)K * Mx, ly, (1 << lmax) >> ly, tw, B, s), "fft")) != MSG_OK ||
+                (st = chk(fft((int64_t)K * Mx, ly, B, A), "fft")) != MSG_OK ||
                 (st = chk(launch_transpose(K, Mx, My, B, A, s), "transpose")) != MSG_OK ||
-                (st = chk(launch_fft_rows((int64_t)K * My, lx, (1 << lmax) >> lx, tw, A, s), "fft")) != MSG_OK ||
+                (st = chk(fft((int64_t)K * My, lx, A, B), "fft")) != MSG_OK ||
                 (st = chk(launch_mat_faces(K, c, P, Q, Mx, My, t, A, d_kx, d_ky, d_kx32, d_ky32, s), "faces")) !=
                     MSG_OK)
                 return st;

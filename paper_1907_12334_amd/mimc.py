@@ -71,6 +71,7 @@ from . import inputs as I
 from . import msg
 
 LOG2 = math.log(2.0)
+MATERN_WS_BYTES = 16 << 30      # cap of the Matern sampler's workspace per batch
 
 
 def initial_rates(beta=(4.0, 4.0), gamma=(1.0, 1.0)) -> np.ndarray:
@@ -212,7 +213,16 @@ class MSGMIMC:
             eta, theta = self.hyperparameters(len(P), self.batches)
             spec = msg.MaternSpec(pr.lam, pr.nu, eta, theta, ids, self.seed, pr.pad)
             ratio = torch.empty(len(P), dtype=torch.float64, device="cuda:0")
-            self.h.sample_matern(spec, batch, bufs.kx, bufs.ky, bufs.kx32, bufs.ky32, ratio=ratio)
+            # a workspace of at most MATERN_WS_BYTES (but one sample of the
+            # largest embedding at least): the library then fields fewer
+            # samples per chunk
+            k = int(np.argmax(P.astype(np.int64) + Q.astype(np.int64)))
+            one = msg.matern_workspace_size(msg.Batch(self.c, [int(P[k])], [int(Q[k])]),
+                                            msg.MaternSpec(pr.lam, pr.nu, [1.0], [0.0], None, self.seed, pr.pad))
+            n = max(one, min(msg.matern_workspace_size(batch, spec), MATERN_WS_BYTES))
+            ws = torch.empty((n + 7) // 8, dtype=torch.float64, device="cuda:0")
+            self.h.sample_matern(spec, batch, bufs.kx, bufs.ky, bufs.kx32, bufs.ky32, ratio=ratio, ws=ws)
+            del ws
             msg.run(self.h, None, batch, self.opts, None, bufs, field=False)
             self.min_eig_ratio = min(self.min_eig_ratio, float(ratio.min()))
         if self.kind != msg.QOI_MEAN:

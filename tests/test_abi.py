@@ -161,13 +161,15 @@ def test_matern_workspace_and_validation():
         with pytest.raises(msg.MsgError) as e:
             msg.matern_workspace_size(b, msg.MaternSpec(**args))
         assert e.value.code == msg.MSG_ERR_ARG, kw
-    # 256 x 256 cells: the paper's factor 13 needs 8192 points per direction (the most a row holds)
+    # 256 x 256 cells: the paper's factor 13 needs 8192 points per direction (the most one workgroup's row holds)
     assert msg.matern_workspace_size(msg.Batch(2, [7], [7]), msg.MaternSpec(0.25, 0.5, [0.1], [0.0])) >= 2 * 8192 ** 2 * 16
-    # 512 x 512 cells: factor 15 needs 16384
+    # 512 x 512 cells (2^18 unknowns, the paper's largest): factor 15 needs 16384, by the four-step FFT
+    assert msg.matern_workspace_size(msg.Batch(2, [8], [8]), msg.MaternSpec(0.25, 0.5, [0.1], [0.0])) >= 2 * 16384 ** 2 * 16
+    # 2048 x 2048 cells: factor 17 needs 2^17 points per direction, beyond the 32768 supported
     with pytest.raises(msg.MsgError) as e:
-        msg.matern_workspace_size(msg.Batch(2, [8], [8]), msg.MaternSpec(0.25, 0.5, [0.1], [0.0]))
+        msg.matern_workspace_size(msg.Batch(2, [10], [10]), msg.MaternSpec(0.25, 0.5, [0.1], [0.0]))
     assert e.value.code == msg.MSG_ERR_UNSUPPORTED
-    assert msg.matern_workspace_size(msg.Batch(2, [8], [8]), msg.MaternSpec(0.25, 0.5, [0.1], [0.0], pad=3)) > 0
+    assert msg.matern_workspace_size(msg.Batch(2, [10], [10]), msg.MaternSpec(0.25, 0.5, [0.1], [0.0], pad=3)) > 0
     code = msg.lib().msg_sample_matern(None, ctypes.byref(spec.c_struct), ctypes.byref(b.c_struct),
                                        *([None] * 6), 0, None)
     assert code == msg.MSG_ERR_ARG

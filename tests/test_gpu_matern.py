@@ -135,3 +135,46 @@ def test_largest_embedding_256x256_grid(handle):
     print("matern 256x256", flush=True)
     g = _gpu(handle, c, P, Q, spec)
     _compare(g, c, P, Q, 0.25, 0.5, eta, theta, [3], 77)
+
+
+@pytest.mark.parametrize("P,Q", [(5, 5), (6, 3)])
+def test_long_rows_by_the_four_step_fft(handle, monkeypatch, P, Q):
+    """Rows longer than one workgroup holds run as the four-step FFT (row
+    transposes, FFTs of the two factors, twiddles).  With the single-pass
+    row length lowered to 2^8 points, every row of these embeddings (2048
+    and 4096 points) takes that path; the fields must still match the
+    oracle's (numpy's FFT of the whole embedding)."""
+    c = 2
+    eta, theta = np.array([1 / 16, 1 / 4]), np.radians([-25.0, 10.0])
+    spec = msg.MaternSpec(0.25, 0.5, eta, theta, [11, 4], seed=31)
+    monkeypatch.setenv("MSG_MATERN_ROW_LOG", "8")
+    print(f"matern four-step ({P},{Q})", flush=True)
+    g = _gpu(handle, c, [P, P], [Q, Q], spec)
+    monkeypatch.delenv("MSG_MATERN_ROW_LOG")
+    _compare(g, c, [P, P], [Q, Q], 0.25, 0.5, eta, theta, [11, 4], 31)
+
+
+def test_512x512_grid_the_papers_largest(handle):
+    """512 x 512 cells (2^18 unknowns, the largest problem of the paper's
+    experiments): the paper's factor 15 gives a 16384 x 16384 embedding whose
+    rows take the four-step FFT.  Checked against the oracle's eigenvalue
+    ratio (numpy's FFT of the same first row) and for finite, positive k on
+    every face of all 81 grids."""
+    c, P, Q = 2, [8], [8]
+    eta, theta = np.array([1 / 8]), np.radians([15.0])
+    spec = msg.MaternSpec(0.25, 0.5, eta, theta, [7], seed=5)
+    print("matern 512x512 (16384^2 embedding)", flush=True)
+    g = _gpu(handle, c, P, Q, spec)
+    assert np.all(np.isfinite(g["kx"])) and np.all(g["kx"] > 0)
+    assert np.all(np.isfinite(g["ky"])) and np.all(g["ky"] > 0)
+    Nx = Ny = c << 8
+    Mx, My = MO.embedding_shape(Nx, Ny, 0.5)
+    assert (Mx, My) == (16384, 16384)
+    print("oracle eigenvalues of the 16384^2 embedding", flush=True)
+    row = MO.first_row(Mx, My, 1 / (2 * Nx), 1 / (2 * Ny), 0.25, 0.5, float(eta[0]), float(theta[0]))
+    lam = np.fft.fft2(row).real
+    del row
+    ratio = float(lam.min() / lam.max())
+    del lam
+    assert abs(g["ratio"][0] - ratio) <= 1e-10 * max(1.0, abs(ratio)), (g["ratio"][0], ratio)
+
