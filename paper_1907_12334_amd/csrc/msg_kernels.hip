@@ -1033,6 +1033,21 @@ k_tail_slots(const KTail* __restrict__ table, int4* __restrict__ out)
     }
 }
 
+// Barrier between the phases of the on-chip tail.  A workgroup of one
+// wavefront needs no hardware barrier: its LDS instructions are executed in
+// program order, so a later read by any lane sees an earlier write.  Only
+// the compiler must keep LDS accesses on their side of the phase boundary.
+template <int NT>
+__device__ __forceinline__ void tail_sync()
+{
+    if constexpr (NT == 64) {
+        __builtin_amdgcn_wave_barrier();
+        asm volatile("" ::: "memory");
+    } else {
+        __syncthreads();
+    }
+}
+
 // every grid of level lev, `sweeps` red-then-black sweeps from the slot
 // table: the same updates, in the same arithmetic, as the decoding loop below
 // slot-table entries are read through a global (not flat) pointer: a flat
@@ -1098,7 +1113,7 @@ __device__ __forceinline__ void tail_smooth_regs(T* sm, SlotPtr tab, int total, 
                     sm[e[r].x + d] = tail_cell_update(sm, e[r], d, db, d ? i1[r] : i0[r]);
                 }
             }
-            __syncthreads();
+            tail_sync<NT>();
         }
 }
 
@@ -1127,7 +1142,7 @@ __device__ __forceinline__ void tail_smooth_table(const KTail& TL, T* sm, int le
                 sm[e.x + d] = tail_cell_update(sm, e, d, db, tail_inv_diag(sm, e, d));
                 e = en;
             }
-            __syncthreads();
+            tail_sync<NT>();
         }
 }
 
@@ -1166,7 +1181,7 @@ __device__ __forceinline__ void tail_smooth(const KTail& TL, T* sm, int lev, int
                 const Nbr<T> nb = neighbours(v, off, i, j, G.nx, G.ny);
                 v[off] = (bb + cW * nb.W + cE * nb.E + cS * nb.S + cN * nb.N) / (cW + cE + cS + cN);
             }
-            __syncthreads();
+            tail_sync<NT>();
         }
 }
 
@@ -1196,7 +1211,7 @@ __device__ __forceinline__ void tail_restrict(const KTail& TL, T* sm, int lev)
         sm[G.b + off] = (hx && hy) ? T(0.5) * rx + T(0.5) * ry : (hx ? rx : ry);
         sm[G.v + off] = T(0);
     }
-    __syncthreads();
+    tail_sync<NT>();
 }
 
 // eq. interpolation on level lev from level lev-1, weights from the scaled
@@ -1240,12 +1255,12 @@ __device__ __forceinline__ void tail_prolong(const KTail& TL, T* sm, int lev, T 
         }
         sm[G.v + off] += omega * corr;
     }
-    __syncthreads();
+    tail_sync<NT>();
 }
 
 // v^(0,0) = (A^(0,0))^-1 b^(0,0) in FP64, lane k computing unknown k (c^2 <= 64)
 // from the sample's inverse
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void tail_coarse(const KTail& TL, T* sm, const double* Ai, int n)
 {
     const KTailLevel L0 = TL.lvl[0];
@@ -1256,7 +1271,7 @@ __device__ __forceinline__ void tail_coarse(const KTail& TL, T* sm, const double
         for (int j = 0; j < n; ++j) x += Ai[k * n + j] * (double)b[j];
         sm[L0.v0 + k] = (T)x;
     }
-    __syncthreads();
+    tail_sync<NT>();
 }
 
 // count mu-cycles on the tail's top level; the recursion is unrolled with
@@ -1274,7 +1289,7 @@ __device__ __forceinline__ void tail_cycles(const KTail& TL, T* sm, const double
     for (;;) {
         if (down) {
             if (lev == 0) {
-                tail_coarse(TL, sm, Lc, n0);
+                tail_coarse<T, NT>(TL, sm, Lc, n0);
                 down = false;
                 continue;
             }
@@ -1318,11 +1333,11 @@ __device__ __forceinline__ void tail_norms(const KTail& TL, T* sm, double& rr, d
     }
     if (NT > 64) {
         if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = rr; red[1][threadIdx.x >> 6] = bb; }
-        __syncthreads();
+        tail_sync<NT>();
         rr = red[0][0];
         bb = red[1][0];
         for (int w = 1; w < NT / 64; ++w) { rr += red[0][w]; bb += red[1][w]; }
-        __syncthreads();
+        tail_sync<NT>();
     }
 }
 
