@@ -1648,10 +1648,12 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
     std::vector<KTail> tails;
     std::vector<int32_t> cls;
     std::vector<std::vector<int32_t>> gcls_host;     // per lockstep group: class descriptor per stage problem
+    std::vector<std::vector<int32_t>> gcls_sent;     // what the device holds for each group slot this stage
     X.tails = (const KTail*)(ws + W.tails);
     X.tpack = ws + W.tpack;
     for (const StagePlan& SP : plans) {
         const auto t_stage = std::chrono::steady_clock::now();
+        gcls_sent.clear();
         // problems of this F-cycle level (the previous level's table copy has
         // completed: the stream was synchronised at its last convergence check)
         HIPCHK(hipStreamSynchronize(s));
@@ -1874,8 +1876,14 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                         G.gend = std::max(G.gend, e.C->first + e.C->K);
                         for (int k = 0; k < e.C->K; ++k) gcls_host[g][e.C->first + k] = 2 * e.C->ci;
                     }
+                    // uploaded only when the group's membership changed since the
+                    // last cycle of this stage (a class stopped)
                     int32_t* d = (int32_t*)(ws + W.gcls) + (int64_t)g * SP.K;
-                    HIPCHK(hipMemcpyAsync(d, gcls_host[g].data(), sizeof(int32_t) * SP.K, hipMemcpyHostToDevice, s));
+                    if (gcls_sent.size() <= g) gcls_sent.resize(g + 1);
+                    if (gcls_sent[g] != gcls_host[g]) {
+                        HIPCHK(hipMemcpyAsync(d, gcls_host[g].data(), sizeof(int32_t) * SP.K, hipMemcpyHostToDevice, s));
+                        gcls_sent[g] = gcls_host[g];
+                    }
                     G.gcls = d;
                 }
                 if (fork) {
