@@ -297,7 +297,8 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-SMOOTH_KERNEL = "k_rbgs<double,2> (red-black Gauss-Seidel, 2 fused sweeps)"
+SMOOTH_KERNEL = ("k_rbgs<double,2|4> (red-black Gauss-Seidel passes: 2 fused sweeps, or 4 where two consecutive "
+                 "W-cycle visits of a level share a pass)")
 
 
 def status_split(status):
