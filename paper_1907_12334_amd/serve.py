@@ -71,6 +71,7 @@ class Request:
 
 
 BIG_TAIL_LDS = 150 * 1024     # LDS bytes per problem of the large-request lane's tails
+SMALL_TAIL_LDS = 100 * 1024   # ... and of the small-request lane's (unless the options set one)
 
 
 def work_estimate(c: int, P: int, Q: int) -> float:
@@ -189,6 +190,10 @@ class Engine:
         # the workers are the concurrency: each batch stays on its worker's
         # stream (more streams than hardware queues serialise the batches)
         opts = dataclasses.replace(opts, overlap=0)
+        # batches of small requests hold few problems per class: deep on-chip
+        # tails save host level visits there too
+        if not opts.tail_budget:
+            opts = dataclasses.replace(opts, tail_budget=SMALL_TAIL_LDS)
         self.field, self.c, self.opts, self.device, self.seed = field, c, opts, device, seed
         self.dev = torch.device(f"cuda:{device}")
         if budget_bytes is None:
