@@ -175,7 +175,10 @@ class MSGMIMC:
         self.h, self.field, self.c, self.kind = handle, field, c, kind
         self.prior = prior
         self.min_eig_ratio = math.inf
-        self.opts = opts or msg.SolveOpts(tol=1e-8, max_cycles=200, precision=msg.MIXED)
+        # batches of a few hundred samples spread over many rectangles: 64 KB
+        # on-chip tails (fewer host level visits) suit them better than the
+        # library's default sized for thousands of problems per class
+        self.opts = opts or msg.SolveOpts(tol=1e-8, max_cycles=200, precision=msg.MIXED, tail_budget=65536)
         self.lmax, self.seed, self.learn = lmax, seed, learn
         self.r = np.array(initial_rates() if r0 is None else r0, dtype=float)
         self.ys: List[float] = []
