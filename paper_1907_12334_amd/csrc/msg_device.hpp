@@ -116,6 +116,7 @@ struct KTail {
     const int4* slots;
     int32_t slot_off[kMaxTailLevels];    // first entry of each level
     int32_t nslots;                      // entries of all levels 0..top
+    int32_t zero;                        // LDS element holding 0: what a neighbour beyond a wall reads
     int32_t first;                       // the class's first problem in the stage's problem table
     int64_t pack_off;                    // element offset of the class's conductance images in the
                                          // stage's image buffer (K * nstat elements, problem order)

@@ -357,6 +357,8 @@ size_t tail_layout(int c, int pc, int qc, int m, const std::vector<int64_t>& gof
         L.v0 = (int)off; off += (int64_t)L.cells * L.ng;
         L.b0 = (int)off; off += (int64_t)L.cells * L.ng;
     }
+    TL.zero = (int)off;
+    off += 1;
     if (off > (int64_t)1 << 30) return 0;
     // red-black slot table entries (pairs of cells: grids with an even width)
     int32_t ns = 0;

@@ -1056,9 +1056,10 @@ __device__ __forceinline__ void tail_sync()
 typedef int SlotV __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) SlotV* SlotPtr;
 
-// one red-black update of the cell at `off` (this colour's cell of its pair)
+// one red-black update of the cell at `off` (this colour's cell of its pair);
+// a neighbour beyond a wall is read from the zero element z
 template <typename T>
-__device__ __forceinline__ T tail_cell_update(const T* sm, SlotV e, int d, int db, T inv)
+__device__ __forceinline__ T tail_cell_update(const T* sm, SlotV e, int d, int db, T inv, int z)
 {
     const int nx = e.w & 0xffff;
     const int off = e.x + d, fx = e.y + d, fy = e.z + d;
@@ -1067,10 +1068,9 @@ __device__ __forceinline__ T tail_cell_update(const T* sm, SlotV e, int d, int d
     const T bb = sm[off + db];
     const bool w = !((e.w >> 17) & 1) || d, ea = !((e.w >> 18) & 1) || !d;
     const bool so = !((e.w >> 19) & 1), no = !((e.w >> 20) & 1);
-    const T xW = sm[w ? off - 1 : off], xE = sm[ea ? off + 1 : off];
-    const T xS = sm[so ? off - nx : off], xN = sm[no ? off + nx : off];
-    const Nbr<T> nb{w ? xW : T(0), ea ? xE : T(0), so ? xS : T(0), no ? xN : T(0)};
-    return (bb + cW * nb.W + cE * nb.E + cS * nb.S + cN * nb.N) * inv;
+    const T xW = sm[w ? off - 1 : z], xE = sm[ea ? off + 1 : z];
+    const T xS = sm[so ? off - nx : z], xN = sm[no ? off + nx : z];
+    return (bb + cW * xW + cE * xE + cS * xS + cN * xN) * inv;
 }
 
 template <typename T>
@@ -1086,7 +1086,7 @@ __device__ __forceinline__ T tail_inv_diag(const T* sm, SlotV e, int d)
 // (the conductances do not change while smoothing), so the table is read
 // once and each cell divides once per call.
 template <typename T, int NT, int R>
-__device__ __forceinline__ void tail_smooth_regs(T* sm, SlotPtr tab, int total, int db, int sweeps)
+__device__ __forceinline__ void tail_smooth_regs(T* sm, SlotPtr tab, int total, int db, int z, int sweeps)
 {
     SlotV e[R];
     T i0[R], i1[R];
@@ -1110,7 +1110,7 @@ __device__ __forceinline__ void tail_smooth_regs(T* sm, SlotPtr tab, int total, 
             for (int r = 0; r < R; ++r) {
                 if ((int)threadIdx.x + r * NT < total) {
                     const int d = (colour + (e[r].w >> 16)) & 1;
-                    sm[e[r].x + d] = tail_cell_update(sm, e[r], d, db, d ? i1[r] : i0[r]);
+                    sm[e[r].x + d] = tail_cell_update(sm, e[r], d, db, d ? i1[r] : i0[r], z);
                 }
             }
             tail_sync<NT>();
@@ -1125,11 +1125,11 @@ __device__ __forceinline__ void tail_smooth_table(const KTail& TL, T* sm, int le
     const int db = L.b0 - L.v0;                     // right-hand side of a cell, relative to its iterate
     const SlotPtr tab = (SlotPtr)(TL.slots + TL.slot_off[lev]);
     if (total <= NT) {
-        tail_smooth_regs<T, NT, 1>(sm, tab, total, db, sweeps);
+        tail_smooth_regs<T, NT, 1>(sm, tab, total, db, TL.zero, sweeps);
         return;
     }
     if (total <= 4 * NT) {
-        tail_smooth_regs<T, NT, 4>(sm, tab, total, db, sweeps);
+        tail_smooth_regs<T, NT, 4>(sm, tab, total, db, TL.zero, sweeps);
         return;
     }
     for (int s = 0; s < sweeps; ++s)
@@ -1139,7 +1139,7 @@ __device__ __forceinline__ void tail_smooth_table(const KTail& TL, T* sm, int le
             for (; sl < total; sl += NT) {
                 const SlotV en = sl + NT < total ? tab[sl + NT] : e;   // the next entry, in flight meanwhile
                 const int d = (colour + (e.w >> 16)) & 1;
-                sm[e.x + d] = tail_cell_update(sm, e, d, db, tail_inv_diag(sm, e, d));
+                sm[e.x + d] = tail_cell_update(sm, e, d, db, tail_inv_diag(sm, e, d), TL.zero);
                 e = en;
             }
             tail_sync<NT>();
@@ -1402,6 +1402,7 @@ k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int ti
         }
     }
     for (int idx = threadIdx.x; idx < n0 * n0; idx += NT) Lc[idx] = chol[(int64_t)pr.sample * n0 * n0 + idx];
+    if (threadIdx.x == 0) sm[TL.zero] = T(0);
     __syncthreads();
 
     if (count > 0) {
