@@ -956,16 +956,28 @@ __device__ __forceinline__ Nbr<T> neighbours(const T* v, int off, int i, int j, 
     return Nbr<T>{w ? xW : T(0), e ? xE : T(0), s ? xS : T(0), n ? xN : T(0)};
 }
 
+// (a neighbour beyond a wall is read from the zero element z of the tail)
 template <typename T>
-__device__ __forceinline__ T tresid(const T* sm, const TGrid& G, int i, int j)
+__device__ __forceinline__ T tresid(const T* sm, const TGrid& G, int i, int j, int z)
 {
-    const T* v = sm + G.v;
-    const int off = j * G.nx + i;
+    const int off = G.v + j * G.nx + i;
     const T cW = sm[G.x + j * (G.nx + 1) + i], cE = sm[G.x + j * (G.nx + 1) + i + 1];
     const T cS = sm[G.y + j * G.nx + i], cN = sm[G.y + (j + 1) * G.nx + i];
-    const T u = v[off], bb = sm[G.b + off];
-    const Nbr<T> nb = neighbours(v, off, i, j, G.nx, G.ny);
-    return bb - (cW * (u - nb.W) + cE * (u - nb.E) + cS * (u - nb.S) + cN * (u - nb.N));
+    const T u = sm[off], bb = sm[G.b + j * G.nx + i];
+    const T xW = sm[i > 0 ? off - 1 : z], xE = sm[i < G.nx - 1 ? off + 1 : z];
+    const T xS = sm[j > 0 ? off - G.nx : z], xN = sm[j < G.ny - 1 ? off + G.nx : z];
+    return bb - (cW * (u - xW) + cE * (u - xE) + cS * (u - xS) + cN * (u - xN));
+}
+
+// linear interpolation of eq. interpolation along a line of LDS (32-bit
+// indexing; the arithmetic of linear_at)
+template <typename T>
+__device__ __forceinline__ T linear_lds(const T* line, int stride, int n, int i)
+{
+    const int I = i >> 1, In = (i & 1) ? I + 1 : I - 1;
+    const T e0 = line[I * stride];
+    const T e1 = (In >= 0 && In < n) ? line[In * stride] : -e0;
+    return T(0.75) * e0 + T(0.25) * e1;
 }
 
 // the face conductances of every tail grid of problem pr, k/h^2 with the wall
@@ -1202,11 +1214,11 @@ __device__ __forceinline__ void tail_restrict(const KTail& TL, T* sm, int lev)
         T rx = T(0), ry = T(0);
         if (hx) {
             const TGrid P = tgrid(TL, F, lev, G.p + 1 - F.pmin);
-            rx = T(0.5) * (tresid(sm, P, 2 * I, J) + tresid(sm, P, 2 * I + 1, J));
+            rx = T(0.5) * (tresid(sm, P, 2 * I, J, TL.zero) + tresid(sm, P, 2 * I + 1, J, TL.zero));
         }
         if (hy) {
             const TGrid P = tgrid(TL, F, lev, G.p - F.pmin);
-            ry = T(0.5) * (tresid(sm, P, I, 2 * J) + tresid(sm, P, I, 2 * J + 1));
+            ry = T(0.5) * (tresid(sm, P, I, 2 * J, TL.zero) + tresid(sm, P, I, 2 * J + 1, TL.zero));
         }
         sm[G.b + off] = (hx && hy) ? T(0.5) * rx + T(0.5) * ry : (hx ? rx : ry);
         sm[G.v + off] = T(0);
@@ -1231,11 +1243,11 @@ __device__ __forceinline__ void tail_prolong(const KTail& TL, T* sm, int lev, T 
         T ex = T(0), ey = T(0);
         if (hx) {
             const TGrid X = tgrid(TL, C, lev - 1, G.p - 1 - C.pmin);
-            ex = linear_at(sm + X.v + j * (G.nx / 2), (int64_t)1, G.nx / 2, i);
+            ex = linear_lds(sm + X.v + j * (G.nx / 2), 1, G.nx / 2, i);
         }
         if (hy) {
             const TGrid Y = tgrid(TL, C, lev - 1, G.p - C.pmin);
-            ey = linear_at(sm + Y.v + i, (int64_t)G.nx, G.ny / 2, j);
+            ey = linear_lds(sm + Y.v + i, G.nx, G.ny / 2, j);
         }
         T corr;
         if (hx && hy) {
@@ -1322,7 +1334,7 @@ __device__ __forceinline__ void tail_norms(const KTail& TL, T* sm, double& rr, d
     for (int off = threadIdx.x; off < L.cells; off += NT) {
         int i, j;
         cell_ij(off, G.nx, G.sh, i, j);
-        const double r = (double)tresid(sm, G, i, j);
+        const double r = (double)tresid(sm, G, i, j, TL.zero);
         const double b = (double)sm[G.b + off];
         rr += r * r;
         bb += b * b;
