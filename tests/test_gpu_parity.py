@@ -341,6 +341,33 @@ def test_full_size_config2_sampled(handle):
         assert eu <= FP64_TOL and eq <= FP64_TOL and edq <= FP64_TOL, (s, eu, eq, edq)
 
 
+def test_full_size_config2_whole_batch(handle):
+    """The whole 4096-sample 256x256 batch in the benchmark's launch
+    configuration (automatic overlap: three concurrently solved parts, the
+    shared passes of consecutive visits, lockstep tails): every sample
+    converges, and samples at both ends of every part match the oracle
+    grid by grid."""
+    import torch
+    w = I.config(2)
+    xi = w.xi()
+    print("config 2, 4096 samples", flush=True)
+    opts = msg.SolveOpts(tol=w.tol, max_cycles=w.max_cycles)
+    b = msg.Batch(w.c, w.P, w.Q)
+    bufs = msg.Buffers(b, opts)
+    msg.run(handle, w.field, b, opts, torch.tensor(xi, dtype=torch.float64, device="cuda:0"), bufs)
+    torch.cuda.synchronize()
+    assert np.all(bufs.status.cpu().numpy() == 0)
+    lay = bufs.layout
+    for s in (0, 1365, 1366, 4095):
+        c0, c1, g0, g1 = (int(x) for x in (lay["cell"][s], lay["cell"][s + 1], lay["grid"][s], lay["grid"][s + 1]))
+        g = {"u": bufs.u[c0:c1].cpu().numpy(), "q": bufs.q[g0:g1].cpu().numpy(),
+             "dq": bufs.dq[g0:g1].cpu().numpy(), "cycles": bufs.cycles[g0:g1].cpu().numpy()}
+        eu, eq, edq, _ = PR.compare_sample(w.c, 7, 7, w.field, xi[s], g, max_cycles=w.max_cycles)
+        assert eu <= FP64_TOL and eq <= FP64_TOL and edq <= FP64_TOL, (s, eu, eq, edq)
+    del bufs
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("kind", [msg.QOI_MEAN, msg.QOI_POINT, msg.QOI_SUBDOMAIN, msg.QOI_FLUX])
 def test_quantities_of_interest_match_oracle(handle, kind):
     """Section 5's quantities on every grid: from the GPU's own solutions they
