@@ -97,6 +97,7 @@ struct KTailLevel {
 };
 
 constexpr int kMaxTailLevels = 9;        // levels 0..8
+constexpr int kTailRegLevels = 3;        // tail levels that can keep their slot state in registers
 
 struct KTail {
     int32_t top;               // level the cycles start on
@@ -117,6 +118,8 @@ struct KTail {
     int32_t slot_off[kMaxTailLevels];    // first entry of each level
     int32_t nslots;                      // entries of all levels 0..top
     int32_t zero;                        // LDS element holding 0: what a neighbour beyond a wall reads
+    int32_t reg_levels;                  // levels 1..reg_levels keep their slot entries and reciprocal
+                                         // diagonals in registers for the whole launch (0: none)
     int32_t first;                       // the class's first problem in the stage's problem table
     int64_t pack_off;                    // element offset of the class's conductance images in the
                                          // stage's image buffer (K * nstat elements, problem order)

@@ -139,6 +139,7 @@ int g_rbgs_lds = kRbgsLds;
 int g_tail_lds = 20480;      // LDS budget of the W-cycle tail (sets its depth)
 int g_split_inner = 0;       // overlap mode inside each concurrently solved half (0 or 1)
 int g_handoff = 1024;        // hand a class's last cycling problems to one kernel at or below this count
+int g_tail_reg_levels = kTailRegLevels;   // tail levels 1..n with register-resident slot state
 int g_solve_lds = 65536;     // LDS budget under which a class is solved entirely in one kernel
 bool g_tail_table = true;    // tails smooth from a red-black slot table (false: decode every slot)
 bool g_fuse_restrict = true; // pre-smoothing passes of nu1 = 2 also restrict their residual
@@ -367,6 +368,14 @@ size_t tail_layout(int c, int pc, int qc, int m, const std::vector<int64_t>& gof
         ns += (TL.lvl[lev].cells / 2) * TL.lvl[lev].ng;
     }
     TL.nslots = (c & 1) ? 0 : ns;
+    // levels whose slots fit one per lane of a wavefront keep their slot
+    // state in registers (the small levels that a W-cycle visits most)
+    TL.reg_levels = 0;
+    if (TL.nslots > 0)
+        for (int lev = 1; lev <= std::min(m, g_tail_reg_levels); ++lev) {
+            if ((TL.lvl[lev].cells / 2) * TL.lvl[lev].ng > 64) break;
+            TL.reg_levels = lev;
+        }
     TL.lds_elems = (int)off;
     TL.chol_off = (int)(((size_t)off * sizeof(T) + 15) / 16 * 16);
     return (size_t)TL.chol_off + sizeof(double) * (size_t)c * c * c * c;
@@ -803,6 +812,7 @@ void read_env()
         if (const char* t = std::getenv("MSG_SOLVE_LDS")) g_solve_lds = std::max(0, std::atoi(t));
         if (const char* t = std::getenv("MSG_DEBUG_STAGES")) g_debug_stages = std::atoi(t) != 0;
         if (const char* t = std::getenv("MSG_HANDOFF")) g_handoff = std::max(0, std::atoi(t));
+        if (const char* t = std::getenv("MSG_TAIL_REG")) g_tail_reg_levels = std::max(0, std::min(kTailRegLevels, std::atoi(t)));
         if (const char* t = std::getenv("MSG_RBGS_TW")) g_rbgs_tw = std::max(4, std::min(256, std::atoi(t)));
         if (const char* t = std::getenv("MSG_RBGS_CELLS")) g_rbgs_cells = std::max(64, std::min(4096, std::atoi(t)));
         if (const char* t = std::getenv("MSG_RBGS_LDS")) g_rbgs_lds = std::max(1024, std::min(kRbgsLdsMax, std::atoi(t)));

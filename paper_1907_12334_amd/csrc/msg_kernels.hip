@@ -1129,6 +1129,66 @@ __device__ __forceinline__ void tail_smooth_regs(T* sm, SlotPtr tab, int total, 
         }
 }
 
+// The small levels of a tail (one slot per lane at most) are smoothed many
+// times per launch: a W-cycle visits level l 2^(top-l) times.  Their slot
+// entry and the reciprocal diagonals of its two cells are formed once, when
+// the launch starts (the conductances stay fixed for the whole launch), and
+// held in registers; each smoothing call then only sweeps.  Same arithmetic
+// as tail_smooth_regs.  Levels 1..kTailRegLevels at most.
+
+template <typename T>
+struct TailRegLevel {
+    SlotV e;
+    T i0, i1;
+    bool on;                                        // this lane owns a slot of the level
+};
+
+template <typename T, int NT>
+__device__ __forceinline__ TailRegLevel<T> tail_reg_level(const KTail& TL, const T* sm, int lev)
+{
+    TailRegLevel<T> R;
+    R.e = SlotV{0, 0, 0, 0};
+    R.i0 = T(0);
+    R.i1 = T(0);
+    R.on = false;
+    if (lev > TL.top || lev > TL.reg_levels) return R;
+    const KTailLevel L = TL.lvl[lev];
+    const int total = (L.cells >> 1) * L.ng;
+    if (total <= NT && (int)threadIdx.x < total) {
+        R.e = ((SlotPtr)(TL.slots + TL.slot_off[lev]))[threadIdx.x];
+        R.i0 = tail_inv_diag(sm, R.e, 0);
+        R.i1 = tail_inv_diag(sm, R.e, 1);
+        R.on = true;
+    }
+    return R;
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void tail_sweeps_reg(T* sm, const TailRegLevel<T>& R, int db, int z, int sweeps)
+{
+    // the entry passes through an empty asm statement, so the compiler forms
+    // the cell addresses from it at each call instead of keeping those of
+    // every level live for the whole launch: 161 instead of 226 registers,
+    // which leaves room on each SIMD for the smoother's wavefronts that run
+    // beside the tail (measured faster on the overlapped step)
+    int ex = R.e.x, ey = R.e.y, ez = R.e.z, ew = R.e.w;
+    asm volatile("" : "+v"(ex), "+v"(ey), "+v"(ez), "+v"(ew));
+    const SlotV e = SlotV{ex, ey, ez, ew};
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour) {
+            if (R.on) {
+                const int d = (colour + (e.w >> 16)) & 1;
+                sm[e.x + d] = tail_cell_update(sm, e, d, db, d ? R.i1 : R.i0, z);
+            }
+            tail_sync<NT>();
+        }
+}
+
+template <typename T>
+struct TailRegs {
+    TailRegLevel<T> r1, r2, r3;
+};
+
 template <typename T, int NT>
 __device__ __forceinline__ void tail_smooth_table(const KTail& TL, T* sm, int lev, int sweeps)
 {
@@ -1159,10 +1219,17 @@ __device__ __forceinline__ void tail_smooth_table(const KTail& TL, T* sm, int le
 }
 
 template <typename T, int NT>
-__device__ __forceinline__ void tail_smooth(const KTail& TL, T* sm, int lev, int sweeps)
+__device__ __forceinline__ void tail_smooth(const KTail& TL, T* sm, int lev, int sweeps, const TailRegs<T>& RG,
+                                            bool regs)
 {
     const KTailLevel L = TL.lvl[lev];
     const bool pairs = !(TL.c & 1);                 // nx even on every grid
+    if (regs && lev <= TL.reg_levels && (L.cells >> 1) * L.ng <= NT) {
+        const int db = L.b0 - L.v0;
+        if (lev == 1) { tail_sweeps_reg<T, NT>(sm, RG.r1, db, TL.zero, sweeps); return; }
+        if (lev == 2) { tail_sweeps_reg<T, NT>(sm, RG.r2, db, TL.zero, sweeps); return; }
+        if (lev == 3) { tail_sweeps_reg<T, NT>(sm, RG.r3, db, TL.zero, sweeps); return; }
+    }
     if (pairs && TL.slots) {
         tail_smooth_table<T, NT>(TL, sm, lev, sweeps);
         return;
@@ -1290,7 +1357,7 @@ __device__ __forceinline__ void tail_coarse(const KTail& TL, T* sm, const double
 // the cycles still to run on each level kept two bits per level in a register
 template <typename T, int NT>
 __device__ __forceinline__ void tail_cycles(const KTail& TL, T* sm, const double* Lc, int n0, int mu, int nu1,
-                                            int nu2, T omega, int count)
+                                            int nu2, T omega, int count, const TailRegs<T>& RG, bool regs)
 {
     uint64_t left = 0;
     auto get = [&](int l) { return (int)((left >> (2 * l)) & 3u); };
@@ -1305,7 +1372,7 @@ __device__ __forceinline__ void tail_cycles(const KTail& TL, T* sm, const double
                 down = false;
                 continue;
             }
-            tail_smooth<T, NT>(TL, sm, lev, nu1);
+            tail_smooth<T, NT>(TL, sm, lev, nu1, RG, regs);
             tail_restrict<T, NT>(TL, sm, lev);
             --lev;
             set(lev, mu);
@@ -1317,7 +1384,7 @@ __device__ __forceinline__ void tail_cycles(const KTail& TL, T* sm, const double
             if (lev == TL.top) break;
             ++lev;
             tail_prolong<T, NT>(TL, sm, lev, omega);
-            tail_smooth<T, NT>(TL, sm, lev, nu2);
+            tail_smooth<T, NT>(TL, sm, lev, nu2, RG, regs);
         }
     }
 }
@@ -1416,9 +1483,14 @@ k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int ti
     for (int idx = threadIdx.x; idx < n0 * n0; idx += NT) Lc[idx] = chol[(int64_t)pr.sample * n0 * n0 + idx];
     if (threadIdx.x == 0) sm[TL.zero] = T(0);
     __syncthreads();
+    const bool use_regs = TL.reg_levels > 0 && TL.slots && !(TL.c & 1);
+    TailRegs<T> RG;
+    RG.r1 = tail_reg_level<T, NT>(TL, sm, use_regs ? 1 : kMaxTailLevels);
+    RG.r2 = tail_reg_level<T, NT>(TL, sm, use_regs ? 2 : kMaxTailLevels);
+    RG.r3 = tail_reg_level<T, NT>(TL, sm, use_regs ? 3 : kMaxTailLevels);
 
     if (count > 0) {
-        tail_cycles<T, NT>(TL, sm, Lc, n0, mu, nu1, nu2, omega, count);
+        tail_cycles<T, NT>(TL, sm, Lc, n0, mu, nu1, nu2, omega, count, RG, use_regs);
     } else {
         int ncyc = ad.pcycles[k];                // cycles already run on this level
         for (;;) {
@@ -1437,7 +1509,7 @@ k_tail(const KTail* __restrict__ tables, const int32_t* __restrict__ cls, int ti
                 if (threadIdx.x == 0) atomicMax(&ad.status[pr.sample], (int)MSG_ST_MAXITER);
                 break;
             }
-            tail_cycles<T, NT>(TL, sm, Lc, n0, mu, nu1, nu2, omega, 1);
+            tail_cycles<T, NT>(TL, sm, Lc, n0, mu, nu1, nu2, omega, 1, RG, use_regs);
             ++ncyc;
         }
         if (threadIdx.x == 0) ad.pcycles[k] = ncyc;
