@@ -980,6 +980,23 @@ __device__ __forceinline__ T linear_lds(const T* line, int stride, int n, int i)
     return T(0.75) * e0 + T(0.25) * e1;
 }
 
+// kappa of eq. interpolation at cell (i,j) of a tail grid with both coarse
+// children (the weights of tail_prolong)
+template <typename T>
+__device__ __forceinline__ T tail_kappa(const T* sm, const TGrid& G, int i, int j)
+{
+    const T cW = sm[G.x + j * (G.nx + 1) + i], cE = sm[G.x + j * (G.nx + 1) + i + 1];
+    const T cS = sm[G.y + j * G.nx + i], cN = sm[G.y + (j + 1) * G.nx + i];
+    T lx = (i == 0 ? cW : T(2) * cW) + (i == G.nx - 1 ? cE : T(2) * cE);
+    T ly = (j == 0 ? cS : T(2) * cS) + (j == G.ny - 1 ? cN : T(2) * cN);
+    if (j == 0) lx += cS;
+    if (j == G.ny - 1) lx += cN;
+    if (i == 0) ly += cW;
+    if (i == G.nx - 1) ly += cE;
+    const T a = lx * lx, b = ly * ly;
+    return a / (a + b);
+}
+
 // the face conductances of every tail grid of problem pr, k/h^2 with the wall
 // faces doubled, written to dst in the tail layout (LDS or the prepared image)
 template <typename T, int NT>
@@ -1121,8 +1138,17 @@ __device__ __forceinline__ void tail_smooth_regs(T* sm, SlotPtr tab, int total, 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if ((int)threadIdx.x + r * NT < total) {
-                    const int d = (colour + (e[r].w >> 16)) & 1;
-                    sm[e[r].x + d] = tail_cell_update(sm, e[r], d, db, d ? i1[r] : i0[r], z);
+                    // FP64, several slots per lane: the entry passes through an
+                    // empty asm statement so that the cell addresses are formed
+                    // again at each half-sweep rather than held for all R slots
+                    // (108 instead of 161 registers: more room for the smoother's
+                    // wavefronts beside the tail; FP32 tails measured faster
+                    // with the addresses held)
+                    int ex = e[r].x, ey = e[r].y, ez = e[r].z, ew = e[r].w;
+                    if constexpr (R > 1 && sizeof(T) == 8) asm volatile("" : "+v"(ex), "+v"(ey), "+v"(ez), "+v"(ew));
+                    const SlotV ee = SlotV{ex, ey, ez, ew};
+                    const int d = (colour + (ee.w >> 16)) & 1;
+                    sm[ee.x + d] = tail_cell_update(sm, ee, d, db, d ? i1[r] : i0[r], z);
                 }
             }
             tail_sync<NT>();
@@ -1168,9 +1194,9 @@ __device__ __forceinline__ void tail_sweeps_reg(T* sm, const TailRegLevel<T>& R,
 {
     // the entry passes through an empty asm statement, so the compiler forms
     // the cell addresses from it at each call instead of keeping those of
-    // every level live for the whole launch: 161 instead of 226 registers,
-    // which leaves room on each SIMD for the smoother's wavefronts that run
-    // beside the tail (measured faster on the overlapped step)
+    // every level live for the whole launch (which took the kernel from 161
+    // to 226 registers and left no room on a SIMD for the smoother's
+    // wavefronts running beside the tail: slower on the overlapped step)
     int ex = R.e.x, ey = R.e.y, ez = R.e.z, ew = R.e.w;
     asm volatile("" : "+v"(ex), "+v"(ey), "+v"(ez), "+v"(ew));
     const SlotV e = SlotV{ex, ey, ez, ew};
@@ -1318,16 +1344,7 @@ __device__ __forceinline__ void tail_prolong(const KTail& TL, T* sm, int lev, T 
         }
         T corr;
         if (hx && hy) {
-            const T cW = sm[G.x + j * (G.nx + 1) + i], cE = sm[G.x + j * (G.nx + 1) + i + 1];
-            const T cS = sm[G.y + j * G.nx + i], cN = sm[G.y + (j + 1) * G.nx + i];
-            T lx = (i == 0 ? cW : T(2) * cW) + (i == G.nx - 1 ? cE : T(2) * cE);
-            T ly = (j == 0 ? cS : T(2) * cS) + (j == G.ny - 1 ? cN : T(2) * cN);
-            if (j == 0) lx += cS;
-            if (j == G.ny - 1) lx += cN;
-            if (i == 0) ly += cW;
-            if (i == G.nx - 1) ly += cE;
-            const T a = lx * lx, b = ly * ly;
-            const T ka = a / (a + b);
+            const T ka = tail_kappa(sm, G, i, j);
             corr = ka * ex + (T(1) - ka) * ey;
         } else {
             corr = hx ? ex : ey;
