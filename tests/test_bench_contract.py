@@ -12,15 +12,31 @@ import bench  # noqa: E402
 
 
 def test_roofline_from_launch_totals():
-    """achieved = algorithmic bytes over event time; averages per launch."""
+    """achieved = algorithmic bytes over event time; averages per launch.
+    Without per-step model bytes the algorithmic bytes are the launch's own."""
     r = bench.roofline_of((1000, 250.0, 2.0e12), "k", traffic=3.0e9)
     assert r["achieved"] == pytest.approx(8000.0)          # 2e12 B in 0.25 s
     assert r["frac"] == pytest.approx(1.0)
     assert r["avg_launch_us"] == pytest.approx(250.0)
     assert r["algorithmic_bytes_per_launch"] == pytest.approx(2.0e9)
+    assert r["achieved_minimal"] == pytest.approx(8000.0)
     assert r["traffic"] == 3.0e9 and r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert r["achieved_hbm_counters"] == pytest.approx(12000.0)   # 3e9 B per 250 us launch
     empty = bench.roofline_of((0, 0.0, 0.0), "k")
     assert empty["achieved"] is None and empty["avg_launch_us"] is None
+
+
+def test_roofline_counts_the_per_step_model():
+    """A smoother kind carries both byte counts: achieved follows the per-step
+    model (each fused sweep, residual and correction counted as its own pass),
+    the minimal count (every value once) is reported beside it."""
+    r = bench.roofline_of((100, 50.0, 1.0e11, 3.0e11), "k")
+    assert r["achieved"] == pytest.approx(6000.0)          # 3e11 B in 0.05 s
+    assert r["frac"] == pytest.approx(0.75)
+    assert r["algorithmic_bytes_per_launch"] == pytest.approx(3.0e9)
+    assert r["achieved_minimal"] == pytest.approx(2000.0)
+    assert r["frac_minimal"] == pytest.approx(0.25)
+    assert r["minimal_bytes_per_launch"] == pytest.approx(1.0e9)
 
 
 def test_traffic_is_dropped_when_the_kernel_source_changed(tmp_path):
