@@ -1167,6 +1167,11 @@ struct TailRegLevel {
     SlotV e;
     T i0, i1;
     bool on;                                        // this lane owns a slot of the level
+    // restriction into level lev-1, lane = coarse cell of that level: the
+    // slots (lanes) of level lev holding its x-parent pair and its y-parent
+    // pairs, with flags (see tail_restrict_reg), and its LDS iterate offset
+    int rrec, rdst;
+    bool ron;                                       // this lane has a coarse cell
 };
 
 template <typename T, int NT>
@@ -1186,7 +1191,45 @@ __device__ __forceinline__ TailRegLevel<T> tail_reg_level(const KTail& TL, const
         R.i1 = tail_inv_diag(sm, R.e, 1);
         R.on = true;
     }
+    R.rrec = 0;
+    R.rdst = 0;
+    R.ron = false;
+    // coarse cell (I,J) of grid G = (p,q) on level lev-1: its x-parent
+    // (p+1,q) holds fine cells (2I,J), (2I+1,J), the pair of slot I of row J;
+    // its y-parent (p,q+1) holds (I,2J) and (I,2J+1), cells I&1 of the pairs
+    // of slot I>>1 in rows 2J and 2J+1 (nx/2 slots apart)
+    const KTailLevel C = TL.lvl[lev - 1];
+    const int per = L.cells >> 1, ctotal = C.cells * C.ng;
+    if (total <= 64 && ctotal <= 64 && (int)threadIdx.x < ctotal) {
+        int g, off, I, J;
+        split_slot((int)threadIdx.x, C.cells, C.csh, g, off);
+        const TGrid G = tgrid(TL, C, lev - 1, g);
+        cell_ij(off, G.nx, G.sh, I, J);
+        const bool hx = G.p + 1 <= TL.pc, hy = G.q + 1 <= TL.qc;
+        const int sx = hx ? (G.p + 1 - L.pmin) * per + J * G.nx + I : 0;
+        const int sy = hy ? (G.p - L.pmin) * per + J * G.nx + (I >> 1) : 0;
+        const int step = hy ? G.nx >> 1 : 0;
+        R.rrec = sx | (sy << 7) | (step << 14) | ((int)hx << 21) | ((int)hy << 22) | ((I & 1) << 23);
+        R.rdst = G.v + off;
+        R.ron = true;
+    }
     return R;
+}
+
+// b - A v at cell d of a slot's pair, from LDS (the arithmetic of tresid)
+template <typename T>
+__device__ __forceinline__ T tail_pair_resid(const T* sm, SlotV e, int d, int db, int z)
+{
+    const int nx = e.w & 0xffff;
+    const int off = e.x + d, fx = e.y + d, fy = e.z + d;
+    const T cW = sm[fx], cE = sm[fx + 1];
+    const T cS = sm[fy], cN = sm[fy + nx];
+    const T u = sm[off], bb = sm[off + db];
+    const bool w = !((e.w >> 17) & 1) || d, ea = !((e.w >> 18) & 1) || !d;
+    const bool so = !((e.w >> 19) & 1), no = !((e.w >> 20) & 1);
+    const T xW = sm[w ? off - 1 : z], xE = sm[ea ? off + 1 : z];
+    const T xS = sm[so ? off - nx : z], xN = sm[no ? off + nx : z];
+    return bb - (cW * (u - xW) + cE * (u - xE) + cS * (u - xS) + cN * (u - xN));
 }
 
 template <typename T, int NT>
@@ -1290,11 +1333,52 @@ __device__ __forceinline__ void tail_smooth(const KTail& TL, T* sm, int lev, int
         }
 }
 
+// tail_restrict on a level whose pairs and coarse cells fit one per lane of
+// the first wavefront: each lane forms the residuals of its own fine pair
+// from its slot entry, and each coarse cell gathers its parents' residuals
+// from the lanes holding them.  Same arithmetic as tail_restrict.
+template <typename T, int NT>
+__device__ __forceinline__ void tail_restrict_reg(const KTail& TL, T* sm, int lev, const TailRegLevel<T>& R)
+{
+    const KTailLevel F = TL.lvl[lev], C = TL.lvl[lev - 1];
+    const int dbf = F.b0 - F.v0, dbc = C.b0 - C.v0;
+    int ex = R.e.x, ey = R.e.y, ez = R.e.z, ew = R.e.w;
+    asm volatile("" : "+v"(ex), "+v"(ey), "+v"(ez), "+v"(ew));
+    const SlotV e = SlotV{ex, ey, ez, ew};
+    T r0 = T(0), r1 = T(0);
+    if (R.on) {
+        r0 = tail_pair_resid(sm, e, 0, dbf, TL.zero);
+        r1 = tail_pair_resid(sm, e, 1, dbf, TL.zero);
+    }
+    const T rxp = T(0.5) * (r0 + r1);               // the pair's cells restricted in x
+    const int rec = R.rrec;
+    const int sx = rec & 127, sy = (rec >> 7) & 127, step = (rec >> 14) & 127;
+    const T gx = __shfl(rxp, sx, 64);
+    const T a0 = __shfl(r0, sy, 64), a1 = __shfl(r1, sy, 64);
+    const T c0 = __shfl(r0, sy + step, 64), c1 = __shfl(r1, sy + step, 64);
+    if (R.ron) {
+        const bool hx = (rec >> 21) & 1, hy = (rec >> 22) & 1, odd = (rec >> 23) & 1;
+        const T rx = gx;
+        const T ry = T(0.5) * ((odd ? a1 : a0) + (odd ? c1 : c0));
+        sm[R.rdst + dbc] = (hx && hy) ? T(0.5) * rx + T(0.5) * ry : (hx ? rx : ry);
+        sm[R.rdst] = T(0);
+    }
+    tail_sync<NT>();
+}
+
 // residual of level lev restricted to level lev-1 (eq. restriction); the
 // coarse iterate is zeroed
 template <typename T, int NT>
-__device__ __forceinline__ void tail_restrict(const KTail& TL, T* sm, int lev)
+__device__ __forceinline__ void tail_restrict(const KTail& TL, T* sm, int lev, const TailRegs<T>& RG, bool regs)
 {
+    if (regs && lev <= TL.reg_levels) {
+        const KTailLevel F = TL.lvl[lev], C = TL.lvl[lev - 1];
+        if ((F.cells >> 1) * F.ng <= 64 && C.cells * C.ng <= 64) {
+            if (lev == 1) { tail_restrict_reg<T, NT>(TL, sm, 1, RG.r1); return; }
+            if (lev == 2) { tail_restrict_reg<T, NT>(TL, sm, 2, RG.r2); return; }
+            if (lev == 3) { tail_restrict_reg<T, NT>(TL, sm, 3, RG.r3); return; }
+        }
+    }
     const KTailLevel C = TL.lvl[lev - 1], F = TL.lvl[lev];
     const int total = C.cells * C.ng;
     for (int sl = threadIdx.x; sl < total; sl += NT) {
@@ -1390,7 +1474,7 @@ __device__ __forceinline__ void tail_cycles(const KTail& TL, T* sm, const double
                 continue;
             }
             tail_smooth<T, NT>(TL, sm, lev, nu1, RG, regs);
-            tail_restrict<T, NT>(TL, sm, lev);
+            tail_restrict<T, NT>(TL, sm, lev, RG, regs);
             --lev;
             set(lev, mu);
         } else {
