@@ -1466,16 +1466,23 @@ __device__ __forceinline__ void tail_cycles(const KTail& TL, T* sm, const double
     int lev = TL.top;
     set(lev, count);
     bool down = true;
+    // The coarsest solve overwrites v^(0,0) from b^(0,0) alone, and nothing
+    // changes b^(0,0) between the mu calls of one visit of level 1 (nor
+    // between cycles when level 0 is the top): the repeated solves would
+    // write the same bits, so only the first after a restriction runs.
+    bool solved0 = false;
     for (;;) {
         if (down) {
             if (lev == 0) {
-                tail_coarse<T, NT>(TL, sm, Lc, n0);
+                if (!solved0) tail_coarse<T, NT>(TL, sm, Lc, n0);
+                solved0 = true;
                 down = false;
                 continue;
             }
             tail_smooth<T, NT>(TL, sm, lev, nu1, RG, regs);
             tail_restrict<T, NT>(TL, sm, lev, RG, regs);
             --lev;
+            if (lev == 0) solved0 = false;
             set(lev, mu);
         } else {
             // one cycle on level lev just finished
