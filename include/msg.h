@@ -131,8 +131,9 @@ typedef struct {
                                    remaining cycles run inside one kernel */
     int32_t overlap;            /* -1 = automatic (2 for 1024 samples or more, else 0);
                                    0 = every launch on `stream`; 1 = the cycles of the classes
-                                   of a level alternate over two streams forked from and
-                                   joined back to `stream`; 2 = the batch is split in parts
+                                   of a level alternate over side streams (four; environment
+                                   MSG_SIDE_STREAMS = 1..4) forked from and joined back to
+                                   `stream`; 2 = the batch is split in parts
                                    (three by default; environment MSG_PARTS = 2..4) solved
                                    concurrently by one host thread each, each part on one
                                    stream of its own.  Results do not depend on it; the

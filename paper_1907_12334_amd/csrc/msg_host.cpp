@@ -131,7 +131,8 @@ BatchLayout make_layout(const msg_batch_desc* b)
 }
 
 // ---------------------------------------------------------------- plans
-constexpr int kSideStreams = 2;   // W-cycles of sub-batches run on these, forked from the caller's stream
+constexpr int kSideStreams = 4;   // W-cycles of sub-batches run on these, forked from the caller's stream
+int g_side = 4;                   // side streams in use (at most kSideStreams; MSG_SIDE_STREAMS)
 int g_fuse = 2;              // smoother sweeps fused per pass (1 or 2)
 int g_rbgs_tw = 64;          // smoother tile: widest, most cells, LDS elements
 int g_rbgs_cells = 1024;
@@ -717,7 +718,7 @@ struct Lane {
             if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
             if (e == hipSuccess) e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
         }
-        for (int k = 0; with_side && k < kSideStreams && e == hipSuccess; ++k) {
+        for (int k = 0; with_side && k < g_side && e == hipSuccess; ++k) {
             if (side[k]) continue;
             e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
@@ -813,6 +814,7 @@ void read_env()
         if (const char* t = std::getenv("MSG_DEBUG_STAGES")) g_debug_stages = std::atoi(t) != 0;
         if (const char* t = std::getenv("MSG_HANDOFF")) g_handoff = std::max(0, std::atoi(t));
         if (const char* t = std::getenv("MSG_TAIL_REG")) g_tail_reg_levels = std::max(0, std::min(kTailRegLevels, std::atoi(t)));
+        if (const char* t = std::getenv("MSG_SIDE_STREAMS")) g_side = std::max(1, std::min(kSideStreams, std::atoi(t)));
         if (const char* t = std::getenv("MSG_RBGS_TW")) g_rbgs_tw = std::max(4, std::min(256, std::atoi(t)));
         if (const char* t = std::getenv("MSG_RBGS_CELLS")) g_rbgs_cells = std::max(64, std::min(4096, std::atoi(t)));
         if (const char* t = std::getenv("MSG_RBGS_LDS")) g_rbgs_lds = std::max(1024, std::min(kRbgsLdsMax, std::atoi(t)));
@@ -1541,7 +1543,7 @@ namespace {
 
 // One part of a batch (the whole batch, or one of the parts solved
 // concurrently) on stream s with lane ln; ov > 0 lets the classes of a level
-// alternate over the lane's two side streams.  Arguments are validated by
+// alternate over the lane's side streams.  Arguments are validated by
 // the caller; the part's arrays start at its first sample.
 msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batch, const msg_solve_opts* opts,
                       const double* d_kx, const double* d_ky, const float* d_kx32, const float* d_ky32,
@@ -1900,12 +1902,12 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                 }
                 if (fork) {
                     HIPCHK(hipEventRecord(ln.fork, s));
-                    for (int k = 0; k < kSideStreams; ++k) HIPCHK(hipStreamWaitEvent(ln.side[k], ln.fork, 0));
+                    for (int k = 0; k < g_side; ++k) HIPCHK(hipStreamWaitEvent(ln.side[k], ln.fork, 0));
                 }
                 for (size_t g = 0; g < groups.size(); ++g) {
                     const Group& G = groups[g];
                     Ctx Y = X;
-                    Y.s = ov > 0 ? ln.side[rr++ % kSideStreams] : s;
+                    Y.s = ov > 0 ? ln.side[rr++ % g_side] : s;
                     // the members' buffer states are equal: they have cycled together
                     // since the stage began
                     const int c0 = gci[g][0];
@@ -1931,7 +1933,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
             } else {
             if (fork) {
                 HIPCHK(hipEventRecord(ln.fork, s));
-                for (int k = 0; k < kSideStreams; ++k) HIPCHK(hipStreamWaitEvent(ln.side[k], ln.fork, 0));
+                for (int k = 0; k < g_side; ++k) HIPCHK(hipStreamWaitEvent(ln.side[k], ln.fork, 0));
             }
             int rr = 0;
             for (int ci = 0; ci < ncls; ++ci) {
@@ -1939,7 +1941,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                 if (host_active[ci] == 0) continue;        // every problem of this class has stopped
                 Ctx Y = X;
                 Y.kact = host_active[ci];
-                Y.s = ov > 0 ? ln.side[rr++ % kSideStreams] : (use_graphs ? ln.side[0] : s);
+                Y.s = ov > 0 ? ln.side[rr++ % g_side] : (use_graphs ? ln.side[0] : s);
                 const Span span{0, C.K};
                 // one W-cycle of the class (and its refinement update)
                 auto cycle = [&]() -> msg_status {
@@ -1987,7 +1989,7 @@ msg_status solve_part(msg_handle h, Lane& ln, int ov, const msg_batch_desc* batc
                 HIPCHK(hipGraphLaunch(G.exec, Y.s));
             }
             }
-            for (int k = 0; fork && k < kSideStreams; ++k) {
+            for (int k = 0; fork && k < g_side; ++k) {
                 HIPCHK(hipEventRecord(ln.join[k], ln.side[k]));
                 HIPCHK(hipStreamWaitEvent(s, ln.join[k], 0));
             }
