@@ -1141,7 +1141,7 @@ __device__ __forceinline__ void tail_smooth_regs(T* sm, SlotPtr tab, int total, 
                     // FP64, several slots per lane: the entry passes through an
                     // empty asm statement so that the cell addresses are formed
                     // again at each half-sweep rather than held for all R slots
-                    // (108 instead of 161 registers: more room for the smoother's
+                    // (about 50 registers fewer: more room for the smoother's
                     // wavefronts beside the tail; FP32 tails measured faster
                     // with the addresses held)
                     int ex = e[r].x, ey = e[r].y, ez = e[r].z, ew = e[r].w;
